@@ -1,0 +1,144 @@
+"""ctypes binding of libfdbscan (include/fdbscan.h): argument marshalling only.
+
+Every step of the clustering runs in the library's HIP kernels; PyTorch only
+provides device memory and the stream. The library is loaded from this
+directory; if it has not been built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdbscan.so")
+
+FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE = range(5)
+FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX = 0, 1
+FDB_BORDER_CANONICAL, FDB_BORDER_FIRST = 0, 1
+FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE = 1, 2
+
+ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX}
+BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST}
+
+
+class FdbOptions(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("border", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FdbError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libfdbscan.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: build it with __graft_entry__.build() "
+                           "or python paper_2103_05162_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.fdb_status_string.argtypes = [ctypes.c_int]
+    lib.fdb_status_string.restype = ctypes.c_char_p
+    lib.fdb_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+    lib.fdb_create.restype = ctypes.c_int
+    lib.fdb_destroy.argtypes = [vp]
+    lib.fdb_destroy.restype = None
+    lib.fdb_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(FdbOptions), ctypes.POINTER(sz)]
+    lib.fdb_workspace_bytes.restype = ctypes.c_int
+    lib.fdb_dbscan.argtypes = [vp, vp, i64, i32, ctypes.c_float, i32, ctypes.POINTER(FdbOptions), vp, vp,
+                               ctypes.POINTER(i32), vp, sz, vp]
+    lib.fdb_dbscan.restype = ctypes.c_int
+    lib.fdb_last_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+    lib.fdb_last_info.restype = ctypes.c_int
+    lib.fdb_set_timing.argtypes = [vp, i32]
+    lib.fdb_set_timing.restype = ctypes.c_int
+    lib.fdb_stage_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.fdb_stage_times.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().fdb_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str) -> None:
+    if status != FDB_OK:
+        raise FdbError(status, what)
+
+
+def make_options(algo="fdbscan", border="canonical", leaf_size=0, block_size=0, flags=0) -> FdbOptions:
+    a = ALGOS[algo] if isinstance(algo, str) else int(algo)
+    b = BORDERS[border] if isinstance(border, str) else int(border)
+    return FdbOptions(a, b, int(leaf_size), int(block_size), int(flags))
+
+
+def workspace_bytes(n: int, dim: int, algo="fdbscan") -> int:
+    out = ctypes.c_size_t(0)
+    opt = make_options(algo)
+    _check(load().fdb_workspace_bytes(int(n), int(dim), ctypes.byref(opt), ctypes.byref(out)), "fdb_workspace_bytes")
+    return int(out.value)
+
+
+class Handle:
+    """An fdb_handle bound to one HIP device (owns a cached workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.fdb_create(ctypes.byref(h), int(device)), "fdb_create")
+        self.ptr = h
+        self.device = int(device)
+
+    def close(self) -> None:
+        if getattr(self, "ptr", None):
+            self._lib.fdb_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dbscan_raw(self, points_ptr: int, n: int, dim: int, eps: float, min_pts: int, labels_ptr: int,
+                   core_ptr: int | None, stream: int, options: FdbOptions | None = None, want_k: bool = True,
+                   workspace_ptr: int | None = None, workspace_size: int = 0):
+        """fdb_dbscan on raw device pointers. Returns K (or None when want_k is False)."""
+        k = ctypes.c_int32(-1)
+        st = self._lib.fdb_dbscan(self.ptr, ctypes.c_void_p(points_ptr), int(n), int(dim), ctypes.c_float(eps),
+                                  int(min_pts), ctypes.byref(options) if options is not None else None,
+                                  ctypes.c_void_p(labels_ptr), ctypes.c_void_p(core_ptr) if core_ptr else None,
+                                  ctypes.byref(k) if want_k else None,
+                                  ctypes.c_void_p(workspace_ptr) if workspace_ptr else None, int(workspace_size),
+                                  ctypes.c_void_p(stream))
+        _check(st, "fdb_dbscan")
+        return int(k.value) if want_k else None
+
+    def last_info(self) -> int:
+        v = ctypes.c_uint32(0)
+        _check(self._lib.fdb_last_info(self.ptr, ctypes.byref(v)), "fdb_last_info")
+        return int(v.value)
+
+    def set_timing(self, enable: bool) -> None:
+        _check(self._lib.fdb_set_timing(self.ptr, 1 if enable else 0), "fdb_set_timing")
+
+    def stage_times(self):
+        """(dict stage -> total ms, number of timed calls)."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int32(0)
+        calls = ctypes.c_int32(0)
+        _check(self._lib.fdb_stage_times(self.ptr, cap, names, ms, ctypes.byref(cnt), ctypes.byref(calls)),
+               "fdb_stage_times")
+        return {names[i].decode(): ms[i] for i in range(min(cnt.value, cap))}, int(calls.value)

@@ -1,0 +1,511 @@
+// C ABI of libfdbscan and the launch sequence of one clustering call.
+//
+// FDbscan (Section 4.1): bounds -> Morton keys -> radix sort -> gather to SoA ->
+// LBVH (Karras hierarchy, ropes, refit) -> core pass if minPts > 2 (early exit
+// at minPts) -> fused masked traversal with union-find -> finalisation ->
+// canonical ids (and the border pass) -> scatter to input order.
+// FDbscan-DenseBox (Section 4.2): bounds (read back once to size the grid) ->
+// grid-cell keys -> radix sort -> gather -> dense cells + mixed primitives ->
+// LBVH over the primitives -> core pass over points outside dense cells ->
+// fused traversal -> the same tail.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fdb_internal.hpp"
+#include "fdbscan.h"
+
+namespace fdb {
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+Plan make_plan(int64_t n, int dim, int algo) {
+  Plan p;
+  p.n = n;
+  p.dim = dim;
+  p.algo = algo;
+  const size_t N = static_cast<size_t>(n > 0 ? n : 1);
+  p.sort_tiles = ceil_div(static_cast<int64_t>(N), kSortTile);
+  p.scan_blocks = ceil_div(static_cast<int64_t>(N), kScanTile);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  p.bounds = take(8 * sizeof(uint32_t));
+  p.misc = take(kMiscCount * sizeof(int));
+  p.keys0 = take(N * 8);
+  p.keys1 = take(N * 8);
+  p.vals0 = take(N * 4);
+  p.vals1 = take(N * 4);
+  p.hist = take(8 * 256 * 4);
+  p.digoff = take(8 * 256 * 4);
+  p.tilectr = take(64);
+  p.status = take(static_cast<size_t>(p.sort_tiles) * 256 * 8);
+  p.xs = take(static_cast<size_t>(dim) * N * 4);
+  p.node_a = take(N * 16);
+  p.node_b = take(N * 16);
+  p.rope = take(N * 4);
+  p.leaf_rope = take(N * 4);
+  p.parent = take(2 * N * 4);
+  p.flags = take(N * 4);
+  p.other = take(N * 4);
+  p.gamma = take(N * 4);
+  p.labels = take(N * 4);
+  p.core = take(N);
+  p.minorig = take(N * 4);
+  p.lflag = take(N * 4);
+  p.rank = take(N * 4);
+  p.bsums = take(static_cast<size_t>(p.scan_blocks + 1) * 4);
+  p.cid = take(N * 4);
+  p.border = take(N * 4);
+  p.cell_id = p.cell_start = p.cand = p.cell_dense = p.cell_lo = p.cell_hi = 0;
+  p.pflag = p.prim_of = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = 0;
+  if (algo == FDB_ALGO_DENSEBOX) {
+    p.cell_id = take(N * 4);
+    p.cell_start = take((N + 1) * 4);
+    p.cand = take(N * 4);
+    p.cell_dense = take(N);
+    p.cell_lo = take(N * 16);
+    p.cell_hi = take(N * 16);
+    p.pflag = take(N * 4);
+    p.prim_of = take(N * 4);
+    p.prim_start = take(N * 4);
+    p.prim_cnt = take(N * 4);
+    p.prim_lo = take(N * 16);
+    p.prim_hi = take(N * 16);
+    p.prim_key = take(N * 8);
+  }
+  p.bytes = off;
+  return p;
+}
+
+struct StageRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace fdb
+
+struct fdb_handle {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* d_info = nullptr;
+  uint32_t* h_pinned = nullptr;  // 16 words of pinned host memory for read-backs
+  uint32_t host_info = 0;
+  hipStream_t last_stream = nullptr;
+  bool timing = false;
+  int32_t timed_calls = 0;
+  std::vector<fdb::StageRec> pending;  // event pairs of the calls since the last collection
+  std::vector<std::string> names;      // accumulated stage names (static strings)
+  std::vector<double> ms;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+using fdb::ceil_div;
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+hipEvent_t take_event(fdb_handle* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Marks the start of a named stage; the previous stage (if any) ends there.
+struct Stager {
+  fdb_handle* h;
+  hipStream_t s;
+  const char* cur = nullptr;
+  hipEvent_t cur_a = nullptr;
+  Stager(fdb_handle* hh, hipStream_t ss) : h(hh), s(ss) {}
+  void mark(const char* name) {
+    if (!h->timing) return;
+    hipEvent_t e = take_event(h);
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    if (cur) {
+      hipEvent_t e2 = take_event(h);
+      if (e2) {
+        (void)hipEventRecord(e2, s);
+        h->pending.push_back({cur, cur_a, e2});
+      }
+    }
+    cur = name;
+    cur_a = e;
+  }
+  void finish() {
+    if (!h->timing || !cur) return;
+    hipEvent_t e2 = take_event(h);
+    if (e2) {
+      (void)hipEventRecord(e2, s);
+      h->pending.push_back({cur, cur_a, e2});
+    }
+    cur = nullptr;
+  }
+};
+
+fdb_status collect_timing(fdb_handle* h) {
+  for (auto& r : h->pending) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return FDB_ERR_HIP;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return FDB_ERR_HIP;
+    size_t k = 0;
+    while (k < h->names.size() && h->names[k] != r.name) ++k;
+    if (k == h->names.size()) {
+      h->names.emplace_back(r.name);
+      h->ms.push_back(0.0);
+    }
+    h->ms[k] += t;
+    h->event_pool.push_back(r.a);
+    h->event_pool.push_back(r.b);
+  }
+  h->pending.clear();
+  return FDB_OK;
+}
+
+bool valid_options(const fdb_options& o) {
+  if (o.algo != FDB_ALGO_FDBSCAN && o.algo != FDB_ALGO_DENSEBOX) return false;
+  if (o.border != FDB_BORDER_CANONICAL && o.border != FDB_BORDER_FIRST) return false;
+  if (o.leaf_size < 0 || o.leaf_size > 1024) return false;
+  if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64 != 0)) return false;
+  if (o.flags != 0) return false;
+  return true;
+}
+
+constexpr int kDefaultLeaf = 4;
+constexpr int kDefaultBlock = 256;
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdb_status_string(fdb_status s) {
+  switch (s) {
+    case FDB_OK: return "ok";
+    case FDB_ERR_INVALID: return "invalid argument";
+    case FDB_ERR_NOMEM: return "workspace too small or allocation failed";
+    case FDB_ERR_HIP: return "HIP runtime error";
+    case FDB_ERR_NONFINITE: return "non-finite coordinate";
+    case FDB_ERR_INTERNAL: return "internal consistency check failed";
+  }
+  return "unknown status";
+}
+
+fdb_status fdb_create(fdb_handle** out, int device) {
+  if (!out) return FDB_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return FDB_ERR_HIP;
+  if (device < 0 || device >= count) return FDB_ERR_INVALID;
+  fdb_handle* h = new (std::nothrow) fdb_handle();
+  if (!h) return FDB_ERR_NOMEM;
+  h->device = device;
+  DeviceGuard g(device);
+  if (hipMalloc(&h->d_info, 256) != hipSuccess) {
+    delete h;
+    return FDB_ERR_NOMEM;
+  }
+  if (hipHostMalloc(&h->h_pinned, 16 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(h->d_info);
+    delete h;
+    return FDB_ERR_NOMEM;
+  }
+  *out = h;
+  return FDB_OK;
+}
+
+void fdb_destroy(fdb_handle* h) {
+  if (!h) return;
+  DeviceGuard g(h->device);
+  (void)hipDeviceSynchronize();
+  for (auto& r : h->pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->d_info) (void)hipFree(h->d_info);
+  if (h->h_pinned) (void)hipHostFree(h->h_pinned);
+  delete h;
+}
+
+fdb_status fdb_workspace_bytes(int64_t n, int32_t dim, const fdb_options* opt, size_t* h_out) {
+  if (!h_out) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o) || (dim != 2 && dim != 3) || n < 0 || n > fdb::kMaxPoints) return FDB_ERR_INVALID;
+  *h_out = fdb::make_plan(n, dim, o.algo).bytes;
+  return FDB_OK;
+}
+
+fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info) {
+  if (!h || !h_info) return FDB_ERR_INVALID;
+  DeviceGuard g(h->device);
+  if (hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, h->last_stream) != hipSuccess)
+    return FDB_ERR_HIP;
+  if (hipStreamSynchronize(h->last_stream) != hipSuccess) return FDB_ERR_HIP;
+  *h_info = h->h_pinned[8] | h->host_info;
+  return FDB_OK;
+}
+
+fdb_status fdb_set_timing(fdb_handle* h, int32_t enable) {
+  if (!h) return FDB_ERR_INVALID;
+  DeviceGuard g(h->device);
+  fdb_status st = collect_timing(h);
+  h->names.clear();
+  h->ms.clear();
+  h->timed_calls = 0;
+  h->timing = enable != 0;
+  return st;
+}
+
+fdb_status fdb_stage_times(fdb_handle* h, int32_t max, const char** h_names, double* h_ms, int32_t* h_count,
+                           int32_t* h_calls) {
+  if (!h || max < 0 || !h_count) return FDB_ERR_INVALID;
+  DeviceGuard g(h->device);
+  fdb_status st = collect_timing(h);
+  if (st != FDB_OK) return st;
+  int32_t k = static_cast<int32_t>(h->names.size());
+  *h_count = k;
+  for (int32_t i = 0; i < k && i < max; ++i) {
+    if (h_names) h_names[i] = h->names[i].c_str();
+    if (h_ms) h_ms[i] = h->ms[i];
+  }
+  if (h_calls) *h_calls = h->timed_calls;
+  return FDB_OK;
+}
+
+fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                      const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
+                      void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace fdb;
+  if (!h) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o)) return FDB_ERR_INVALID;
+  if (dim != 2 && dim != 3) return FDB_ERR_INVALID;
+  if (n < 0 || n > kMaxPoints) return FDB_ERR_INVALID;
+  if (!std::isfinite(eps) || !(eps > 0.0f) || min_pts < 1) return FDB_ERR_INVALID;
+  if (n > 0 && (!points || !labels)) return FDB_ERR_INVALID;
+  DeviceGuard guard(h->device);
+  h->last_stream = stream;
+  h->host_info = 0;
+  if (n == 0) {
+    if (h_num_clusters) *h_num_clusters = 0;
+    return FDB_OK;
+  }
+  const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
+  const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
+  bool densebox = o.algo == FDB_ALGO_DENSEBOX;
+  const bool first_border = o.border == FDB_BORDER_FIRST;
+  const Plan plan = make_plan(n, dim, o.algo);
+  void* ws = workspace;
+  if (ws) {
+    if (workspace_bytes < plan.bytes) return FDB_ERR_NOMEM;
+  } else {
+    if (h->ws_bytes < plan.bytes) {
+      if (h->ws) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+      }
+      if (hipMalloc(&h->ws, plan.bytes) != hipSuccess) return FDB_ERR_NOMEM;
+      h->ws_bytes = plan.bytes;
+    }
+    ws = h->ws;
+  }
+  (void)hipGetLastError();
+  const float eps2 = eps * eps;
+  hipStream_t s = stream;
+  Stager st(h, s);
+  if (h->timing) ++h->timed_calls;
+
+  uint32_t* bounds = at<uint32_t>(ws, plan.bounds);
+  int* misc = at<int>(ws, plan.misc);
+  void* keys[2] = {at<void>(ws, plan.keys0), at<void>(ws, plan.keys1)};
+  uint32_t* vals[2] = {at<uint32_t>(ws, plan.vals0), at<uint32_t>(ws, plan.vals1)};
+  float* xs = at<float>(ws, plan.xs);
+  int* lab = at<int>(ws, plan.labels);
+  uint8_t* core = at<uint8_t>(ws, plan.core);
+
+  st.mark("bounds");
+  fill_u32(h->d_info, 0, 1, s);
+  fill_u32(bounds, 0xffffffffu, 4, s);
+  fill_u32(bounds + 4, 0u, 4, s);
+  launch_bounds(points, n, dim, bounds, h->d_info, s);
+
+  GridParams gp{};
+  if (densebox) {
+    // The grid is sized on the host from the bounds: one read-back.
+    if (hipMemcpyAsync(h->h_pinned, bounds, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FDB_ERR_HIP;
+    if (h->h_pinned[8] & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
+    auto dec = [](uint32_t u) {
+      uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+      float f;
+      std::memcpy(&f, &b, 4);
+      return f;
+    };
+    // cell side h = eps/sqrt(d), shrunk by 2^-20 so rounding in the cell index
+    // rarely pushes a cell's extent past h (the guard catches the rest)
+    const double side = static_cast<double>(eps) / std::sqrt(static_cast<double>(dim)) * (1.0 - 1.0 / 1048576.0);
+    int bits = 0;
+    bool ok = side > 0.0 && std::isfinite(side);
+    for (int k = 0; k < dim && ok; ++k) {
+      double ext = static_cast<double>(dec(h->h_pinned[4 + k])) - static_cast<double>(dec(h->h_pinned[k]));
+      double cells = std::floor(ext / side) + 1.0;
+      if (!(cells < 2147483648.0)) {
+        ok = false;
+        break;
+      }
+      gp.ncell[k] = static_cast<uint32_t>(cells);
+      gp.inv_h[k] = static_cast<float>(1.0 / side);
+      int b = 0;
+      while ((uint64_t(1) << b) < gp.ncell[k]) ++b;
+      bits = b > bits ? b : bits;
+    }
+    const int maxbits = dim == 3 ? 21 : 32;
+    if (!ok || bits > maxbits) {
+      densebox = false;
+      h->host_info |= FDB_INFO_DENSEBOX_FALLBACK;
+    } else {
+      gp.bits = bits;
+      gp.key64 = bits * dim > 32;
+    }
+  }
+
+  int cur = 0;
+  const uint32_t* perm = nullptr;
+  TravArgs ta{};
+  ta.xs = xs;
+  ta.n = n;
+  ta.eps2 = eps2;
+  ta.min_pts = min_pts;
+  ta.labels = lab;
+  ta.core = core;
+  ta.cid = at<int>(ws, plan.cid);
+  ta.border = at<int>(ws, plan.border);
+  ta.block = block;
+  ta.info = h->d_info;
+  ta.t.node_a = at<float4>(ws, plan.node_a);
+  ta.t.node_b = at<float4>(ws, plan.node_b);
+  ta.t.rope = at<int>(ws, plan.rope);
+  ta.t.leaf_rope = at<int>(ws, plan.leaf_rope);
+  ta.t.leaf_size = leaf;
+
+  if (densebox) {
+    st.mark("cell_keys");
+    launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], s);
+    st.mark("sort");
+    cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, gp.key64, gp.bits * dim, at<uint32_t>(ws, plan.hist),
+                     at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
+    perm = vals[cur];
+    st.mark("permute");
+    launch_permute(points, n, dim, perm, xs, h->d_info, s);
+    st.mark("dense_cells");
+    fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
+    densebox_cells(keys[cur], gp.key64, n, dim, xs, eps2, min_pts, at<int>(ws, plan.cell_id),
+                   at<int>(ws, plan.cell_start), at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense),
+                   at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
+                   at<int>(ws, plan.prim_of), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
+                   at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key), lab, core,
+                   misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
+    st.mark("lbvh");
+    build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
+               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
+               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
+    ta.t.m_cap = static_cast<int>(n);
+    ta.t.d_m = misc + kMiscNumPrims;
+    ta.prim_of = at<int>(ws, plan.prim_of);
+    ta.prim_start = at<int>(ws, plan.prim_start);
+    ta.prim_cnt = at<int>(ws, plan.prim_cnt);
+    ta.prim_lo = at<float4>(ws, plan.prim_lo);
+    ta.prim_hi = at<float4>(ws, plan.prim_hi);
+  } else {
+    st.mark("morton");
+    launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], s);
+    st.mark("sort");
+    cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, dim == 3 ? 63 : 62, at<uint32_t>(ws, plan.hist),
+                     at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
+    perm = vals[cur];
+    st.mark("permute");
+    launch_permute(points, n, dim, perm, xs, h->d_info, s);
+    launch_init_labels(lab, n, s);
+    st.mark("lbvh");
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
+               at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
+               at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
+               nullptr, h->d_info, s);
+    ta.t.m_cap = static_cast<int>(n);
+    ta.t.d_m = nullptr;
+  }
+
+  const bool all_core = min_pts <= 2;
+  if (!all_core) {
+    st.mark("core");
+    launch_core(ta, dim, densebox, s);
+  }
+  st.mark("main");
+  launch_main(ta, dim, densebox, all_core, first_border && !all_core, s);
+  st.mark("finalize");
+  launch_finalize(lab, n, h->d_info, s);
+  if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);
+  st.mark("cluster_ids");
+  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<int>(ws, plan.lflag), at<int>(ws, plan.rank),
+                at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s);
+  const bool have_border = !all_core && !first_border;
+  if (have_border) {
+    st.mark("border");
+    launch_border(ta, dim, densebox, s);
+  }
+  st.mark("scatter");
+  launch_scatter(lab, core, perm, at<int>(ws, plan.cid), at<int>(ws, plan.border), first_border && !all_core,
+                 have_border, n, labels, is_core, h->d_info, s);
+  st.finish();
+  if (hipGetLastError() != hipSuccess) return FDB_ERR_HIP;
+  if (h_num_clusters) {
+    if (hipMemcpyAsync(h->h_pinned, misc + kMiscNumClusters, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FDB_ERR_HIP;
+    *h_num_clusters = static_cast<int32_t>(h->h_pinned[0]);
+    if (h->h_pinned[8] & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
+    if (h->h_pinned[8] & FDB_INFO_INTERNAL) return FDB_ERR_INTERNAL;
+  }
+  return FDB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Host-side internals of libfdbscan: the workspace plan, the device views the
+// kernels receive, and the launch helpers each kernel file exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fdb {
+
+constexpr int kSortItems = 16;                 // keys per thread in a radix pass
+constexpr int kSortTile = 256 * kSortItems;    // keys per workgroup tile
+constexpr int kScanItems = 16;                 // items per thread in the device scan
+constexpr int kScanTile = 256 * kScanItems;
+constexpr int64_t kMaxPoints = (int64_t(1) << 30) - 1;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Byte offsets of every buffer inside the caller's (or the handle's) workspace.
+// Sizes depend on (n, dim, algo) only, never on eps or minPts: the footprint is
+// linear in n (Section 3.2).
+struct Plan {
+  int64_t n = 0;
+  int dim = 3;
+  int algo = 0;
+  size_t bytes = 0;
+  // common
+  size_t bounds, misc, keys0, keys1, vals0, vals1, hist, digoff, tilectr, status;
+  size_t xs;                       // dim * n floats, sorted SoA
+  size_t node_a, node_b, rope, leaf_rope, parent, flags, other, gamma;
+  size_t labels, core;
+  size_t minorig, lflag, rank, bsums, cid, border;
+  // DenseBox
+  size_t cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt,
+      prim_lo, prim_hi, prim_key;
+  int64_t sort_tiles = 0, scan_blocks = 0;
+};
+
+Plan make_plan(int64_t n, int dim, int algo);
+
+// Small device-side scalars kept in the workspace's misc block.
+enum MiscSlot : int {
+  kMiscNumClusters = 0,  // K after the scan
+  kMiscNumCells = 1,     // DenseBox: number of non-empty cells
+  kMiscNumCand = 2,      // DenseBox: cells with >= minPts points
+  kMiscNumPrims = 3,     // DenseBox: m = dense cells + points outside them
+  kMiscCount = 16
+};
+
+// Device view of an LBVH over m primitives. Internal node k: node_a[k] =
+// (lo.xyz, other end of its leaf range as int bits), node_b[k] = (hi.xyz, split
+// position gamma as int bits); its leaves are [min(k,other), max(k,other)], its
+// children cover [first,gamma] and [gamma+1,last]. rope[k] / leaf_rope[l] give
+// the next node in depth-first pre-order after that subtree (kEnd at the end).
+struct TreeView {
+  const float4* node_a;
+  const float4* node_b;
+  const int* rope;
+  const int* leaf_rope;
+  int m_cap;       // number of primitives, or an upper bound when d_m is set
+  const int* d_m;  // device-side primitive count (DenseBox), or null
+  int leaf_size;   // subtrees of at most this many primitives are scanned linearly
+};
+
+// ---- launch helpers (stream-ordered, asynchronous) --------------------------
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+
+// k_prep.hip
+void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint32_t* info, hipStream_t s);
+void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds, uint64_t* keys, uint32_t* vals,
+                   hipStream_t s);
+void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const float* inv_h3,
+                     const uint32_t* ncell3, int bits, bool key64, void* keys, uint32_t* vals, hipStream_t s);
+void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,
+                    hipStream_t s);
+
+// k_sort.hip: LSD radix sort of (key, index) pairs over the low `bits` bits.
+// Returns which of the two buffers holds the result (0 or 1).
+int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
+               uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info,
+               hipStream_t s);
+
+// k_tree.hip
+void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
+                const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
+                int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m, uint32_t* info,
+                hipStream_t s);
+
+// k_dense.hip
+struct GridParams {
+  float inv_h[3];
+  uint32_t ncell[3];
+  int bits;
+  bool key64;
+};
+void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2,
+                    int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo,
+                    float4* cell_hi, int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo,
+                    float4* prim_hi, void* prim_key, int* labels, uint8_t* core, int* misc, int* bsums,
+                    int64_t scan_blocks, hipStream_t s);
+
+// k_trav.hip
+struct TravArgs {
+  TreeView t;
+  const float* xs;  // sorted SoA coordinates: x[n], y[n], z[n]
+  int64_t n;
+  float eps2;
+  int min_pts;
+  int* labels;
+  uint8_t* core;
+  const int* cid;
+  int* border;
+  // DenseBox primitives (null for FDbscan)
+  const int* prim_of;
+  const int* prim_start;
+  const int* prim_cnt;  // > 0: a single point; < 0: -(count) points of a dense cell
+  const float4* prim_lo;
+  const float4* prim_hi;
+  uint32_t* info;  // FDB_INFO_* bits; kernels raise FDB_INFO_INTERNAL on a broken walk
+  int block;
+};
+void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
+void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, hipStream_t s);
+void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);
+
+// k_label.hip
+void launch_init_labels(int* labels, int64_t n, hipStream_t s);
+void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s);
+void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
+void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
+                   int* lflag, int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s);
+void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid,
+                    const int* border, bool first_border, bool have_border, int64_t n, int32_t* out_labels,
+                    uint8_t* out_core, uint32_t* info, hipStream_t s);
+void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums, int64_t blocks, int* d_total,
+                 hipStream_t s);
+
+}  // namespace fdb

@@ -1,0 +1,203 @@
+// FDbscan-DenseBox preprocessing (Section 4.2). Points arrive sorted by grid-cell
+// key (cells of side eps/sqrt(d), keyed along a Morton curve), so each cell is a
+// contiguous run. A cell is dense when it holds at least minPts points; then all
+// its points are core and share one cluster. The BVH is built over a mix of
+// dense-cell boxes and the points outside dense cells, in key order, so the one
+// sort serves both the grid and the tree.
+//
+// Exactness guard (the paper asks for one, Section 4.2): a cell counts as dense
+// only if the neighbour test holds across its tight bounding box's diagonal,
+// evaluated with the same fp32 operations. Rounded subtraction is monotone, so
+// then every pair of points in the cell passes the test, whatever rounding the
+// cell index computation suffered.
+#include "fdb_device.hpp"
+#include "fdb_internal.hpp"
+
+namespace fdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_cell_heads(const K* __restrict__ keys, int64_t n, int* __restrict__ head) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+// cell_id[i] = (number of heads at or before i) - 1; heads record their start.
+__global__ __launch_bounds__(kBlock) void k_cell_start(const int* __restrict__ head, int64_t n,
+                                                       int* __restrict__ cell_id, int* __restrict__ cell_start,
+                                                       const int* __restrict__ num_cells) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    int h = head[i];
+    int c = cell_id[i] + h - 1;  // cell_id holds the exclusive scan of head on entry
+    cell_id[i] = c;
+    if (h) cell_start[c] = static_cast<int>(i);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[*num_cells] = static_cast<int>(n);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_candidates(const int* __restrict__ cell_start,
+                                                            const int* __restrict__ num_cells, int min_pts,
+                                                            int* __restrict__ cand, int* __restrict__ num_cand,
+                                                            uint8_t* __restrict__ dense) {
+  const int nc = *num_cells;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
+    int cnt = cell_start[c + 1] - cell_start[c];
+    dense[c] = 0;
+    if (cnt >= min_pts) cand[atomicAdd(num_cand, 1)] = c;
+  }
+}
+
+// One wavefront per candidate cell: tight box by a wave reduction, then the guard.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__ xs, int64_t n,
+                                                       const int* __restrict__ cell_start, const int* __restrict__ cand,
+                                                       const int* __restrict__ num_cand, float eps2,
+                                                       uint8_t* __restrict__ dense, float4* __restrict__ cell_lo,
+                                                       float4* __restrict__ cell_hi) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kBlock) >> 6;
+  const int ncand = *num_cand;
+  for (int w = wave; w < ncand; w += nwaves) {
+    const int c = cand[w];
+    const int s = cell_start[c], e = cell_start[c + 1];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = s + lane; j < e; j += 64) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        float v = xs[k * n + j];
+        lo[k] = fminf(lo[k], v);
+        hi[k] = fmaxf(hi[k], v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+      }
+    if (lane == 0) {
+      if (D == 2) lo[2] = hi[2] = 0.0f;
+      bool ok = dist2v<D>(hi[0], hi[1], hi[2], lo[0], lo[1], lo[2]) <= eps2;
+      dense[c] = ok ? 1 : 0;
+      cell_lo[c] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+      cell_hi[c] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prim_flags(const int* __restrict__ cell_id,
+                                                       const int* __restrict__ cell_start,
+                                                       const uint8_t* __restrict__ dense, int64_t n,
+                                                       int* __restrict__ pflag) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    int c = cell_id[i];
+    pflag[i] = (!dense[c] || cell_start[c] == i) ? 1 : 0;
+  }
+}
+
+// pidx holds the exclusive scan of pflag: the primitive index of every point
+// that opens a primitive (a point outside dense cells, or a dense cell's first).
+template <int D, typename K>
+__global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, const float* __restrict__ xs, int64_t n,
+                                                  const int* __restrict__ cell_id, const int* __restrict__ cell_start,
+                                                  const uint8_t* __restrict__ dense, const float4* __restrict__ cell_lo,
+                                                  const float4* __restrict__ cell_hi, const int* __restrict__ pidx,
+                                                  int* __restrict__ prim_of, int* __restrict__ prim_start,
+                                                  int* __restrict__ prim_cnt, float4* __restrict__ prim_lo,
+                                                  float4* __restrict__ prim_hi, K* __restrict__ prim_key,
+                                                  int* __restrict__ labels, uint8_t* __restrict__ core) {
+  for (int64_t i64 = blockIdx.x * int64_t(kBlock) + threadIdx.x; i64 < n; i64 += int64_t(gridDim.x) * kBlock) {
+    const int i = static_cast<int>(i64);
+    const int c = cell_id[i];
+    const int s = cell_start[c];
+    if (dense[c]) {
+      const int p = pidx[s];
+      prim_of[i] = p;
+      labels[i] = s;
+      core[i] = 1;
+      if (i == s) {
+        prim_start[p] = s;
+        prim_cnt[p] = -(cell_start[c + 1] - s);
+        prim_lo[p] = cell_lo[c];
+        prim_hi[p] = cell_hi[c];
+        prim_key[p] = keys[i];
+      }
+    } else {
+      const int p = pidx[i];
+      prim_of[i] = p;
+      labels[i] = i;
+      core[i] = 0;
+      prim_start[p] = i;
+      prim_cnt[p] = 1;
+      float x = xs[i], y = xs[n + i], z = D == 3 ? xs[2 * n + i] : 0.0f;
+      prim_lo[p] = make_float4(x, y, z, 0.0f);
+      prim_hi[p] = make_float4(x, y, z, 0.0f);
+      prim_key[p] = keys[i];
+    }
+  }
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = ceil_div(n, kBlock * 4);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
+template <typename K>
+void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
+             int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag, int* prim_of,
+             int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* labels,
+             uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, hipStream_t s) {
+  int* d_cells = misc + kMiscNumCells;
+  int* d_cand = misc + kMiscNumCand;
+  int* d_prims = misc + kMiscNumPrims;
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_cell_heads<K>, dim3(g), dim3(kBlock), 0, s, keys, n, pflag);
+  device_scan(pflag, cell_id, n, nullptr, bsums, scan_blocks, d_cells, s);
+  hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(kBlock), 0, s, pflag, n, cell_id, cell_start, d_cells);
+  fill_u32(reinterpret_cast<uint32_t*>(d_cand), 0, 1, s);
+  hipLaunchKernelGGL(k_cell_candidates, dim3(g), dim3(kBlock), 0, s, cell_start, d_cells, min_pts, cand, d_cand,
+                     dense);
+  const int gb = 2048;  // 8192 wavefronts, grid-stride over candidate cells
+  if (dim == 3)
+    hipLaunchKernelGGL(k_cell_boxes<3>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, dense,
+                       cell_lo, cell_hi);
+  else
+    hipLaunchKernelGGL(k_cell_boxes<2>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, dense,
+                       cell_lo, cell_hi);
+  hipLaunchKernelGGL(k_prim_flags, dim3(g), dim3(kBlock), 0, s, cell_id, cell_start, dense, n, pflag);
+  int* pidx = cand;  // candidates are no longer needed; reuse for primitive indices
+  device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_prims<3, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, labels,
+                       core);
+  else
+    hipLaunchKernelGGL((k_prims<2, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, labels,
+                       core);
+}
+
+}  // namespace
+
+void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2, int min_pts,
+                    int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo, float4* cell_hi,
+                    int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
+                    void* prim_key, int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks,
+                    hipStream_t s) {
+  if (key64)
+    cells_t(static_cast<const uint64_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
+            cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
+            static_cast<uint64_t*>(prim_key), labels, core, misc, bsums, scan_blocks, s);
+  else
+    cells_t(static_cast<const uint32_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
+            cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
+            static_cast<uint32_t*>(prim_key), labels, core, misc, bsums, scan_blocks, s);
+}
+
+}  // namespace fdb

@@ -1,0 +1,246 @@
+// Finalisation (Section 4.3: point every label straight at its representative)
+// and the output encoding, which the paper leaves open: canonical cluster ids
+// 0..K-1 in increasing order of the smallest input index among each cluster's
+// core points, -1 for noise, scattered back to input order. Also the device-wide
+// exclusive scan used here and by DenseBox.
+#include "fdb_device.hpp"
+#include "fdb_internal.hpp"
+
+namespace fdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t n) {
+  int64_t g = ceil_div(n, kBlock * 4);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int* __restrict__ labels, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    labels[i] = static_cast<int>(i);
+}
+
+// No unions run now, so roots are fixed; a stale read is an ancestor and the
+// walk still ends at the root.
+__global__ __launch_bounds__(kBlock) void k_finalize(int* labels, int64_t n, uint32_t* __restrict__ info) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    int r = labels[i];
+    for (int64_t it = 0;; ++it) {
+      if (r < 0 || r >= n || it > n) {
+        atomicOr(info, kInternalBit);
+        r = static_cast<int>(i);
+        break;
+      }
+      int p = labels[r];
+      if (p == r) break;
+      r = p;
+    }
+    labels[i] = r;
+  }
+}
+
+// minPts <= 2 skips the core pass (Algorithm 3). Then every pair within eps is
+// a core pair: with minPts = 2 a point is core iff its set has another member,
+// with minPts = 1 every point is core.
+__global__ __launch_bounds__(kBlock) void k_core_from_sets(const int* __restrict__ labels,
+                                                           uint8_t* __restrict__ core, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    int r = labels[i];
+    if (r != i) {
+      core[i] = 1;
+      core[r] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_minorig(const int* __restrict__ labels, const uint8_t* __restrict__ core,
+                                                    const uint32_t* __restrict__ perm, int64_t n,
+                                                    int* __restrict__ minorig) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    if (core[i]) atomicMin(minorig + labels[i], static_cast<int>(perm[i]));
+}
+
+// lflag[o] = 1 iff input index o is the smallest input index among the core
+// points of its cluster; its exclusive scan in input order is the cluster id.
+__global__ __launch_bounds__(kBlock) void k_leaders(const int* __restrict__ labels, const uint8_t* __restrict__ core,
+                                                    const uint32_t* __restrict__ perm, const int* __restrict__ minorig,
+                                                    int64_t n, int* __restrict__ lflag) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    int o = static_cast<int>(perm[i]);
+    lflag[o] = (core[i] && minorig[labels[i]] == o) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cluster_ids(const int* __restrict__ labels,
+                                                        const uint8_t* __restrict__ core,
+                                                        const int* __restrict__ minorig, const int* __restrict__ rank,
+                                                        int64_t n, int* __restrict__ cid) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    if (core[i] && labels[i] == i) cid[i] = rank[minorig[i]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ labels, const uint8_t* __restrict__ core,
+                                                    const uint32_t* __restrict__ perm, const int* __restrict__ cid,
+                                                    const int* __restrict__ border, int mode, int64_t n,
+                                                    int32_t* __restrict__ out, uint8_t* __restrict__ out_core,
+                                                    uint32_t* __restrict__ info) {
+  // mode 0: non-core = noise; 1: non-core from the border pass; 2: first claim
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    const uint32_t o = perm[i];
+    if (o >= n) {
+      atomicOr(info, kInternalBit);
+      continue;
+    }
+    const bool c = core[i];
+    int v;
+    if (c) v = cid[labels[i]];
+    else if (mode == 1) v = border[i];
+    else if (mode == 2) v = labels[i] != i ? cid[labels[i]] : -1;
+    else v = -1;
+    out[o] = v;
+    if (out_core) out_core[o] = c ? 1 : 0;
+  }
+}
+
+// ---- device-wide exclusive scan of int32 (reduce, scan block sums, apply) ----
+
+__device__ __forceinline__ int wave_inclusive(int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int block_reduce(int x, int* s_w) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = x;
+  __syncthreads();
+  int t = 0;
+  for (int j = 0; j < kBlock / 64; ++j) t += s_w[j];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ in, int64_t n_cap,
+                                                        const int* __restrict__ d_n, int* __restrict__ bsums) {
+  __shared__ int s_w[kBlock / 64];
+  const int64_t n = d_n ? *d_n : n_cap;
+  const int64_t base = blockIdx.x * int64_t(kScanTile);
+  int x = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k * kBlock + threadIdx.x;
+    if (i < n) x += in[i];
+  }
+  int t = block_reduce(x, s_w);
+  if (threadIdx.x == 0) bsums[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_bsums(int* __restrict__ bsums, int64_t blocks,
+                                                       int* __restrict__ d_total) {
+  __shared__ int s_w[kBlock / 64];
+  __shared__ int s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < blocks; base += kBlock) {
+    int64_t i = base + threadIdx.x;
+    int v = i < blocks ? bsums[i] : 0;
+    int inc = wave_inclusive(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+    __syncthreads();
+    int add = s_carry;
+    for (int j = 0; j < w; ++j) add += s_w[j];
+    if (i < blocks) bsums[i] = inc - v + add;
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) s_carry = add + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && d_total) *d_total = s_carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int64_t n_cap,
+                                                       const int* __restrict__ d_n, const int* __restrict__ bsums) {
+  __shared__ int s_w[kBlock / 64];
+  __shared__ int s_carry;
+  const int64_t n = d_n ? *d_n : n_cap;
+  const int64_t base = blockIdx.x * int64_t(kScanTile);
+  // blocked layout: thread t owns items [t*kScanItems, (t+1)*kScanItems)
+  int v[kScanItems];
+  int sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + int64_t(threadIdx.x) * kScanItems + k;
+    v[k] = i < n ? in[i] : 0;
+    sum += v[k];
+  }
+  if (threadIdx.x == 0) s_carry = bsums[blockIdx.x];
+  int inc = wave_inclusive(sum);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+  __syncthreads();
+  int run = s_carry + inc - sum;
+  for (int j = 0; j < w; ++j) run += s_w[j];
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + int64_t(threadIdx.x) * kScanItems + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
+}  // namespace
+
+void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums, int64_t blocks, int* d_total,
+                 hipStream_t s) {
+  if (n <= 0) {
+    if (d_total) fill_u32(reinterpret_cast<uint32_t*>(d_total), 0, 1, s);
+    return;
+  }
+  const int64_t nb = ceil_div(n, kScanTile);
+  (void)blocks;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, in, n, d_n, bsums);
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsums, nb, d_total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, in, out, n, d_n, bsums);
+}
+
+void launch_init_labels(int* labels, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n);
+}
+
+void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, info);
+}
+
+void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s) {
+  if (min_pts <= 1) {
+    fill_u8(core, 1, n, s);
+    return;
+  }
+  fill_u8(core, 0, n, s);
+  hipLaunchKernelGGL(k_core_from_sets, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, n);
+}
+
+void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig, int* lflag,
+                   int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s) {
+  const int g = grid_for(n);
+  fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
+  hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
+  hipLaunchKernelGGL(k_leaders, dim3(g), dim3(kBlock), 0, s, labels, core, perm, minorig, n, lflag);
+  device_scan(lflag, rank, n, nullptr, bsums, scan_blocks, d_k, s);
+  hipLaunchKernelGGL(k_cluster_ids, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, rank, n, cid);
+}
+
+void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid, const int* border,
+                    bool first_border, bool have_border, int64_t n, int32_t* out_labels, uint8_t* out_core,
+                    uint32_t* info, hipStream_t s) {
+  int mode = have_border ? 1 : (first_border ? 2 : 0);
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, cid, border, mode, n,
+                     out_labels, out_core, info);
+}
+
+}  // namespace fdb

@@ -1,0 +1,263 @@
+// LSD radix sort of (key, index) pairs, 8-bit digits, stable. Section 4.1 sorts
+// queries and primitives along a space-filling curve; Karras' hierarchy needs
+// the keys sorted with equal keys left in index order, which a stable LSD sort
+// started from the identity permutation gives.
+//
+// Design (single-pass per digit, after Merrill & Adinets' "onesweep"): one
+// kernel builds the histograms of every pass at once; then each pass is a
+// single kernel in which a workgroup ranks a 4096-key tile with wavefront
+// ballots, learns its global offsets by a decoupled look-back over earlier
+// tiles, and scatters through LDS so that writes are contiguous per digit.
+// Tiles are numbered in the order workgroups start (an atomic ticket), so a
+// tile only waits on tiles already running.
+#include "fdb_device.hpp"
+#include "fdb_internal.hpp"
+
+namespace fdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kRadix = 256;
+
+// Look-back status word: [epoch:30][flag:2][count:32]. flag 1 = this tile's own
+// count, flag 2 = inclusive prefix through this tile. epoch = pass + 1 tells a
+// word of this pass from one left by an earlier pass.
+constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
+__device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint64_t flag, uint32_t count) {
+  return (uint64_t(epoch) << 34) | (flag << 32) | count;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift) {
+  return static_cast<uint32_t>(key >> shift) & 0xffu;
+}
+
+// Lanes of the wavefront whose `d` equals this lane's, among lanes with `valid`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t m = ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    bool bit = (d >> b) & 1u;
+    uint64_t bb = ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// Histogram of every pass's digit over all keys.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, int64_t n, int passes,
+                                                 uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[8][kRadix];
+  for (int i = threadIdx.x; i < 8 * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  // every lane of a wavefront runs the same trip count so ballots see all lanes
+  const int64_t base0 = blockIdx.x * int64_t(kBlock) + (threadIdx.x & ~63);
+  for (int64_t base = base0; base < n; base += stride) {
+    int64_t i = base + (threadIdx.x & 63);
+    bool valid = i < n;
+    K key = valid ? keys[i] : K(0);
+    for (int p = 0; p < passes; ++p) {
+      uint32_t d = digit_of(key, 8 * p);
+      uint64_t m = match_digit(d, valid);
+      if (valid && lane_id() == __ffsll(static_cast<unsigned long long>(m)) - 1)
+        atomicAdd(&s_h[p][d], static_cast<uint32_t>(__popcll(m)));
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * kRadix; i += kBlock) {
+    uint32_t v = (&s_h[0][0])[i];
+    if (v) atomicAdd(hist + i, v);
+  }
+}
+
+// Exclusive scan of each pass's 256 digit counts -> global digit offsets.
+__global__ __launch_bounds__(kRadix) void k_digit_offsets(const uint32_t* __restrict__ hist,
+                                                          uint32_t* __restrict__ digoff) {
+  __shared__ uint32_t s[kRadix];
+  const int p = blockIdx.x, d = threadIdx.x;
+  s[d] = hist[p * kRadix + d];
+  __syncthreads();
+  for (int off = 1; off < kRadix; off <<= 1) {
+    uint32_t v = d >= off ? s[d - off] : 0;
+    __syncthreads();
+    s[d] += v;
+    __syncthreads();
+  }
+  digoff[p * kRadix + d] = s[d] - hist[p * kRadix + d];
+}
+
+// Block-wide exclusive scan of one value per thread (kBlock threads).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) s_wsum[w] = x;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int j = 0; j < w; ++j) add += s_wsum[j];
+  __syncthreads();
+  return x - v + add;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_onesweep(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                     K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+                                                     int shift, uint32_t epoch, const uint32_t* __restrict__ digoff,
+                                                     uint32_t* __restrict__ tilectr, uint64_t* __restrict__ status,
+                                                     uint32_t* __restrict__ info) {
+  constexpr int kItems = kSortItems;
+  constexpr int kTile = kSortTile;
+  constexpr int kWaveTile = 64 * kItems;
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave prefixes
+  __shared__ uint32_t s_dstart[kRadix];        // tile-local start of each digit
+  __shared__ uint32_t s_gbase[kRadix];         // global start of this tile's run of each digit
+  __shared__ uint32_t s_wsum[kWaves];
+  __shared__ K s_keys[kTile];
+  __shared__ uint32_t s_vals[kTile];
+
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  if (tid == 0) s_tile = atomicAdd(tilectr, 1u);
+  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t wbase = tile * kTile + int64_t(w) * kWaveTile;
+
+  K key[kItems];
+  uint32_t val[kItems];
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t pos = wbase + k * 64 + lane;
+    bool valid = pos < n;
+    key[k] = valid ? kin[pos] : K(0);
+    val[k] = valid ? vin[pos] : 0u;
+  }
+  // Rank within the wavefront: positions run wave-major, then item, then lane,
+  // so processing items in order keeps the sort stable.
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    bool valid = wbase + k * 64 + lane < n;
+    uint32_t d = digit_of(key[k], shift);
+    uint64_t m = match_digit(d, valid);
+    int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    uint32_t before = 0;
+    if (valid && lane == leader) {  // leaders of distinct digits touch distinct words
+      before = s_wcnt[w][d];
+      s_wcnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
+    }
+    before = __shfl(before, leader < 0 ? 0 : leader);
+    rank[k] = before + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
+  }
+  __syncthreads();
+
+  // Thread d: prefix over wavefronts, tile total, then the look-back.
+  const uint32_t d = tid;
+  uint32_t total = 0;
+#pragma unroll
+  for (int j = 0; j < kWaves; ++j) {
+    uint32_t c = s_wcnt[j][d];
+    s_wcnt[j][d] = total;
+    total += c;
+  }
+  uint64_t* st = status + tile * kRadix + d;
+  uint32_t excl = 0;
+  if (tile == 0) {
+    st_agent64(st, pack_status(epoch, kFlagIncl, total));
+  } else {
+    st_agent64(st, pack_status(epoch, kFlagAgg, total));
+    int spins = 0;
+    for (int64_t j = tile - 1; j >= 0;) {
+      uint64_t v = ld_agent64(status + j * kRadix + d);
+      if (static_cast<uint32_t>(v >> 34) != epoch) {
+        // earlier tiles are running and publish without waiting; the cap only
+        // turns a broken invariant into an error instead of a hang
+        if (++spins > (1 << 24)) {
+          atomicOr(info, kInternalBit);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += static_cast<uint32_t>(v);
+      if (((v >> 32) & 3u) == kFlagIncl) break;
+      --j;
+    }
+    st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
+  }
+  s_gbase[d] = digoff[d] + excl;
+  uint32_t ds = block_exclusive_scan(total, s_wsum);
+  s_dstart[d] = ds;
+  __syncthreads();
+
+  // Local scatter into LDS in sorted order.
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    if (wbase + k * 64 + lane < n) {
+      uint32_t dk = digit_of(key[k], shift);
+      uint32_t pos = s_dstart[dk] + s_wcnt[w][dk] + rank[k];
+      s_keys[pos] = key[k];
+      s_vals[pos] = val[k];
+    }
+  }
+  __syncthreads();
+  const int64_t tile_n = n - tile * kTile < kTile ? n - tile * kTile : kTile;
+  for (int i = tid; i < tile_n; i += kBlock) {
+    K kk = s_keys[i];
+    uint32_t dk = digit_of(kk, shift);
+    uint32_t dest = s_gbase[dk] + (i - s_dstart[dk]);
+    if (dest >= n) {  // only after a failed look-back
+      atomicOr(info, kInternalBit);
+      continue;
+    }
+    kout[dest] = kk;
+    vout[dest] = s_vals[i];
+  }
+}
+
+template <typename K>
+int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, int bits, uint32_t* hist,
+                 uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info, hipStream_t s) {
+  const int passes = (bits + 7) / 8;
+  if (n <= 1 || passes == 0) return 0;
+  const int64_t tiles = ceil_div(n, kSortTile);
+  fill_u32(hist, 0, passes * kRadix, s);
+  fill_u32(tilectr, 0, passes, s);
+  fill_u32(reinterpret_cast<uint32_t*>(status), 0, tiles * kRadix * 2, s);
+  int hg = static_cast<int>(ceil_div(n, kBlock * 16));
+  if (hg > 2048) hg = 2048;
+  hipLaunchKernelGGL(k_hist<K>, dim3(hg), dim3(kBlock), 0, s, keys0, n, passes, hist);
+  hipLaunchKernelGGL(k_digit_offsets, dim3(passes), dim3(kRadix), 0, s, hist, digoff);
+  K* kb[2] = {keys0, keys1};
+  uint32_t* vb[2] = {vals0, vals1};
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(k_onesweep<K>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, kb[cur], vb[cur],
+                       kb[cur ^ 1], vb[cur ^ 1], n, 8 * p, static_cast<uint32_t>(p + 1), digoff + p * kRadix,
+                       tilectr + p, status, info);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+}  // namespace
+
+int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
+               uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info,
+               hipStream_t s) {
+  if (key64)
+    return radix_sort_t(static_cast<uint64_t*>(keys0), static_cast<uint64_t*>(keys1), vals0, vals1, n, bits, hist,
+                        digoff, tilectr, status, info, s);
+  return radix_sort_t(static_cast<uint32_t*>(keys0), static_cast<uint32_t*>(keys1), vals0, vals1, n, bits, hist,
+                      digoff, tilectr, status, info, s);
+}
+
+}  // namespace fdb

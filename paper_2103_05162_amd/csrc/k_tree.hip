@@ -1,0 +1,192 @@
+// Linear BVH over m primitives sorted by Morton key (Section 4.1 uses an LBVH
+// in the manner of Karras 2012): one thread per internal node finds its leaf
+// range and split from the longest common prefix of neighbouring keys (equal
+// keys compare by index), a second pass writes the escape links ("ropes") for
+// stack-less traversal, and a bottom-up pass computes exact min/max boxes.
+#include "fdb_device.hpp"
+#include "fdb_internal.hpp"
+
+namespace fdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Common-prefix length of keys i and j; -1 outside [0, m). Equal keys are told
+// apart by their positions, so every prefix is strictly ordered.
+template <typename K>
+__device__ __forceinline__ int prefix_len(const K* __restrict__ keys, int m, int i, int64_t j) {
+  if (j < 0 || j >= m) return -1;
+  K a = keys[i], b = keys[j];
+  if (a == b) return int(8 * sizeof(K)) + __clz(static_cast<uint32_t>(i) ^ static_cast<uint32_t>(j));
+  if constexpr (sizeof(K) == 8)
+    return __clzll(static_cast<unsigned long long>(a ^ b));
+  else
+    return __clz(static_cast<uint32_t>(a ^ b));
+}
+
+// Internal node i: its range is [min(i,j), max(i,j)] and its split gamma
+// separates [first, gamma] from [gamma+1, last]. Children are internal node
+// gamma / gamma+1, or leaves when their side holds one primitive.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_karras(const K* __restrict__ keys, int m_cap, const int* __restrict__ d_m,
+                                                   int* __restrict__ other, int* __restrict__ gamma_out,
+                                                   int* __restrict__ parent) {
+  const int m = d_m ? *d_m : m_cap;
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m - 1) return;
+  int dl = prefix_len(keys, m, i, int64_t(i) - 1);
+  int dr = prefix_len(keys, m, i, int64_t(i) + 1);
+  int d = dr > dl ? 1 : -1;
+  int dmin = dr > dl ? dl : dr;
+  int64_t lmax = 2;
+  while (prefix_len(keys, m, i, i + lmax * d) > dmin) lmax <<= 1;
+  int64_t l = 0;
+  for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+    if (prefix_len(keys, m, i, i + (l + t) * d) > dmin) l += t;
+  int64_t j = i + l * d;
+  int dnode = prefix_len(keys, m, i, j);
+  int64_t s = 0, t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (prefix_len(keys, m, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  int g = static_cast<int>(i + s * d + (d < 0 ? -1 : 0));
+  int first = static_cast<int>(d > 0 ? i : j), last = static_cast<int>(d > 0 ? j : i);
+  other[i] = static_cast<int>(j);
+  gamma_out[i] = g;
+  // parent[] holds internal nodes at [0, m-1) and leaf l at m-1+l
+  parent[first == g ? (m - 1) + g : g] = i;
+  parent[last == g + 1 ? (m - 1) + g + 1 : g + 1] = i;
+  if (i == 0) parent[0] = -1;
+}
+
+// Pre-order successor of a subtree whose last leaf is l: the right child of the
+// node splitting l from l+1, which is internal node l+1 when that node's range
+// starts at l+1 and leaf l+1 otherwise.
+__device__ __forceinline__ int successor(const int* __restrict__ other, int m, int l) {
+  if (l >= m - 1) return static_cast<int>(kEnd);
+  int r = l + 1;
+  if (r <= m - 2 && other[r] > r) return r;
+  return static_cast<int>(kLeaf | static_cast<uint32_t>(r));
+}
+
+__global__ __launch_bounds__(kBlock) void k_ropes(const int* __restrict__ other, int m_cap, const int* __restrict__ d_m,
+                                                  int* __restrict__ rope, int* __restrict__ leaf_rope) {
+  const int m = d_m ? *d_m : m_cap;
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < m - 1) {
+    int last = other[i] > i ? other[i] : i;
+    rope[i] = successor(other, m, last);
+  }
+  if (i < m) leaf_rope[i] = successor(other, m, i);
+}
+
+struct Box {
+  float lo[3], hi[3];
+};
+
+template <int D>
+__device__ __forceinline__ Box leaf_box(int l, const float* __restrict__ xs, int64_t n, const float4* prim_lo,
+                                        const float4* prim_hi) {
+  Box b;
+  if (prim_lo) {
+    float4 a = prim_lo[l], c = prim_hi[l];
+    b.lo[0] = a.x; b.lo[1] = a.y; b.lo[2] = a.z;
+    b.hi[0] = c.x; b.hi[1] = c.y; b.hi[2] = c.z;
+  } else {
+    b.lo[0] = b.hi[0] = xs[l];
+    b.lo[1] = b.hi[1] = xs[n + l];
+    b.lo[2] = b.hi[2] = D == 3 ? xs[2 * n + l] : 0.0f;
+  }
+  return b;
+}
+
+// Bottom-up refit: each leaf walks towards the root; at every internal node the
+// second of the two arriving threads merges both child boxes and continues.
+// The fences order a child's box before the arrival counter across XCDs.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
+                                                  int64_t n,
+                                                  const float4* __restrict__ prim_lo, const float4* __restrict__ prim_hi,
+                                                  const int* __restrict__ other, const int* __restrict__ gamma,
+                                                  const int* __restrict__ parent, int* __restrict__ flags,
+                                                  float4* __restrict__ node_a, float4* __restrict__ node_b,
+                                                  uint32_t* __restrict__ info) {
+  const int m = d_m ? *d_m : m_cap;
+  int l = blockIdx.x * kBlock + threadIdx.x;
+  if (m < 2 || l >= m) return;
+  int p = parent[(m - 1) + l];
+  while (p >= 0) {
+    if (p >= m - 1) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    __threadfence();
+    if (atomicAdd(flags + p, 1) == 0) return;
+    __threadfence();
+    int o = other[p], g = gamma[p];
+    int first = o < p ? o : p, last = o > p ? o : p;
+    if (first < 0 || last >= m || g < first || g >= last) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    Box a, b;
+    if (first == g) {
+      a = leaf_box<D>(g, xs, n, prim_lo, prim_hi);
+    } else {
+      float4 u = node_a[g], v = node_b[g];
+      a.lo[0] = u.x; a.lo[1] = u.y; a.lo[2] = u.z;
+      a.hi[0] = v.x; a.hi[1] = v.y; a.hi[2] = v.z;
+    }
+    if (last == g + 1) {
+      b = leaf_box<D>(g + 1, xs, n, prim_lo, prim_hi);
+    } else {
+      float4 u = node_a[g + 1], v = node_b[g + 1];
+      b.lo[0] = u.x; b.lo[1] = u.y; b.lo[2] = u.z;
+      b.hi[0] = v.x; b.hi[1] = v.y; b.hi[2] = v.z;
+    }
+    node_a[p] = make_float4(fminf(a.lo[0], b.lo[0]), fminf(a.lo[1], b.lo[1]), fminf(a.lo[2], b.lo[2]),
+                            __int_as_float(o));
+    node_b[p] = make_float4(fmaxf(a.hi[0], b.hi[0]), fmaxf(a.hi[1], b.hi[1]), fmaxf(a.hi[2], b.hi[2]),
+                            __int_as_float(g));
+    p = parent[p];
+  }
+}
+
+// m_cap: number of primitives, or an upper bound when d_m (device) holds it.
+template <typename K>
+void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs, int64_t n_pts,
+             const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
+             int* leaf_rope, int* parent, int* flags, int* other, int* gamma, uint32_t* info, hipStream_t s) {
+  if (m_cap <= 0) return;
+  int g = static_cast<int>(ceil_div(m_cap, kBlock));
+  if (m_cap >= 2) {
+    fill_u32(reinterpret_cast<uint32_t*>(flags), 0, m_cap - 1, s);
+    hipLaunchKernelGGL(k_karras<K>, dim3(g), dim3(kBlock), 0, s, keys, m_cap, d_m, other, gamma, parent);
+  }
+  hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
+  if (m_cap >= 2) {
+    if (dim == 3)
+      hipLaunchKernelGGL(k_refit<3>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, prim_lo, prim_hi, other,
+                         gamma, parent, flags, node_a, node_b, info);
+    else
+      hipLaunchKernelGGL(k_refit<2>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, prim_lo, prim_hi, other,
+                         gamma, parent, flags, node_a, node_b, info);
+  }
+}
+
+}  // namespace
+
+void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
+                const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* parent,
+                int* flags, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s) {
+  if (key64)
+    build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, prim_lo, prim_hi, node_a, node_b, rope,
+            leaf_rope, parent, flags, other, gamma, info, s);
+  else
+    build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, prim_lo, prim_hi, node_a, node_b, rope,
+            leaf_rope, parent, flags, other, gamma, info, s);
+}
+
+}  // namespace fdb

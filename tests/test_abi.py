@@ -1,0 +1,73 @@
+"""The C ABI library loads and exports every entry point include/fdbscan.h
+declares; host-side argument checks and workspace sizing need no GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdbscan.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("fdb_create", "fdb_destroy", "fdb_workspace_bytes", "fdb_dbscan", "fdb_last_info",
+                 "fdb_status_string", "fdb_set_timing", "fdb_stage_times"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_05162_amd import _lib
+    lib = _lib.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (fdb_\w+)", out))
+    assert set(_declared()) <= exported
+
+
+def test_status_strings():
+    from paper_2103_05162_amd import _lib
+    assert _lib.status_string(0) == "ok"
+    assert "invalid" in _lib.status_string(1)
+    assert _lib.status_string(99) == "unknown status"
+
+
+def test_workspace_is_linear_in_n_and_rejects_bad_arguments():
+    from paper_2103_05162_amd import _lib
+    for algo in ("fdbscan", "densebox"):
+        for d in (2, 3):
+            a = _lib.workspace_bytes(1 << 20, d, algo)
+            b = _lib.workspace_bytes(1 << 21, d, algo)
+            c = _lib.workspace_bytes(1 << 22, d, algo)
+            assert a < b < c
+            per_point = (c - b) / (1 << 21)
+            assert abs((b - a) / (1 << 20) - per_point) < 1.0
+            assert per_point < 400
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    assert lib.fdb_workspace_bytes(10, 4, None, ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_workspace_bytes(-1, 3, None, ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_workspace_bytes(1 << 30, 3, None, ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    bad = _lib.make_options("fdbscan", "canonical", leaf_size=-1)
+    assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    bad = _lib.make_options("fdbscan", "canonical", block_size=100)
+    assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_workspace_bytes(0, 2, None, ctypes.byref(out)) == 0
+
+
+def test_null_handle_is_rejected_before_any_gpu_call():
+    from paper_2103_05162_amd import _lib
+    lib = _lib.load()
+    assert lib.fdb_dbscan(None, None, 0, 3, ctypes.c_float(0.1), 5, None, None, None, None, None, 0,
+                          None) == _lib.FDB_ERR_INVALID
+    lib.fdb_destroy(None)
+    assert lib.fdb_create(None, 0) == _lib.FDB_ERR_INVALID

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Canonical mode must match the oracle bit for bit (labels, core flags, K) for
+both algorithms; first-claim mode (the paper's border rule) must match up to
+the free choice of a border point's cluster. Sizes span many sort tiles,
+traversal workgroups and a ragged tail; edge cases cover the degenerate inputs
+the method has.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import assert_tolerance_mode
+from workloads.gen import workload
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ["fdbscan", "densebox"]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2103_05162_amd as fdb
+    fdb.load()
+    return torch.device("cuda:0")
+
+
+def run_gpu(dev, pts, eps, min_pts, algo="fdbscan", border="canonical", **kw):
+    import torch
+    import paper_2103_05162_amd as fdb
+    t = torch.from_numpy(np.ascontiguousarray(pts, dtype=np.float32)).to(dev)
+    labels, core, k = fdb.dbscan(t, eps, min_pts, algo=algo, border=border, **kw)
+    torch.cuda.synchronize()
+    return labels.cpu().numpy(), core.cpu().numpy(), k
+
+
+def assert_exact(dev, pts, eps, min_pts, algo, ref=None, **kw):
+    _say(f"[gpu] n={len(pts)} d={pts.shape[1]} eps={eps} minPts={min_pts} algo={algo} {kw}")
+    if ref is None:
+        ref = oracle.dbscan(pts, eps, min_pts)
+    lab, core, k = run_gpu(dev, pts, eps, min_pts, algo, **kw)
+    rl, rc, rk = ref
+    assert k == rk, f"K {k} != {rk}"
+    assert np.array_equal(core, rc), f"core differs at {np.flatnonzero(core != rc)[:10]}"
+    bad = np.flatnonzero(lab != rl)
+    assert bad.size == 0, f"{bad.size} labels differ, first {bad[:10]}: gpu {lab[bad[:10]]} ref {rl[bad[:10]]}"
+    return ref
+
+
+# ---- the configured workloads (full C1; reduced C2/C3 with their density) ------
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c1_full_canonical(dev, algo):
+    w = workload("c1_blobs2d_16k")
+    assert_exact(dev, w.points, w.eps, w.min_pts, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c1_first_claim_mode(dev, algo):
+    w = workload("c1_blobs2d_16k")
+    rl, rc, rk = oracle.dbscan(w.points, w.eps, w.min_pts)
+    _say(f"[gpu] c1 first-claim {algo}")
+    lab, core, k = run_gpu(dev, w.points, w.eps, w.min_pts, algo, border="first")
+    assert k == rk
+    assert_tolerance_mode(w.points, w.eps, lab, core, rl, rc, oracle.check_border)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("scale", [1 / 16])
+def test_c2_reduced_canonical(dev, algo, scale):
+    w = workload("c2_fof3d_2m", scale)
+    assert_exact(dev, w.points, w.eps, w.min_pts, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c3_reduced_canonical(dev, algo):
+    w = workload("c3_dense3d_8m", 1 / 64)
+    assert_exact(dev, w.points, w.eps, w.min_pts, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c3_reduced_first_claim_mode(dev, algo):
+    w = workload("c3_dense3d_8m", 1 / 64)
+    rl, rc, rk = oracle.dbscan(w.points, w.eps, w.min_pts)
+    _say(f"[gpu] c3/64 first-claim {algo}")
+    lab, core, k = run_gpu(dev, w.points, w.eps, w.min_pts, algo, border="first")
+    assert k == rk
+    assert_tolerance_mode(w.points, w.eps, lab, core, rl, rc, oracle.check_border)
+
+
+# ---- both algorithms, border-rich mixtures, several parameter choices -----------
+
+def _mixture(seed, n, d, k, sigma, noise=0.3):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0, 1, size=(k, d))
+    lab = rng.integers(0, k, size=n)
+    pts = c[lab] + sigma * rng.standard_normal((n, d))
+    m = rng.random(n) < noise
+    pts[m] = rng.uniform(0, 1, size=(int(m.sum()), d))
+    return pts.astype(np.float32)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("d,n,eps,mp,seed", [
+    (2, 30011, 0.004, 5, 1), (3, 40009, 0.02, 10, 2), (3, 20011, 0.03, 3, 3), (2, 25013, 0.006, 2, 4),
+    (3, 12007, 0.015, 1, 5), (2, 9001, 0.01, 30, 6),
+])
+def test_mixtures_canonical(dev, algo, d, n, eps, mp, seed):
+    pts = _mixture(seed, n, d, 12, 0.01)
+    assert_exact(dev, pts, eps, mp, algo)
+
+
+@pytest.mark.parametrize("leaf,block", [(1, 64), (2, 128), (8, 256), (16, 512), (32, 1024)])
+def test_leaf_and_block_sizes_do_not_change_labels(dev, leaf, block):
+    pts = _mixture(7, 20000, 3, 10, 0.01)
+    ref = oracle.dbscan(pts, 0.02, 6)
+    for algo in ALGOS:
+        assert_exact(dev, pts, 0.02, 6, algo, ref=ref, leaf_size=leaf, block_size=block)
+
+
+# ---- edge cases ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 4095, 4096, 4097, 8193])
+def test_ragged_sizes(dev, algo, n):
+    pts = _mixture(100 + n, n, 3, 3, 0.02)
+    for mp in (1, 2, 4):
+        assert_exact(dev, pts, 0.05, mp, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_empty_input(dev, algo):
+    import torch
+    import paper_2103_05162_amd as fdb
+    t = torch.zeros((0, 3), dtype=torch.float32, device=dev)
+    lab, core, k = fdb.dbscan(t, 0.1, 3, algo=algo)
+    assert k == 0 and lab.numel() == 0
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_all_duplicates(dev, algo):
+    pts = np.full((5000, 3), 0.25, np.float32)
+    assert_exact(dev, pts, 1e-4, 10, algo)
+    assert_exact(dev, pts, 1e-4, 5000, algo)
+    assert_exact(dev, pts, 1e-4, 5001, algo)
+    assert_exact(dev, pts, 1e-4, 2, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_degenerate_extent_and_exact_distances(dev, algo):
+    # points on a line (zero extent on two axes) with dyadic spacing = eps
+    x = np.arange(3000, dtype=np.float32) * np.float32(0.125)
+    pts = np.stack([x, np.zeros_like(x), np.zeros_like(x)], 1)
+    pts[::7, 0] += np.float32(0.0625)
+    assert_exact(dev, pts, 0.125, 3, algo)
+    # 2D unit lattice, eps = 1 exactly: interior points have 5 neighbours
+    g = np.stack(np.meshgrid(np.arange(120), np.arange(90), indexing="ij"), -1).reshape(-1, 2).astype(np.float32)
+    assert_exact(dev, g, 1.0, 5, algo)
+    assert_exact(dev, g, 1.0, 6, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_eps_extremes(dev, algo):
+    pts = _mixture(9, 6000, 2, 4, 0.02)
+    assert_exact(dev, pts, 10.0, 7, algo)       # one cluster
+    assert_exact(dev, pts, 1e-7, 2, algo)       # all noise
+    assert_exact(dev, pts, 1e-7, 1, algo)       # every point its own cluster
+
+
+def test_densebox_falls_back_when_the_grid_cannot_be_keyed(dev):
+    import paper_2103_05162_amd as fdb
+    rng = np.random.default_rng(3)
+    pts = (rng.uniform(0, 1e7, size=(3000, 2))).astype(np.float32)
+    pts[:100] = pts[0] + rng.uniform(0, 1e-3, size=(100, 2)).astype(np.float32)
+    ref = oracle.dbscan(pts, 2e-3, 5)
+    assert_exact(dev, pts, 2e-3, 5, "densebox", ref=ref)
+    assert fdb.default_handle(0).last_info() & fdb.FDB_INFO_DENSEBOX_FALLBACK
+    assert_exact(dev, pts, 2e-3, 5, "fdbscan", ref=ref)
+    assert not fdb.default_handle(0).last_info() & fdb.FDB_INFO_DENSEBOX_FALLBACK
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_nonfinite_input_is_reported(dev, algo):
+    import torch
+    import paper_2103_05162_amd as fdb
+    pts = _mixture(11, 1000, 3, 2, 0.02)
+    pts[17, 1] = np.nan
+    t = torch.from_numpy(pts).to(dev)
+    with pytest.raises(fdb.FdbError) as e:
+        fdb.dbscan(t, 0.05, 4, algo=algo)
+    assert e.value.status == 4
+
+
+def test_invalid_arguments_are_rejected(dev):
+    import torch
+    import paper_2103_05162_amd as fdb
+    t = torch.zeros((10, 3), dtype=torch.float32, device=dev)
+    for eps, mp in ((0.0, 3), (-1.0, 3), (float("nan"), 3), (float("inf"), 3), (0.1, 0)):
+        with pytest.raises(fdb.FdbError) as e:
+            fdb.dbscan(t, eps, mp)
+        assert e.value.status == 1
+
+
+# ---- metamorphic and repeatability ----------------------------------------------
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_reflection_and_scaling_give_identical_labels(dev, algo):
+    pts = _mixture(12, 30000, 3, 8, 0.01)
+    eps, mp = 0.015, 5
+    base = run_gpu(dev, pts, eps, mp, algo)
+    for q, e in ((-pts, eps), (pts[:, [1, 0, 2]].copy(), eps), (pts * np.float32(64.0), eps * 64.0)):
+        got = run_gpu(dev, np.ascontiguousarray(q), e, mp, algo)
+        assert np.array_equal(got[0], base[0]) and np.array_equal(got[1], base[1])
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_repeated_runs_are_identical(dev, algo):
+    w = workload("c3_dense3d_8m", 1 / 128)
+    first = run_gpu(dev, w.points, w.eps, w.min_pts, algo)
+    for _ in range(5):
+        again = run_gpu(dev, w.points, w.eps, w.min_pts, algo)
+        assert np.array_equal(again[0], first[0]) and np.array_equal(again[1], first[1])
+
+
+def test_fdbscan_and_densebox_agree(dev):
+    pts = _mixture(13, 50000, 3, 20, 0.004, noise=0.2)
+    a = run_gpu(dev, pts, 0.01, 8, "fdbscan")
+    b = run_gpu(dev, pts, 0.01, 8, "densebox")
+    assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
