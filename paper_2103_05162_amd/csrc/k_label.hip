@@ -57,11 +57,33 @@ __global__ __launch_bounds__(kBlock) void k_core_from_sets(const int* __restrict
   }
 }
 
+// Smallest input index per cluster. Sorted neighbours mostly share a root, so a
+// wavefront whose core lanes all have one root reduces first and issues a
+// single atomic instead of 64 on the same word.
 __global__ __launch_bounds__(kBlock) void k_minorig(const int* __restrict__ labels, const uint8_t* __restrict__ core,
                                                     const uint32_t* __restrict__ perm, int64_t n,
                                                     int* __restrict__ minorig) {
-  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    if (core[i]) atomicMin(minorig + labels[i], static_cast<int>(perm[i]));
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t base = blockIdx.x * int64_t(kBlock) + (threadIdx.x & ~63); base < n; base += stride) {
+    const int64_t i = base + lane;
+    const bool valid = i < n && core[i];
+    const int r = valid ? labels[i] : -1;
+    int o = valid ? static_cast<int>(perm[i]) : 0x7fffffff;
+    const uint64_t vm = ballot(valid);
+    if (vm == 0) continue;
+    const int leader = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+    const int r0 = __shfl(r, leader);
+    if (ballot(valid && r != r0) == 0) {
+      for (int off = 32; off > 0; off >>= 1) {
+        int y = __shfl_xor(o, off);
+        o = y < o ? y : o;
+      }
+      if (lane == leader) atomicMin(minorig + r0, o);
+    } else if (valid) {
+      atomicMin(minorig + r, o);
+    }
+  }
 }
 
 // lflag[o] = 1 iff input index o is the smallest input index among the core

@@ -102,54 +102,81 @@ __device__ __forceinline__ Box leaf_box(int l, const float* __restrict__ xs, int
   return b;
 }
 
+// Node boxes cross workgroups (and XCDs) inside the refit kernel, so they are
+// written and read with agent-scope (L2-bypassing) 64-bit atomics; a writer
+// drains its stores (s_waitcnt vmcnt(0)) before it bumps the arrival counter,
+// and the second arriver only reads after that counter's value came back. No
+// L2-wide writeback or invalidate is needed.
+__device__ __forceinline__ uint64_t pack2(float a, float b) {
+  return uint64_t(__float_as_uint(a)) | (uint64_t(__float_as_uint(b)) << 32);
+}
+__device__ __forceinline__ float lo32(uint64_t v) { return __uint_as_float(static_cast<uint32_t>(v)); }
+__device__ __forceinline__ float hi32(uint64_t v) { return __uint_as_float(static_cast<uint32_t>(v >> 32)); }
+
+__device__ __forceinline__ void store_node(float4* node_a, float4* node_b, int p, const Box& b, int o, int g) {
+  uint64_t* a = reinterpret_cast<uint64_t*>(node_a + p);
+  uint64_t* c = reinterpret_cast<uint64_t*>(node_b + p);
+  st_agent64(a, pack2(b.lo[0], b.lo[1]));
+  st_agent64(a + 1, pack2(b.lo[2], __int_as_float(o)));
+  st_agent64(c, pack2(b.hi[0], b.hi[1]));
+  st_agent64(c + 1, pack2(b.hi[2], __int_as_float(g)));
+}
+
+__device__ __forceinline__ Box load_node(const float4* node_a, const float4* node_b, int k) {
+  const uint64_t* a = reinterpret_cast<const uint64_t*>(node_a + k);
+  const uint64_t* c = reinterpret_cast<const uint64_t*>(node_b + k);
+  uint64_t a0 = ld_agent64(a), a1 = ld_agent64(a + 1), c0 = ld_agent64(c), c1 = ld_agent64(c + 1);
+  Box b;
+  b.lo[0] = lo32(a0); b.lo[1] = hi32(a0); b.lo[2] = lo32(a1);
+  b.hi[0] = lo32(c0); b.hi[1] = hi32(c0); b.hi[2] = lo32(c1);
+  return b;
+}
+
 // Bottom-up refit: each leaf walks towards the root; at every internal node the
-// second of the two arriving threads merges both child boxes and continues.
-// The fences order a child's box before the arrival counter across XCDs.
+// second of the two arriving threads merges its box with the sibling's and
+// continues upwards, so every box is the exact min/max of its leaves.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
                                                   int64_t n,
                                                   const float4* __restrict__ prim_lo, const float4* __restrict__ prim_hi,
                                                   const int* __restrict__ other, const int* __restrict__ gamma,
                                                   const int* __restrict__ parent, int* __restrict__ flags,
-                                                  float4* __restrict__ node_a, float4* __restrict__ node_b,
-                                                  uint32_t* __restrict__ info) {
+                                                  float4* node_a, float4* node_b, uint32_t* __restrict__ info) {
   const int m = d_m ? *d_m : m_cap;
   int l = blockIdx.x * kBlock + threadIdx.x;
   if (m < 2 || l >= m) return;
+  Box box = leaf_box<D>(l, xs, n, prim_lo, prim_hi);
+  int prev = l;
+  bool prev_leaf = true;
   int p = parent[(m - 1) + l];
   while (p >= 0) {
     if (p >= m - 1) {
       atomicOr(info, kInternalBit);
       return;
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's node stores have landed
     if (atomicAdd(flags + p, 1) == 0) return;
-    __threadfence();
-    int o = other[p], g = gamma[p];
-    int first = o < p ? o : p, last = o > p ? o : p;
+    const int o = other[p], g = gamma[p];
+    const int first = o < p ? o : p, last = o > p ? o : p;
     if (first < 0 || last >= m || g < first || g >= last) {
       atomicOr(info, kInternalBit);
       return;
     }
-    Box a, b;
-    if (first == g) {
-      a = leaf_box<D>(g, xs, n, prim_lo, prim_hi);
-    } else {
-      float4 u = node_a[g], v = node_b[g];
-      a.lo[0] = u.x; a.lo[1] = u.y; a.lo[2] = u.z;
-      a.hi[0] = v.x; a.hi[1] = v.y; a.hi[2] = v.z;
+    const bool left_leaf = first == g, right_leaf = last == g + 1;
+    const bool came_left = prev == g && prev_leaf == left_leaf;
+    Box sib;
+    if (came_left)
+      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, prim_lo, prim_hi) : load_node(node_a, node_b, g + 1);
+    else
+      sib = left_leaf ? leaf_box<D>(g, xs, n, prim_lo, prim_hi) : load_node(node_a, node_b, g);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      box.lo[k] = fminf(box.lo[k], sib.lo[k]);
+      box.hi[k] = fmaxf(box.hi[k], sib.hi[k]);
     }
-    if (last == g + 1) {
-      b = leaf_box<D>(g + 1, xs, n, prim_lo, prim_hi);
-    } else {
-      float4 u = node_a[g + 1], v = node_b[g + 1];
-      b.lo[0] = u.x; b.lo[1] = u.y; b.lo[2] = u.z;
-      b.hi[0] = v.x; b.hi[1] = v.y; b.hi[2] = v.z;
-    }
-    node_a[p] = make_float4(fminf(a.lo[0], b.lo[0]), fminf(a.lo[1], b.lo[1]), fminf(a.lo[2], b.lo[2]),
-                            __int_as_float(o));
-    node_b[p] = make_float4(fmaxf(a.hi[0], b.hi[0]), fmaxf(a.hi[1], b.hi[1]), fmaxf(a.hi[2], b.hi[2]),
-                            __int_as_float(g));
+    store_node(node_a, node_b, p, box, o, g);
+    prev = p;
+    prev_leaf = false;
     p = parent[p];
   }
 }
