@@ -65,7 +65,7 @@ Plan make_plan(int64_t n, int dim, int algo) {
   p.cid = take(N * 4);
   p.border = take(N * 4);
   p.cell_id = p.cell_start = p.cand = p.cell_dense = p.cell_lo = p.cell_hi = 0;
-  p.pflag = p.prim_of = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = 0;
+  p.pflag = p.prim_of = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = p.dense_list = 0;
   if (algo == FDB_ALGO_DENSEBOX) {
     p.cell_id = take(N * 4);
     p.cell_start = take((N + 1) * 4);
@@ -80,6 +80,7 @@ Plan make_plan(int64_t n, int dim, int algo) {
     p.prim_lo = take(N * 16);
     p.prim_hi = take(N * 16);
     p.prim_key = take(N * 8);
+    p.dense_list = take(N * 4);
   }
   p.bytes = off;
   return p;
@@ -440,8 +441,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
                    at<int>(ws, plan.cell_start), at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense),
                    at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_of), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
-                   at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key), lab, core,
-                   misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
+                   at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key),
+                   at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
@@ -454,6 +455,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     ta.prim_cnt = at<int>(ws, plan.prim_cnt);
     ta.prim_lo = at<float4>(ws, plan.prim_lo);
     ta.prim_hi = at<float4>(ws, plan.prim_hi);
+    ta.dense_list = at<int>(ws, plan.dense_list);
+    ta.d_ndense = misc + kMiscNumDense;
   } else {
     st.mark("morton");
     launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], s);

@@ -32,7 +32,7 @@ struct Plan {
   size_t minorig, lflag, rank, bsums, cid, border;
   // DenseBox
   size_t cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt,
-      prim_lo, prim_hi, prim_key;
+      prim_lo, prim_hi, prim_key, dense_list;
   int64_t sort_tiles = 0, scan_blocks = 0;
 };
 
@@ -44,6 +44,7 @@ enum MiscSlot : int {
   kMiscNumCells = 1,     // DenseBox: number of non-empty cells
   kMiscNumCand = 2,      // DenseBox: cells with >= minPts points
   kMiscNumPrims = 3,     // DenseBox: m = dense cells + points outside them
+  kMiscNumDense = 4,     // DenseBox: dense cells
   kMiscCount = 16
 };
 
@@ -97,8 +98,8 @@ struct GridParams {
 void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2,
                     int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo,
                     float4* cell_hi, int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo,
-                    float4* prim_hi, void* prim_key, int* labels, uint8_t* core, int* misc, int* bsums,
-                    int64_t scan_blocks, hipStream_t s);
+                    float4* prim_hi, void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
+                    int* bsums, int64_t scan_blocks, hipStream_t s);
 
 // k_trav.hip
 struct TravArgs {
@@ -117,6 +118,8 @@ struct TravArgs {
   const int* prim_cnt;  // > 0: a single point; < 0: -(count) points of a dense cell
   const float4* prim_lo;
   const float4* prim_hi;
+  const int* dense_list;  // dense-cell primitive indices
+  const int* d_ndense;    // their number (device)
   uint32_t* info;  // FDB_INFO_* bits; kernels raise FDB_INFO_INTERNAL on a broken walk
   int block;
 };

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
                                                   int* __restrict__ prim_of, int* __restrict__ prim_start,
                                                   int* __restrict__ prim_cnt, float4* __restrict__ prim_lo,
                                                   float4* __restrict__ prim_hi, K* __restrict__ prim_key,
+                                                  int* __restrict__ dense_list, int* __restrict__ num_dense,
                                                   int* __restrict__ labels, uint8_t* __restrict__ core) {
   for (int64_t i64 = blockIdx.x * int64_t(kBlock) + threadIdx.x; i64 < n; i64 += int64_t(gridDim.x) * kBlock) {
     const int i = static_cast<int>(i64);
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
         prim_lo[p] = cell_lo[c];
         prim_hi[p] = cell_hi[c];
         prim_key[p] = keys[i];
+        dense_list[atomicAdd(num_dense, 1)] = p;
       }
     } else {
       const int p = pidx[i];
@@ -151,11 +153,12 @@ inline int grid_for(int64_t n) {
 template <typename K>
 void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
              int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag, int* prim_of,
-             int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* labels,
-             uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, hipStream_t s) {
+             int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* dense_list,
+             int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, hipStream_t s) {
   int* d_cells = misc + kMiscNumCells;
   int* d_cand = misc + kMiscNumCand;
   int* d_prims = misc + kMiscNumPrims;
+  int* d_dense = misc + kMiscNumDense;
   const int g = grid_for(n);
   hipLaunchKernelGGL(k_cell_heads<K>, dim3(g), dim3(kBlock), 0, s, keys, n, pflag);
   device_scan(pflag, cell_id, n, nullptr, bsums, scan_blocks, d_cells, s);
@@ -175,12 +178,12 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
   if (dim == 3)
     hipLaunchKernelGGL((k_prims<3, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
-                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, labels,
-                       core);
+                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
+                       d_dense, labels, core);
   else
     hipLaunchKernelGGL((k_prims<2, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
-                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, labels,
-                       core);
+                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
+                       d_dense, labels, core);
 }
 
 }  // namespace
@@ -188,16 +191,16 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
 void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2, int min_pts,
                     int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo, float4* cell_hi,
                     int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
-                    void* prim_key, int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks,
-                    hipStream_t s) {
+                    void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc, int* bsums,
+                    int64_t scan_blocks, hipStream_t s) {
   if (key64)
     cells_t(static_cast<const uint64_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
             cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint64_t*>(prim_key), labels, core, misc, bsums, scan_blocks, s);
+            static_cast<uint64_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, s);
   else
     cells_t(static_cast<const uint32_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
             cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint32_t*>(prim_key), labels, core, misc, bsums, scan_blocks, s);
+            static_cast<uint32_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, s);
 }
 
 }  // namespace fdb

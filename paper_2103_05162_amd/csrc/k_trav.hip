@@ -184,6 +184,9 @@ __global__ void k_border_fdb(TravArgs a) {
 // --------------------------------------------------------------- DenseBox ----
 // Primitive p covers sorted points [prim_start[p], prim_start[p] + |cnt|):
 // cnt > 0 is a single point, cnt < 0 a dense cell (all core, one cluster).
+// Points outside dense cells query one thread per point primitive (so
+// wavefronts are full and in Morton order); a dense cell queries once, one
+// wavefront per cell, whose 64 lanes test the cell's points together.
 
 template <int D>
 __device__ __forceinline__ bool box_near(const TravArgs& a, int p, const Query& q, float eps2) {
@@ -191,111 +194,393 @@ __device__ __forceinline__ bool box_near(const TravArgs& a, int p, const Query& 
   return box_dist2<D>(q.x, q.y, q.z, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= eps2;
 }
 
+// Wave-uniform walk for a box query (every point of box [lo,hi]), masked like
+// traverse(): visit(q) is called with the same q on every lane.
+template <int D, typename F>
+__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const float* lo, const float* hi, float eps2,
+                                             int mask, uint32_t* info, F&& visit) {
+  if (m <= 0 || mask >= m - 1) return;
+  uint32_t node = m == 1 ? kLeaf : 0u;
+  int64_t steps = 0;
+  const int64_t max_steps = 2 * int64_t(m) + 2;
+  while (node != kEnd) {
+    node = __builtin_amdgcn_readfirstlane(node);
+    if (++steps > max_steps) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (node & kLeaf) {
+      int l = static_cast<int>(node & ~kLeaf);
+      if (l >= m) {
+        atomicOr(info, kInternalBit);
+        return;
+      }
+      if (visit(l)) return;
+      node = static_cast<uint32_t>(t.leaf_rope[l]);
+      continue;
+    }
+    if (node >= static_cast<uint32_t>(m - 1)) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    float4 na = t.node_a[node];
+    float4 nb = t.node_b[node];
+    if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > eps2) {
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    int k = static_cast<int>(node);
+    int o = __float_as_int(na.w), g = __float_as_int(nb.w);
+    int first = o < k ? o : k, last = o > k ? o : k;
+    if (first < 0 || last >= m || g < first || g >= last) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (last - first < t.leaf_size) {
+      int s = first <= mask ? mask + 1 : first;
+      for (int l = s; l <= last; ++l)
+        if (visit(l)) return;
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    if (g <= mask)
+      node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+    else
+      node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+  }
+}
+
+// Is some point of the cell [sa, sa+na) within eps of p? (whole wavefront)
+template <int D>
+__device__ __forceinline__ bool cell_reaches_point(const float* __restrict__ xs, int64_t n, int sa, int na, float px,
+                                                   float py, float pz, float eps2) {
+  const int lane = lane_id();
+  for (int base = 0; base < na; base += 64) {
+    bool h = false;
+    if (base + lane < na) {
+      const int64_t j = sa + base + lane;
+      h = dist2v<D>(xs[j], xs[n + j], D == 3 ? xs[2 * n + j] : 0.0f, px, py, pz) <= eps2;
+    }
+    if (ballot(h)) return true;
+  }
+  return false;
+}
+
+// Is some pair (a in cell A, b in cell B) within eps? (whole wavefront; lanes
+// hold A's points, B's points are streamed; A's points out of reach of B's box
+// sit out)
+template <int D>
+__device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_t n, int sa, int na, int sb, int nb,
+                                           float4 blo, float4 bhi, float eps2) {
+  const int lane = lane_id();
+  for (int base = 0; base < na; base += 64) {
+    bool act = base + lane < na;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    if (act) {
+      const int64_t j = sa + base + lane;
+      ax = xs[j];
+      ay = xs[n + j];
+      az = D == 3 ? xs[2 * n + j] : 0.0f;
+      act = box_dist2<D>(ax, ay, az, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) <= eps2;
+    }
+    if (!ballot(act)) continue;
+    for (int jb = sb; jb < sb + nb; ++jb) {
+      const float bx = xs[jb], by = xs[n + jb], bz = D == 3 ? xs[2 * n + jb] : 0.0f;
+      const bool h = act && dist2v<D>(ax, ay, az, bx, by, bz) <= eps2;
+      if (ballot(h)) return true;
+    }
+  }
+  return false;
+}
+
+// Resumable per-lane walk, one primitive (or one internal node) per step, so
+// that a wavefront can pause between steps: the sparse-point kernels below run
+// their lanes in lock-step and, whenever some lanes have reached a dense cell,
+// scan each such cell with the whole wavefront (64 points per ballot) instead
+// of one lane looping over hundreds of points.
+struct Walk {
+  uint32_t node;  // next node to examine, kEnd when finished
+  int cur, end;   // pending bucket primitives [cur, end]; empty when cur > end
+  int64_t steps;  // remaining step budget (see traverse())
+};
+
+template <bool MASKED>
+__device__ __forceinline__ void walk_init(Walk& w, int m, int mask, bool on) {
+  w.cur = 1;
+  w.end = 0;
+  w.steps = 2 * int64_t(m) + 2;
+  if (!on || m <= 0 || (MASKED && mask >= m - 1)) w.node = kEnd;
+  else w.node = m == 1 ? kLeaf : 0u;
+}
+
+__device__ __forceinline__ bool walk_done(const Walk& w) { return w.node == kEnd && w.cur > w.end; }
+
+template <int D, bool MASKED>
+__device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, const Query& q, float eps2, int mask,
+                                         uint32_t* info) {
+  if (w.cur <= w.end) return w.cur++;
+  const uint32_t node = w.node;
+  if (node == kEnd) return -1;
+  if (--w.steps < 0) {
+    atomicOr(info, kInternalBit);
+    w.node = kEnd;
+    return -1;
+  }
+  if (node & kLeaf) {
+    const int l = static_cast<int>(node & ~kLeaf);
+    if (l >= m) {
+      atomicOr(info, kInternalBit);
+      w.node = kEnd;
+      return -1;
+    }
+    w.node = static_cast<uint32_t>(t.leaf_rope[l]);
+    return l;
+  }
+  if (node >= static_cast<uint32_t>(m - 1)) {
+    atomicOr(info, kInternalBit);
+    w.node = kEnd;
+    return -1;
+  }
+  const float4 a = t.node_a[node];
+  const float4 b = t.node_b[node];
+  if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > eps2) {
+    w.node = static_cast<uint32_t>(t.rope[node]);
+    return -1;
+  }
+  const int k = static_cast<int>(node);
+  const int o = __float_as_int(a.w), g = __float_as_int(b.w);
+  const int first = o < k ? o : k, last = o > k ? o : k;
+  if (first < 0 || last >= m || g < first || g >= last) {
+    atomicOr(info, kInternalBit);
+    w.node = kEnd;
+    return -1;
+  }
+  if (last - first < t.leaf_size) {
+    w.cur = (MASKED && first <= mask) ? mask + 1 : first;
+    w.end = last;
+    w.node = static_cast<uint32_t>(t.rope[node]);
+    return w.cur <= w.end ? w.cur++ : -1;
+  }
+  if (MASKED && g <= mask)
+    w.node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+  else
+    w.node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+  return -1;
+}
+
+// Number of points of the cell [s, s+c) within eps of p, counted 64 at a time
+// until at least `want` (whole wavefront).
+template <int D>
+__device__ __forceinline__ int cell_count_near(const float* __restrict__ xs, int64_t n, int s, int c, float px,
+                                               float py, float pz, float eps2, int want) {
+  const int lane = lane_id();
+  int found = 0;
+  for (int base = 0; base < c && found < want; base += 64) {
+    bool h = false;
+    if (base + lane < c) {
+      const int64_t j = s + base + lane;
+      h = dist2v<D>(xs[j], xs[n + j], D == 3 ? xs[2 * n + j] : 0.0f, px, py, pz) <= eps2;
+    }
+    found += __popcll(ballot(h));
+  }
+  return found;
+}
+
+// Core pass for points outside dense cells (one lane per point primitive).
 template <int D>
 __global__ void k_core_dbx(TravArgs a) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= a.n) return;
-  if (a.core[i]) return;  // points of dense cells are core by construction
+  const int m = tree_m(a.t);
+  const int lane = lane_id();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool mine = p < m && a.prim_cnt[p] > 0;  // dense cells are core by construction
+  const int i = mine ? a.prim_start[p] : 0;
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
   const int need = a.min_pts;
   int cnt = 0;
-  traverse<D, false>(a.t, tree_m(a.t), q, eps2, 0, a.info, [&](int p) {
-    int c = a.prim_cnt[p], s = a.prim_start[p];
-    if (c > 0) {
-      if (near<D>(a.xs, a.n, s, q, eps2)) return ++cnt >= need;
-      return false;
+  Walk w;
+  walk_init<false>(w, m, 0, mine);
+  bool active = mine && !walk_done(w);
+  while (ballot(active)) {
+    int pend = -1;
+    if (active) {
+      const int r = walk_step<D, false>(w, a.t, m, q, eps2, 0, a.info);
+      if (r >= 0) {
+        const int c = a.prim_cnt[r], s = a.prim_start[r];
+        if (c > 0) cnt += near<D>(a.xs, a.n, s, q, eps2) ? 1 : 0;
+        else if (box_near<D>(a, r, q, eps2)) pend = r;
+      }
     }
-    if (!box_near<D>(a, p, q, eps2)) return false;
-    for (int j = s; j < s - c; ++j)
-      if (near<D>(a.xs, a.n, j, q, eps2) && ++cnt >= need) return true;
-    return false;
-  });
-  a.core[i] = cnt >= need ? 1 : 0;
+    for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
+      const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+      const int r = __shfl(pend, L);
+      const int want = need - __shfl(cnt, L);
+      const int found = cell_count_near<D>(a.xs, a.n, a.prim_start[r], -a.prim_cnt[r], __shfl(q.x, L),
+                                           __shfl(q.y, L), __shfl(q.z, L), eps2, want);
+      if (lane == L) cnt += found;
+    }
+    if (active && (cnt >= need || walk_done(w))) active = false;
+  }
+  if (mine) a.core[i] = cnt >= need ? 1 : 0;
 }
 
+// Main phase, points outside dense cells: pairs with primitives above their own.
 template <int D, bool ALL_CORE, bool FIRST>
-__global__ void k_main_dbx(TravArgs a) {
-  int64_t i64 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i64 >= a.n) return;
-  const int i = static_cast<int>(i64);
-  const bool ci = ALL_CORE || a.core[i];
-  if (!FIRST && !ci) return;
+__global__ void k_main_dbx_points(TravArgs a) {
+  const int m = tree_m(a.t);
+  const int lane = lane_id();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool pt = p < m && a.prim_cnt[p] > 0;
+  const int i = pt ? a.prim_start[p] : 0;
+  const bool ci = pt && (ALL_CORE || a.core[i]);
+  const bool mine = pt && (FIRST || ci);
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
   int* labels = a.labels;
-  int root = labels[i];  // a dense cell's points start out pointing at its first point
-  const int own = a.prim_of[i];
-  traverse<D, true>(a.t, tree_m(a.t), q, eps2, own, a.info, [&](int p) {
-    int c = a.prim_cnt[p], s = a.prim_start[p];
-    if (c > 0) {
-      const int j = s;
-      if (!near<D>(a.xs, a.n, j, q, eps2)) return false;
-      const bool cj = ALL_CORE || a.core[j];
-      if (ci && cj) {
-        if (!known_same_set(labels, j, root)) root = uf_union(labels, root, j, a.info);
-        return false;
+  int root = i;
+  Walk w;
+  walk_init<true>(w, m, p, mine);
+  bool active = mine && !walk_done(w);
+  while (ballot(active)) {
+    int pend = -1;
+    if (active) {
+      const int r = walk_step<D, true>(w, a.t, m, q, eps2, p, a.info);
+      if (r >= 0) {
+        const int c = a.prim_cnt[r], s = a.prim_start[r];
+        if (c > 0) {
+          if (near<D>(a.xs, a.n, s, q, eps2)) {
+            const bool cj = ALL_CORE || a.core[s];
+            if (ci && cj) {
+              if (!known_same_set(labels, s, root)) root = uf_union(labels, root, s, a.info);
+            } else if (FIRST && ci) {
+              uf_claim(labels, s, i);
+            } else if (FIRST && cj) {
+              uf_claim(labels, i, s);
+              active = false;  // i is a member now (by this or an earlier claim)
+            }
+          }
+        } else if (box_near<D>(a, r, q, eps2) && !(ci && known_same_set(labels, s, root))) {
+          pend = r;
+        }
       }
-      if (FIRST) {
+    }
+    // a dense cell: one of its points within eps suffices
+    for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
+      const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+      const int r = __shfl(pend, L);
+      const int s = a.prim_start[r];
+      const bool hit = cell_reaches_point<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
+                                             __shfl(q.z, L), eps2);
+      if (lane == L && hit) {
         if (ci) {
-          uf_claim(labels, j, i);
-          return false;
-        }
-        if (cj) {
-          uf_claim(labels, i, j);
-          return true;
+          root = uf_union(labels, root, s, a.info);
+        } else if (FIRST) {
+          uf_claim(labels, i, s);
+          active = false;
         }
       }
-      return false;
     }
-    // a dense cell: one point within eps suffices (its points are all core and
-    // already share one set)
-    if (!box_near<D>(a, p, q, eps2)) return false;
-    if (ci && known_same_set(labels, s, root)) return false;
-    for (int j = s; j < s - c; ++j) {
-      if (!near<D>(a.xs, a.n, j, q, eps2)) continue;
-      if (ci) {
-        root = uf_union(labels, root, s, a.info);
-        return false;
-      }
-      if (FIRST) {
-        uf_claim(labels, i, s);
-        return true;
-      }
-      return false;
-    }
-    return false;
-  });
+    if (active && walk_done(w)) active = false;
+  }
 }
 
+// Main phase, dense cells: one wavefront per cell A walks the tree once with
+// A's box, over primitives above A; a dense neighbour B joins A's set if some
+// pair is within eps, a core point if some point of A reaches it, and (first-
+// claim mode) a non-core point is claimed the same way.
+template <int D, bool ALL_CORE, bool FIRST>
+__global__ void k_main_dbx_cells(TravArgs a) {
+  const int m = tree_m(a.t);
+  const int nd = *a.d_ndense;
+  const int lane = lane_id();
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const float eps2 = a.eps2;
+  int* labels = a.labels;
+  for (int w = wave; w < nd; w += nwaves) {
+    const int A = a.dense_list[w];
+    const int sa = a.prim_start[A], na = -a.prim_cnt[A];
+    const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
+    const float alo[3] = {alo4.x, alo4.y, alo4.z}, ahi[3] = {ahi4.x, ahi4.y, ahi4.z};
+    int root = sa;
+    traverse_box<D>(a.t, m, alo, ahi, eps2, A, a.info, [&](int r) {
+      const int c = a.prim_cnt[r], s = a.prim_start[r];
+      if (c > 0) {
+        const int j = s;
+        const float px = a.xs[j], py = a.xs[a.n + j], pz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
+        if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) return false;
+        const bool cj = ALL_CORE || a.core[j];
+        if (cj) {
+          if (known_same_set(labels, j, root)) return false;
+          if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2)) {
+            int nr = 0;
+            if (lane == 0) nr = uf_union(labels, root, j, a.info);
+            root = __shfl(nr, 0);
+          }
+        } else if (FIRST) {
+          if (labels[j] != j) return false;
+          if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2) && lane == 0) uf_claim(labels, j, sa);
+        }
+        return false;
+      }
+      const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
+      if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) return false;
+      if (known_same_set(labels, s, root)) return false;
+      if (cells_touch<D>(a.xs, a.n, sa, na, s, -c, blo, bhi, eps2)) {
+        int nr = 0;
+        if (lane == 0) nr = uf_union(labels, root, s, a.info);
+        root = __shfl(nr, 0);
+      }
+      return false;
+    });
+  }
+}
+
+// Canonical border pass for non-core points (all outside dense cells).
 template <int D>
 __global__ void k_border_dbx(TravArgs a) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i >= a.n) return;
-  if (a.core[i]) return;
+  const int m = tree_m(a.t);
+  const int lane = lane_id();
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool pt = p < m && a.prim_cnt[p] > 0;
+  const int i = pt ? a.prim_start[p] : 0;
+  const bool mine = pt && !a.core[i];
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
   int best = 0x7fffffff;
-  traverse<D, false>(a.t, tree_m(a.t), q, eps2, 0, a.info, [&](int p) {
-    int c = a.prim_cnt[p], s = a.prim_start[p];
-    if (c > 0) {
-      if (!a.core[s] || !near<D>(a.xs, a.n, s, q, eps2)) return false;
-      int id = a.cid[a.labels[s]];
-      best = id < best ? id : best;
-      return best == 0;
-    }
-    if (!box_near<D>(a, p, q, eps2)) return false;
-    int id = a.cid[a.labels[s]];
-    if (id >= best) return false;
-    for (int j = s; j < s - c; ++j) {
-      if (near<D>(a.xs, a.n, j, q, eps2)) {
-        best = id;
-        return best == 0;
+  Walk w;
+  walk_init<false>(w, m, 0, mine);
+  bool active = mine && !walk_done(w);
+  while (ballot(active)) {
+    int pend = -1;
+    if (active) {
+      const int r = walk_step<D, false>(w, a.t, m, q, eps2, 0, a.info);
+      if (r >= 0) {
+        const int c = a.prim_cnt[r], s = a.prim_start[r];
+        if (c > 0) {
+          if (a.core[s] && near<D>(a.xs, a.n, s, q, eps2)) {
+            const int id = a.cid[a.labels[s]];
+            best = id < best ? id : best;
+          }
+        } else if (box_near<D>(a, r, q, eps2) && a.cid[a.labels[s]] < best) {
+          pend = r;
+        }
       }
     }
-    return false;
-  });
-  a.border[i] = best == 0x7fffffff ? -1 : best;
+    for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
+      const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+      const int r = __shfl(pend, L);
+      const int s = a.prim_start[r];
+      const bool hit = cell_reaches_point<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
+                                             __shfl(q.z, L), eps2);
+      if (lane == L && hit) {
+        const int id = a.cid[a.labels[s]];
+        best = id < best ? id : best;
+      }
+    }
+    if (active && (best == 0 || walk_done(w))) active = false;
+  }
+  if (mine) a.border[i] = best == 0x7fffffff ? -1 : best;
 }
 
 inline dim3 grid_of(int64_t n, int block) { return dim3(static_cast<unsigned>(ceil_div(n, block))); }
@@ -317,8 +602,12 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
 template <int D, bool ALL, bool FIRST>
 static void main_t(const TravArgs& a, bool densebox, hipStream_t s) {
   dim3 g = grid_of(a.n, a.block), b(a.block);
-  if (densebox) hipLaunchKernelGGL((k_main_dbx<D, ALL, FIRST>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_main_fdb<D, ALL, FIRST>), g, b, 0, s, a);
+  if (densebox) {
+    hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST>), dim3(2048), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_main_fdb<D, ALL, FIRST>), g, b, 0, s, a);
+  }
 }
 
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, hipStream_t s) {
