@@ -25,8 +25,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-VALU_PEAK_TOPS = 78.6          # fp32 vector lane-ops/s (256 CU x 4 SIMD x 16 lanes x 2 (dual-issue/packed) x 2.4 GHz)
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+# fp32 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s for the plain
+# (non-packed, non-fused) v_sub/v_mul/v_add/v_cmp the neighbour test compiles to; packed
+# fp32 would double it (78.6 T) but is disabled in this build. The published 157.3 TFLOP/s
+# counts a packed FMA as 4 flops.
+ALU_PEAK_TOPS = 39.3
+PRED_OPS_3D = 9         # 3 sub, 3 mul, 2 add, 1 compare per neighbour test
+
+P_BYTES = 12            # one 3D float32 point
+NODE_BYTES = 36         # internal node: box + range end + split (32 B) + escape link (4 B)
+I_BYTES, F_BYTES = 4, 1
 
 
 def log(*a):
@@ -45,6 +54,8 @@ def parse():
                     help="volume fraction of the spatial window the CPU oracle clusters")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (PMC calibration)")
     return ap.parse_args()
 
 
@@ -69,7 +80,85 @@ def time_algo(fdb, h, pts, eps, min_pts, algo, steps, warmup, leaf, block):
     h.set_timing(False)
     ms = (t1 - t0) * 1e3 / steps
     per_call = {k2: v / max(calls, 1) for k2, v in stages.items()}
-    return dict(ms=ms, k=k, stages=per_call, info=h.last_info())
+    return dict(ms=ms, k=k, stages=per_call, info=h.last_info(), sizes=h.last_counts())
+
+
+def algorithmic_bytes(stage, n, sizes):
+    """Compulsory HBM bytes of one launch of a single-kernel stage: every input read
+    once and every output written once (cache reuse is free)."""
+    m = sizes["prims"]                      # BVH primitives
+    c = sizes["dense_cells"]
+    ns = m - c if c else n                  # points outside dense cells (all points for FDbscan)
+    tree = max(m - 1, 0) * NODE_BYTES + m * I_BYTES                 # nodes + leaf escape links
+    prims = m * (2 * I_BYTES) + c * 32 if c else 0                  # DenseBox primitive records
+    pts = n * P_BYTES                                               # every point once
+    if stage == "core":        # queries (points outside dense cells) count neighbours, write a flag
+        return pts + tree + prims + ns * F_BYTES
+    if stage == "main_points":  # queries read flag + label, candidates' flags and labels, label writes
+        return pts + tree + prims + n * (F_BYTES + I_BYTES) + ns * I_BYTES
+    if stage == "main_cells":  # dense-cell queries
+        return pts + tree + prims + n * (F_BYTES + I_BYTES) + c * I_BYTES
+    if stage == "main":        # FDbscan fused traversal
+        return pts + tree + n * (F_BYTES + I_BYTES) + n * I_BYTES
+    if stage == "border":      # non-core queries: candidates' flags, labels and cluster ids
+        return pts + tree + prims + n * (F_BYTES + 2 * I_BYTES) + ns * I_BYTES
+    if stage == "scatter":     # labels, flags, permutation, ids in; labels + flags out
+        return n * (I_BYTES + F_BYTES + I_BYTES + I_BYTES + I_BYTES) + n * (I_BYTES + F_BYTES)
+    if stage == "finalize":
+        return n * 2 * I_BYTES
+    return None
+
+
+def roofline(algo, stages, n, sizes, golden, traffic_db):
+    single = ["core", "main", "main_cells", "main_points", "border", "scatter", "finalize"]
+    cand = {k: v for k, v in stages.items() if k in single}
+    if not cand:
+        return None
+    dom = max(cand, key=cand.get)
+    ms = cand[dom]
+    if algo == "fdbscan" and dom in ("main", "core") and golden and "sum_neighbors" in golden:
+        # ALU bound: one neighbour test per pair (each pair once in the masked main phase;
+        # up to minPts tests per point in the core phase)
+        tests = (golden["sum_neighbors"] - n) // 2 if dom == "main" else golden["sum_min_neighbors_minpts"]
+        ach = tests * PRED_OPS_3D / (ms / 1e3) / 1e12
+        out = {"bound": "alu", "achieved": round(ach, 3), "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+               "frac": round(ach / ALU_PEAK_TOPS, 4), "kernel": dom, "ms": round(ms, 4),
+               "work": f"{tests} neighbour tests x {PRED_OPS_3D} fp32 ops"}
+    else:
+        b = algorithmic_bytes(dom, n, sizes)
+        ach = b / (ms / 1e3) / 1e9
+        out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom, "ms": round(ms, 4), "alg_bytes": b}
+    t = (traffic_db or {}).get(f"{algo}:{dom}")
+    out["traffic"] = t
+    return out
+
+
+def source_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2103_05162_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE), scaled by a
+    copy-kernel calibration; only valid while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    db = json.load(open(path))
+    if db.get("src_hash") != source_hash():
+        return None
+    return db.get("kernels")
+
+
+def load_golden(name):
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    return json.load(open(path)) if os.path.exists(path) else None
 
 
 def cpu_baseline(points, eps, min_pts, frac):
@@ -98,6 +187,14 @@ def main():
     w = workload("c3_dense3d_8m", args.scale)
     log(f"[bench] workload {w.name}: n={w.n} eps={w.eps} minPts={w.min_pts}")
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
     pts = torch.from_numpy(w.points).to(dev)
     h = fdb.Handle(0)
     algos = ["densebox", "fdbscan"] if args.algo == "both" else [args.algo]
@@ -112,6 +209,14 @@ def main():
             log(f"    {st:12s} {v:9.3f} ms")
     head = algos[0]
     ms = res[head]["ms"]
+    golden = load_golden("c3_dense3d_8m") if args.scale == 1.0 else None
+    traffic_db = load_traffic()
+    for a in algos:
+        res[a]["roofline"] = roofline(a, res[a]["stages"], w.n, res[a]["sizes"], golden, traffic_db)
+    if golden is not None:
+        for a in algos:
+            if res[a]["k"] != golden["num_clusters"]:
+                log(f"[bench] WARNING: {a} K={res[a]['k']} but the oracle's K={golden['num_clusters']}")
     out = {
         "metric": "Mpts/s clustered (3D, 8M pts)",
         "value": round(w.n / (ms / 1e3) / 1e6, 3),
@@ -128,11 +233,14 @@ def main():
         "config": {"workload": f"{w.name}: {w.n} 3D float32 points, 500 Gaussian clumps (sigma 5e-4, 80%) "
                                f"+ uniform background, eps={w.eps:g}, minPts={w.min_pts}",
                    "algo": head, "num_clusters": res[head]["k"]},
+        "roofline": res[head]["roofline"],
         "stages_ms": {a: {k2: round(v, 4) for k2, v in res[a]["stages"].items()} for a in algos},
         "per_algo": {a: {"ms_per_step": round(res[a]["ms"], 4),
                          "mpts_per_s": round(w.n / (res[a]["ms"] / 1e3) / 1e6, 3),
                          "mfeatures_per_s": round(3 * w.n / (res[a]["ms"] / 1e3) / 1e6, 3),
-                         "num_clusters": res[a]["k"]} for a in algos},
+                         "num_clusters": res[a]["k"], "sizes": res[a]["sizes"],
+                         "roofline": res[a]["roofline"]} for a in algos},
+        "src_hash": source_hash(),
     }
     if not args.no_cpu_baseline:
         log(f"[bench] cpu oracle on a {args.cpu_window:g} window")

@@ -124,6 +124,12 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
 /* Wait for the stream of the last fdb_dbscan call on h and return its FDB_INFO_* bits. */
 fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info);
 
+/* Wait for the stream of the last fdb_dbscan call on h and report its sizes, for
+   cost models: h_counts[0] = K (clusters), [1] = non-empty grid cells, [2] = dense
+   cells, [3] = BVH primitives (dense cells + points outside them; n for FDbscan).
+   Entries 1-2 are 0 for FDbscan. The workspace of that call must still be alive. */
+fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts);
+
 /* Per-stage GPU timing. With timing enabled, fdb_dbscan records a HIP event pair
    around every stage on the call's stream; fdb_stage_times waits for the last
    call and reports up to `max` stages: names (static strings) and milliseconds,

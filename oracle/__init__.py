@@ -57,6 +57,9 @@ def _load():
                                             ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                                             ctypes.c_int, ctypes.c_int]
         lib.oracle_check_border.restype = ctypes.c_int64
+        lib.oracle_neighbors_of.argtypes = [fp, ctypes.c_int64, ctypes.c_int, ctypes.c_float, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]
+        lib.oracle_neighbors_of.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -133,3 +136,17 @@ def check_border(points, eps: float, is_core, labels, method: str = "auto", thre
     if bad < 0:
         raise RuntimeError(f"oracle_check_border failed ({bad})")
     return int(bad)
+
+
+def neighbors_of(points, eps: float, i: int, cap: int = 1 << 20) -> np.ndarray:
+    """Indices j (increasing) with point i within eps of point j, by brute force over all points."""
+    pts = _as_points(points)
+    n, d = pts.shape
+    out = np.empty(cap, dtype=np.int64)
+    k = _load().oracle_neighbors_of(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, d, ctypes.c_float(eps),
+                                    int(i), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap)
+    if k < 0:
+        raise RuntimeError("oracle_neighbors_of failed")
+    if k > cap:
+        return neighbors_of(points, eps, i, cap=int(k))
+    return out[:k].copy()

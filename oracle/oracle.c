@@ -392,3 +392,23 @@ int64_t oracle_check_border(const float *pts, int64_t n, int dim, float eps, con
     grid_free(&g);
     return bad;
 }
+
+/*
+ * Brute force over all n points for one query: the indices j with the query
+ * within eps of point j (query itself included), in increasing order.
+ * Writes at most cap indices; returns the full count.
+ */
+int64_t oracle_neighbors_of(const float *pts, int64_t n, int dim, float eps, int64_t i, int64_t *out,
+                            int64_t cap)
+{
+    if (n < 0 || i < 0 || i >= n || (dim != 2 && dim != 3)) return -1;
+    const float eps2 = oracle_eps2(eps);
+    const float *p = pts + i * dim;
+    int64_t k = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!oracle_pred(p, pts + j * dim, dim, eps2)) continue;
+        if (k < cap) out[k] = j;
+        ++k;
+    }
+    return k;
+}

@@ -58,6 +58,8 @@ def load() -> ctypes.CDLL:
     lib.fdb_dbscan.restype = ctypes.c_int
     lib.fdb_last_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.fdb_last_info.restype = ctypes.c_int
+    lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.fdb_last_counts.restype = ctypes.c_int
     lib.fdb_set_timing.argtypes = [vp, i32]
     lib.fdb_set_timing.restype = ctypes.c_int
     lib.fdb_stage_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -128,6 +130,12 @@ class Handle:
         v = ctypes.c_uint32(0)
         _check(self._lib.fdb_last_info(self.ptr, ctypes.byref(v)), "fdb_last_info")
         return int(v.value)
+
+    def last_counts(self) -> dict:
+        """Sizes of the last call: clusters, grid cells, dense cells, BVH primitives."""
+        v = (ctypes.c_int64 * 4)()
+        _check(self._lib.fdb_last_counts(self.ptr, v), "fdb_last_counts")
+        return {"clusters": int(v[0]), "cells": int(v[1]), "dense_cells": int(v[2]), "prims": int(v[3])}
 
     def set_timing(self, enable: bool) -> None:
         _check(self._lib.fdb_set_timing(self.ptr, 1 if enable else 0), "fdb_set_timing")

@@ -101,6 +101,9 @@ struct fdb_handle {
   uint32_t* h_pinned = nullptr;  // 16 words of pinned host memory for read-backs
   uint32_t host_info = 0;
   hipStream_t last_stream = nullptr;
+  const int* last_misc = nullptr;  // device counters of the last call (in its workspace)
+  bool last_densebox = false;
+  int64_t last_n = 0;
   bool timing = false;
   int32_t timed_calls = 0;
   std::vector<fdb::StageRec> pending;  // event pairs of the calls since the last collection
@@ -278,6 +281,27 @@ fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info) {
   return FDB_OK;
 }
 
+fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts) {
+  if (!h || !h_counts) return FDB_ERR_INVALID;
+  for (int k = 0; k < 4; ++k) h_counts[k] = 0;
+  if (!h->last_misc) return FDB_OK;
+  DeviceGuard g(h->device);
+  if (hipMemcpyAsync(h->h_pinned, h->last_misc, 5 * sizeof(int), hipMemcpyDeviceToHost, h->last_stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->last_stream) != hipSuccess)
+    return FDB_ERR_HIP;
+  const int32_t* v = reinterpret_cast<const int32_t*>(h->h_pinned);
+  h_counts[0] = v[fdb::kMiscNumClusters];
+  if (h->last_densebox) {
+    h_counts[1] = v[fdb::kMiscNumCells];
+    h_counts[2] = v[fdb::kMiscNumDense];
+    h_counts[3] = v[fdb::kMiscNumPrims];
+  } else {
+    h_counts[3] = h->last_n;
+  }
+  return FDB_OK;
+}
+
 fdb_status fdb_set_timing(fdb_handle* h, int32_t enable) {
   if (!h) return FDB_ERR_INVALID;
   DeviceGuard g(h->device);
@@ -360,6 +384,9 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   uint8_t* core = at<uint8_t>(ws, plan.core);
 
   st.mark("bounds");
+  h->last_misc = misc;
+  h->last_densebox = false;
+  h->last_n = n;
   fill_u32(h->d_info, 0, 1, s);
   fill_u32(bounds, 0xffffffffu, 4, s);
   fill_u32(bounds + 4, 0u, 4, s);
@@ -413,6 +440,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.xs = xs;
   ta.n = n;
   ta.eps2 = eps2;
+  ta.packet_ext2 = 4.0f * eps2;  // group extent <= 2 eps
+  ta.packet_leaf = 32;
   ta.min_pts = min_pts;
   ta.labels = lab;
   ta.core = core;
@@ -426,6 +455,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.t.leaf_rope = at<int>(ws, plan.leaf_rope);
   ta.t.leaf_size = leaf;
 
+  h->last_densebox = densebox;
   if (densebox) {
     st.mark("cell_keys");
     launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], s);
@@ -481,8 +511,15 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     st.mark("core");
     launch_core(ta, dim, densebox, s);
   }
-  st.mark("main");
-  launch_main(ta, dim, densebox, all_core, first_border && !all_core, s);
+  if (densebox) {
+    st.mark("main_cells");
+    launch_main(ta, dim, true, all_core, first_border && !all_core, 1, s);
+    st.mark("main_points");
+    launch_main(ta, dim, true, all_core, first_border && !all_core, 2, s);
+  } else {
+    st.mark("main");
+    launch_main(ta, dim, false, all_core, first_border && !all_core, 0, s);
+  }
   st.mark("finalize");
   launch_finalize(lab, n, h->d_info, s);
   if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);

@@ -107,6 +107,8 @@ struct TravArgs {
   const float* xs;  // sorted SoA coordinates: x[n], y[n], z[n]
   int64_t n;
   float eps2;
+  float packet_ext2;  // a wavefront walks as one packet if its queries' box is at most this (squared extent)
+  int packet_leaf;    // bucket size of packet walks (<= 64: a bucket is loaded one point per lane)
   int min_pts;
   int* labels;
   uint8_t* core;
@@ -124,7 +126,8 @@ struct TravArgs {
   int block;
 };
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
-void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, hipStream_t s);
+void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
+                 hipStream_t s);
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);
 
 // k_label.hip

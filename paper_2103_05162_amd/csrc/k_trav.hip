@@ -101,12 +101,18 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Query& 
 }
 
 // True only if `root` is an ancestor of x within a few plain-load hops (then x
-// already is in root's set: sets only grow). False means "unknown".
-__device__ __forceinline__ bool known_same_set(const int* __restrict__ labels, int x, int root) {
+// already is in root's set: sets only grow). False means "unknown". When the
+// chain had intermediate links, x is re-pointed straight at root (an ancestor,
+// so the store is safe however it races) and the next check is one load.
+__device__ __forceinline__ bool known_same_set(int* labels, int x, int root) {
+  const int x0 = x;
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     int p = labels[x];
-    if (p == root) return true;
+    if (p == root) {
+      if (h > 0) labels[x0] = root;
+      return true;
+    }
     if (p == x) return false;
     x = p;
   }
@@ -114,6 +120,67 @@ __device__ __forceinline__ bool known_same_set(const int* __restrict__ labels, i
 }
 
 __device__ __forceinline__ int tree_m(const TreeView& t) { return t.d_m ? *t.d_m : t.m_cap; }
+
+// Wave-uniform walk for a box query (every point of box [lo,hi]), masked like
+// traverse(): visit(first, last) is called with the same primitive range on
+// every lane, for each bucket (a subtree of at most leaf_size primitives, cut
+// to primitives above the mask) and each single leaf the walk reaches.
+template <int D, typename F>
+__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const float* lo, const float* hi, float eps2,
+                                             int mask, int leaf_size, uint32_t* info, F&& visit) {
+  if (m <= 0 || mask >= m - 1) return;
+  uint32_t node = m == 1 ? kLeaf : 0u;
+  int64_t steps = 0;
+  const int64_t max_steps = 2 * int64_t(m) + 2;
+  while (node != kEnd) {
+    node = __builtin_amdgcn_readfirstlane(node);
+    if (++steps > max_steps) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (node & kLeaf) {
+      int l = static_cast<int>(node & ~kLeaf);
+      if (l >= m) {
+        atomicOr(info, kInternalBit);
+        return;
+      }
+      if (visit(l, l)) return;
+      node = static_cast<uint32_t>(t.leaf_rope[l]);
+      continue;
+    }
+    if (node >= static_cast<uint32_t>(m - 1)) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    float4 na = t.node_a[node];
+    float4 nb = t.node_b[node];
+    if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > eps2) {
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    int k = static_cast<int>(node);
+    int o = __float_as_int(na.w), g = __float_as_int(nb.w);
+    int first = o < k ? o : k, last = o > k ? o : k;
+    if (first < 0 || last >= m || g < first || g >= last) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (last - first < leaf_size) {
+      int s = first <= mask ? mask + 1 : first;
+      if (s <= last && visit(s, last)) return;
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    if (g <= mask)
+      node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+    else
+      node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+  }
+}
+
+__device__ __forceinline__ float readlane_f(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
 
 // ---------------------------------------------------------------- FDbscan ----
 
@@ -132,35 +199,99 @@ __global__ void k_core_fdb(TravArgs a) {
   a.core[i] = cnt >= need ? 1 : 0;
 }
 
+// Fused main phase. A wavefront whose 64 queries (consecutive in Morton order)
+// lie within a small box walks the tree once for the whole group ("packet"):
+// each candidate point is loaded once for all lanes and each lane tests it
+// against its own query (and j > i, so every pair is still seen once). A
+// candidate already in the lane's set needs no test: the union would change
+// nothing. Wavefronts whose queries are spread out walk per lane.
+template <int D, bool ALL_CORE, bool FIRST>
+__device__ __forceinline__ void main_pair(const TravArgs& a, int i, bool ci, int j, bool cj, int& root,
+                                          bool& done) {
+  int* labels = a.labels;
+  if (ci && cj) {
+    if (!known_same_set(labels, j, root)) root = uf_union(labels, root, j, a.info);
+    return;
+  }
+  if (FIRST) {
+    if (ci) {
+      uf_claim(labels, j, i);
+    } else if (cj) {
+      uf_claim(labels, i, j);
+      done = true;  // i is a member now (by this or an earlier claim)
+    }
+  }
+}
+
 template <int D, bool ALL_CORE, bool FIRST>
 __global__ void k_main_fdb(TravArgs a) {
-  int64_t i64 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  if (i64 >= a.n) return;
-  const int i = static_cast<int>(i64);
-  const bool ci = ALL_CORE || a.core[i];
-  if (!FIRST && !ci) return;  // canonical mode: border points are settled later
+  const int64_t i64 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  const bool valid = i64 < a.n;
+  const int i = valid ? static_cast<int>(i64) : 0;
+  const bool ci = valid && (ALL_CORE || a.core[i]);
+  const bool mine = valid && (FIRST || ci);  // canonical mode: border points are settled later
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
+  const int m = tree_m(a.t);
   int* labels = a.labels;
   int root = i;
-  traverse<D, true>(a.t, tree_m(a.t), q, eps2, i, a.info, [&](int j) {
+  bool done = !mine;
+
+  // group box of this wavefront's queries
+  float lo[3], hi[3];
+  lo[0] = mine ? q.x : INFINITY; hi[0] = mine ? q.x : -INFINITY;
+  lo[1] = mine ? q.y : INFINITY; hi[1] = mine ? q.y : -INFINITY;
+  lo[2] = mine ? q.z : INFINITY; hi[2] = mine ? q.z : -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+    }
+  const uint64_t any_mine = ballot(mine);
+  if (!any_mine) return;
+  float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
+  if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
+  const bool packet = ext * ext <= a.packet_ext2;
+
+  if (packet) {
+    const int i0 = __shfl(i, __ffsll(static_cast<unsigned long long>(any_mine)) - 1);
+    const int lane = lane_id();
+    traverse_box<D>(a.t, m, lo, hi, eps2, i0, a.packet_leaf, a.info, [&](int s, int e) {
+      // the lanes load the bucket's points once; each is then broadcast to all
+      const int cnt = e - s + 1;  // <= packet_leaf <= 64
+      float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+      int cc = 0, cl = 0;
+      if (lane < cnt) {
+        const int j = s + lane;
+        cx = a.xs[j];
+        cy = a.xs[a.n + j];
+        cz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
+        cc = (ALL_CORE || a.core[j]) ? 1 : 0;
+        cl = labels[j];
+      }
+      for (int k = 0; k < cnt; ++k) {
+        const int j = s + k;
+        const bool cj = __builtin_amdgcn_readlane(cc, k) != 0;
+        if (!FIRST && !cj) continue;
+        const int lj = __builtin_amdgcn_readlane(cl, k);
+        bool act = !done && j > i;
+        if (act && ci && cj && lj == root) act = false;  // already one set
+        if (!ballot(act)) continue;
+        const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
+        if (act && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2)
+          main_pair<D, ALL_CORE, FIRST>(a, i, ci, j, cj, root, done);
+      }
+      return false;
+    });
+    return;
+  }
+  if (!mine) return;
+  traverse<D, true>(a.t, m, q, eps2, i, a.info, [&](int j) {
     if (!near<D>(a.xs, a.n, j, q, eps2)) return false;
     const bool cj = ALL_CORE || a.core[j];
-    if (ci && cj) {
-      if (!known_same_set(labels, j, root)) root = uf_union(labels, root, j, a.info);
-      return false;
-    }
-    if (FIRST) {
-      if (ci) {
-        uf_claim(labels, j, i);
-        return false;
-      }
-      if (cj) {
-        uf_claim(labels, i, j);
-        return true;  // i is a member now (by this or an earlier claim)
-      }
-    }
-    return false;
+    main_pair<D, ALL_CORE, FIRST>(a, i, ci, j, cj, root, done);
+    return done;
   });
 }
 
@@ -192,62 +323,6 @@ template <int D>
 __device__ __forceinline__ bool box_near(const TravArgs& a, int p, const Query& q, float eps2) {
   float4 lo = a.prim_lo[p], hi = a.prim_hi[p];
   return box_dist2<D>(q.x, q.y, q.z, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= eps2;
-}
-
-// Wave-uniform walk for a box query (every point of box [lo,hi]), masked like
-// traverse(): visit(q) is called with the same q on every lane.
-template <int D, typename F>
-__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const float* lo, const float* hi, float eps2,
-                                             int mask, uint32_t* info, F&& visit) {
-  if (m <= 0 || mask >= m - 1) return;
-  uint32_t node = m == 1 ? kLeaf : 0u;
-  int64_t steps = 0;
-  const int64_t max_steps = 2 * int64_t(m) + 2;
-  while (node != kEnd) {
-    node = __builtin_amdgcn_readfirstlane(node);
-    if (++steps > max_steps) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    if (node & kLeaf) {
-      int l = static_cast<int>(node & ~kLeaf);
-      if (l >= m) {
-        atomicOr(info, kInternalBit);
-        return;
-      }
-      if (visit(l)) return;
-      node = static_cast<uint32_t>(t.leaf_rope[l]);
-      continue;
-    }
-    if (node >= static_cast<uint32_t>(m - 1)) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    float4 na = t.node_a[node];
-    float4 nb = t.node_b[node];
-    if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > eps2) {
-      node = static_cast<uint32_t>(t.rope[node]);
-      continue;
-    }
-    int k = static_cast<int>(node);
-    int o = __float_as_int(na.w), g = __float_as_int(nb.w);
-    int first = o < k ? o : k, last = o > k ? o : k;
-    if (first < 0 || last >= m || g < first || g >= last) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    if (last - first < t.leaf_size) {
-      int s = first <= mask ? mask + 1 : first;
-      for (int l = s; l <= last; ++l)
-        if (visit(l)) return;
-      node = static_cast<uint32_t>(t.rope[node]);
-      continue;
-    }
-    if (g <= mask)
-      node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
-    else
-      node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
-  }
 }
 
 // Is some point of the cell [sa, sa+na) within eps of p? (whole wavefront)
@@ -503,34 +578,36 @@ __global__ void k_main_dbx_cells(TravArgs a) {
     const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
     const float alo[3] = {alo4.x, alo4.y, alo4.z}, ahi[3] = {ahi4.x, ahi4.y, ahi4.z};
     int root = sa;
-    traverse_box<D>(a.t, m, alo, ahi, eps2, A, a.info, [&](int r) {
+    traverse_box<D>(a.t, m, alo, ahi, eps2, A, a.t.leaf_size, a.info, [&](int r0, int r1) {
+     for (int r = r0; r <= r1; ++r) {
       const int c = a.prim_cnt[r], s = a.prim_start[r];
       if (c > 0) {
         const int j = s;
         const float px = a.xs[j], py = a.xs[a.n + j], pz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
-        if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) return false;
+        if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) continue;
         const bool cj = ALL_CORE || a.core[j];
         if (cj) {
-          if (known_same_set(labels, j, root)) return false;
+          if (known_same_set(labels, j, root)) continue;
           if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2)) {
             int nr = 0;
             if (lane == 0) nr = uf_union(labels, root, j, a.info);
             root = __shfl(nr, 0);
           }
         } else if (FIRST) {
-          if (labels[j] != j) return false;
+          if (labels[j] != j) continue;
           if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2) && lane == 0) uf_claim(labels, j, sa);
         }
-        return false;
+        continue;
       }
       const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
-      if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) return false;
-      if (known_same_set(labels, s, root)) return false;
+      if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) continue;
+      if (known_same_set(labels, s, root)) continue;
       if (cells_touch<D>(a.xs, a.n, sa, na, s, -c, blo, bhi, eps2)) {
         int nr = 0;
         if (lane == 0) nr = uf_union(labels, root, s, a.info);
         root = __shfl(nr, 0);
       }
+     }
       return false;
     });
   }
@@ -599,27 +676,29 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
   }
 }
 
+// part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
 template <int D, bool ALL, bool FIRST>
-static void main_t(const TravArgs& a, bool densebox, hipStream_t s) {
+static void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
   dim3 g = grid_of(a.n, a.block), b(a.block);
   if (densebox) {
-    hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST>), dim3(2048), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST>), g, b, 0, s, a);
+    if (part != 2) hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST>), dim3(2048), dim3(256), 0, s, a);
+    if (part != 1) hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST>), g, b, 0, s, a);
   } else {
     hipLaunchKernelGGL((k_main_fdb<D, ALL, FIRST>), g, b, 0, s, a);
   }
 }
 
-void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, hipStream_t s) {
+void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
+                 hipStream_t s) {
   if (a.n <= 0) return;
   if (dim == 3) {
-    if (all_core) main_t<3, true, false>(a, densebox, s);
-    else if (first_border) main_t<3, false, true>(a, densebox, s);
-    else main_t<3, false, false>(a, densebox, s);
+    if (all_core) main_t<3, true, false>(a, densebox, part, s);
+    else if (first_border) main_t<3, false, true>(a, densebox, part, s);
+    else main_t<3, false, false>(a, densebox, part, s);
   } else {
-    if (all_core) main_t<2, true, false>(a, densebox, s);
-    else if (first_border) main_t<2, false, true>(a, densebox, s);
-    else main_t<2, false, false>(a, densebox, s);
+    if (all_core) main_t<2, true, false>(a, densebox, part, s);
+    else if (first_border) main_t<2, false, true>(a, densebox, part, s);
+    else main_t<2, false, false>(a, densebox, part, s);
   }
 }
 

@@ -263,3 +263,13 @@ def test_golden_summaries_match():
     assert k == g["num_clusters"]
     assert int(core.sum()) == g["num_core"]
     assert int((labels == -1).sum()) == g["num_noise"]
+
+
+def test_neighbors_of_matches_counts():
+    rng = np.random.default_rng(41)
+    pts = rng.uniform(0, 1, size=(3000, 3)).astype(np.float32)
+    counts = oracle.neighbor_counts(pts, 0.08, "brute")
+    for i in (0, 17, 2999):
+        nb = oracle.neighbors_of(pts, 0.08, i)
+        assert len(nb) == counts[i] and i in nb
+        assert all(oracle.pred(pts[i], pts[j], 0.08) for j in nb)
