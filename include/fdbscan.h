@@ -139,6 +139,16 @@ fdb_status fdb_set_timing(fdb_handle* h, int32_t enable);
 fdb_status fdb_stage_times(fdb_handle* h, int32_t max, const char** h_names, double* h_ms, int32_t* h_count,
                            int32_t* h_calls);
 
+/* Test hook (synchronous, allocates; not for production use): build the LBVH over m
+   sorted 64-bit keys h_keys (Karras' hierarchy, ties by index; Section 4.1), return
+   every internal node's split h_gamma[k] and other range end h_other[k] (k < m-1),
+   and walk it from the root with every box accepted, masked at `mask` as in the main
+   phase (Section 4.1, Figure 1: subtrees whose leaves are all <= mask are skipped;
+   mask = -1 walks everything). h_leaves[0..*h_num_leaves) receives the leaves reached,
+   in walk order (h_leaves holds m entries). m <= 2^24. */
+fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int32_t mask, int32_t leaf_size,
+                          int32_t* h_gamma, int32_t* h_other, int32_t* h_leaves, int32_t* h_num_leaves);
+
 /* Static description of a status code. */
 const char* fdb_status_string(fdb_status s);
 

@@ -60,6 +60,9 @@ def load() -> ctypes.CDLL:
     lib.fdb_last_info.restype = ctypes.c_int
     lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fdb_last_counts.restype = ctypes.c_int
+    pi32 = ctypes.POINTER(i32)
+    lib.fdb_debug_lbvh.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32, i32, i32, pi32, pi32, pi32, pi32]
+    lib.fdb_debug_lbvh.restype = ctypes.c_int
     lib.fdb_set_timing.argtypes = [vp, i32]
     lib.fdb_set_timing.restype = ctypes.c_int
     lib.fdb_stage_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -136,6 +139,21 @@ class Handle:
         v = (ctypes.c_int64 * 4)()
         _check(self._lib.fdb_last_counts(self.ptr, v), "fdb_last_counts")
         return {"clusters": int(v[0]), "cells": int(v[1]), "dense_cells": int(v[2]), "prims": int(v[3])}
+
+    def debug_lbvh(self, keys, mask: int = -1, leaf_size: int = 1):
+        """Test hook: (gamma, other, leaves reached by a walk masked at `mask`) for sorted keys."""
+        import numpy as np
+        k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+        m = int(k.size)
+        gamma = np.zeros(max(m - 1, 1), np.int32)
+        other = np.zeros(max(m - 1, 1), np.int32)
+        leaves = np.zeros(m, np.int32)
+        cnt = ctypes.c_int32(0)
+        p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        _check(self._lib.fdb_debug_lbvh(self.ptr, k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), m, int(mask),
+                                        int(leaf_size), p(gamma), p(other), p(leaves), ctypes.byref(cnt)),
+               "fdb_debug_lbvh")
+        return gamma[:m - 1], other[:m - 1], leaves[:min(cnt.value, m)]
 
     def set_timing(self, enable: bool) -> None:
         _check(self._lib.fdb_set_timing(self.ptr, 1 if enable else 0), "fdb_set_timing")

@@ -302,6 +302,61 @@ fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts) {
   return FDB_OK;
 }
 
+fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int32_t mask, int32_t leaf_size,
+                          int32_t* h_gamma, int32_t* h_other, int32_t* h_leaves, int32_t* h_num_leaves) {
+  using namespace fdb;
+  if (!h || !h_keys || m < 1 || m > (1 << 24) || mask < -1 || mask >= m || leaf_size < 1 || leaf_size > 1024 ||
+      !h_leaves || !h_num_leaves || (m > 1 && (!h_gamma || !h_other)))
+    return FDB_ERR_INVALID;
+  for (int32_t k = 1; k < m; ++k)
+    if (h_keys[k] < h_keys[k - 1]) return FDB_ERR_INVALID;
+  DeviceGuard g(h->device);
+  const size_t M = static_cast<size_t>(m);
+  void* buf = nullptr;
+  const size_t bytes = M * 8 + 3 * M * 4 + 2 * M * 16 + 2 * M * 4 + 2 * M * 4 + 3 * M * 4 + M * 4 + 256;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return FDB_ERR_NOMEM;
+  char* p = static_cast<char*>(buf);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(p); p += M * 8;
+  float* xs = reinterpret_cast<float*>(p); p += 3 * M * 4;
+  float4* na = reinterpret_cast<float4*>(p); p += M * 16;
+  float4* nb = reinterpret_cast<float4*>(p); p += M * 16;
+  int* rope = reinterpret_cast<int*>(p); p += M * 4;
+  int* lrope = reinterpret_cast<int*>(p); p += M * 4;
+  int* parent = reinterpret_cast<int*>(p); p += 2 * M * 4;
+  int* flags = reinterpret_cast<int*>(p); p += M * 4;
+  int* other = reinterpret_cast<int*>(p); p += M * 4;
+  int* gamma = reinterpret_cast<int*>(p); p += M * 4;
+  int* leaves = reinterpret_cast<int*>(p); p += M * 4;
+  int* count = reinterpret_cast<int*>(p);
+  fdb_status st = FDB_OK;
+  hipStream_t s = nullptr;
+  if (hipMemcpy(keys, h_keys, M * 8, hipMemcpyHostToDevice) != hipSuccess) st = FDB_ERR_HIP;
+  if (st == FDB_OK) {
+    fill_u32(reinterpret_cast<uint32_t*>(xs), 0, 3 * M, s);
+    fill_u32(h->d_info, 0, 1, s);
+    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
+               h->d_info, s);
+    TreeView t{na, nb, rope, lrope, m, nullptr, leaf_size};
+    launch_debug_walk(t, m, mask, leaves, count, m, h->d_info, s);
+    if (hipStreamSynchronize(s) != hipSuccess) st = FDB_ERR_HIP;
+  }
+  if (st == FDB_OK && m > 1 &&
+      (hipMemcpy(h_gamma, gamma, (M - 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+       hipMemcpy(h_other, other, (M - 1) * 4, hipMemcpyDeviceToHost) != hipSuccess))
+    st = FDB_ERR_HIP;
+  int32_t cnt = 0;
+  if (st == FDB_OK && hipMemcpy(&cnt, count, 4, hipMemcpyDeviceToHost) != hipSuccess) st = FDB_ERR_HIP;
+  if (st == FDB_OK && cnt > 0 &&
+      hipMemcpy(h_leaves, leaves, static_cast<size_t>(cnt < m ? cnt : m) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    st = FDB_ERR_HIP;
+  uint32_t info = 0;
+  if (st == FDB_OK && hipMemcpy(&info, h->d_info, 4, hipMemcpyDeviceToHost) != hipSuccess) st = FDB_ERR_HIP;
+  if (st == FDB_OK && (info & FDB_INFO_INTERNAL)) st = FDB_ERR_INTERNAL;
+  *h_num_leaves = cnt;
+  (void)hipFree(buf);
+  return st;
+}
+
 fdb_status fdb_set_timing(fdb_handle* h, int32_t enable) {
   if (!h) return FDB_ERR_INVALID;
   DeviceGuard g(h->device);

@@ -129,6 +129,8 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
                  hipStream_t s);
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);
+void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int* out_count, int cap,
+                       uint32_t* info, hipStream_t s);
 
 // k_label.hip
 void launch_init_labels(int* labels, int64_t n, hipStream_t s);

@@ -660,6 +660,21 @@ __global__ void k_border_dbx(TravArgs a) {
   if (mine) a.border[i] = best == 0x7fffffff ? -1 : best;
 }
 
+// Test hook: one lane walks the tree with an always-true box test and records,
+// in order, the leaves a walk masked at `mask` reaches (mask = -1: unmasked).
+__global__ void k_debug_walk(TreeView t, int m, int mask, int* out_leaves, int* out_count, int cap,
+                             uint32_t* info) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const Query q{0.0f, 0.0f, 0.0f};
+  int cnt = 0;
+  traverse<3, true>(t, m, q, INFINITY, mask, info, [&](int l) {
+    if (cnt < cap) out_leaves[cnt] = l;
+    ++cnt;
+    return false;
+  });
+  *out_count = cnt;
+}
+
 inline dim3 grid_of(int64_t n, int block) { return dim3(static_cast<unsigned>(ceil_div(n, block))); }
 
 }  // namespace
@@ -700,6 +715,11 @@ void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool 
     else if (first_border) main_t<2, false, true>(a, densebox, part, s);
     else main_t<2, false, false>(a, densebox, part, s);
   }
+}
+
+void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int* out_count, int cap,
+                       uint32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_walk, dim3(1), dim3(64), 0, s, t, m, mask, out_leaves, out_count, cap, info);
 }
 
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
