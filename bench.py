@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--algo", default="both", choices=["both", "densebox", "fdbscan"])
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1 = full 8M points)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=float, default=1 / 32,
+    ap.add_argument("--cpu-window", type=float, default=1 / 8,
                     help="volume fraction of the spatial window the CPU oracle clusters")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
