@@ -175,6 +175,29 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
 
+// ---- XCD-aware workgroup order -------------------------------------------------
+// gfx950 hands workgroups to its 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8), and each XCD has its own L2. Renumbering so that XCD x gets one
+// contiguous range of logical workgroups keeps Morton-neighbouring queries -
+// which walk the same subtrees - on the same L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b % kNumXcd, k = b / kNumXcd;
+  const int per = nb / kNumXcd, rem = nb % kNumXcd;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// Index of thread `tid` of workgroup b (of blocks of `bdim` threads) when the
+// active range [0, m) is split into 8 contiguous chunks, one per XCD (chunks are
+// whole workgroups); -1 for threads past their chunk. A grid of
+// 8 * ceil(ceil(n/8)/bdim) workgroups, for any n >= m, covers [0, m).
+__device__ __forceinline__ int64_t xcd_spread(int b, int bdim, int tid, int64_t m) {
+  const int64_t chunk = ((m + kNumXcd - 1) / kNumXcd + bdim - 1) / bdim * bdim;
+  const int64_t off = static_cast<int64_t>(b / kNumXcd) * bdim;
+  if (off >= chunk) return -1;
+  return (b % kNumXcd) * chunk + off + tid;
+}
+
 // ---- wavefront helpers ---------------------------------------------------------
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

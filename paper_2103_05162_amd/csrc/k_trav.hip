@@ -186,7 +186,8 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
 
 template <int D>
 __global__ void k_core_fdb(TravArgs a) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  if (i < 0) return;
   if (i >= a.n) return;
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
@@ -225,8 +226,8 @@ __device__ __forceinline__ void main_pair(const TravArgs& a, int i, bool ci, int
 
 template <int D, bool ALL_CORE, bool FIRST>
 __global__ void k_main_fdb(TravArgs a) {
-  const int64_t i64 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-  const bool valid = i64 < a.n;
+  const int64_t i64 = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  const bool valid = i64 >= 0 && i64 < a.n;
   const int i = valid ? static_cast<int>(i64) : 0;
   const bool ci = valid && (ALL_CORE || a.core[i]);
   const bool mine = valid && (FIRST || ci);  // canonical mode: border points are settled later
@@ -255,8 +256,29 @@ __global__ void k_main_fdb(TravArgs a) {
   const bool packet = ext * ext <= a.packet_ext2;
 
   if (packet) {
-    const int i0 = __shfl(i, __ffsll(static_cast<unsigned long long>(any_mine)) - 1);
     const int lane = lane_id();
+    const int first_lane = __ffsll(static_cast<unsigned long long>(any_mine)) - 1;
+    const int i0 = __shfl(i, first_lane);
+    // The wavefront's own queries are the sorted range [p0, p1].
+    const int p0 = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x & ~63, a.n));
+    const int p1 = p0 + 63;
+    bool common = false;
+    int r = 0;
+    if (!FIRST) {
+      // Phase A: pairs inside the packet, lane against lane.
+      for (int k = 0; k < 64; ++k) {
+        if (!((any_mine >> k) & 1)) continue;
+        const int jk = p0 + k;
+        const float px = readlane_f(q.x, k), py = readlane_f(q.y, k), pz = readlane_f(q.z, k);
+        if (mine && jk > i && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 && !known_same_set(labels, jk, root))
+          root = uf_union(labels, root, jk, a.info);
+      }
+      // One root for every query of the packet? Then a candidate already in that
+      // set needs no test, and a hit needs one union for the whole packet.
+      if (mine) root = uf_find(labels, root, a.info);
+      r = __shfl(root, first_lane);
+      common = !ballot(mine && root != r);
+    }
     traverse_box<D>(a.t, m, lo, hi, eps2, i0, a.packet_leaf, a.info, [&](int s, int e) {
       // the lanes load the bucket's points once; each is then broadcast to all
       const int cnt = e - s + 1;  // <= packet_leaf <= 64
@@ -275,6 +297,20 @@ __global__ void k_main_fdb(TravArgs a) {
         const bool cj = __builtin_amdgcn_readlane(cc, k) != 0;
         if (!FIRST && !cj) continue;
         const int lj = __builtin_amdgcn_readlane(cl, k);
+        if (!FIRST) {
+          if (j <= p1) continue;  // inside the packet: done in phase A (j > i0 by the mask)
+          if (common) {
+            if (lj == r) continue;
+            const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
+            const uint64_t hit = ballot(mine && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2);
+            if (!hit) continue;
+            const int leader = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+            int nr = r;
+            if (lane == leader && !known_same_set(labels, j, r)) nr = uf_union(labels, r, j, a.info);
+            r = __shfl(nr, leader);
+            continue;
+          }
+        }
         bool act = !done && j > i;
         if (act && ci && cj && lj == root) act = false;  // already one set
         if (!ballot(act)) continue;
@@ -297,7 +333,8 @@ __global__ void k_main_fdb(TravArgs a) {
 
 template <int D>
 __global__ void k_border_fdb(TravArgs a) {
-  int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  if (i < 0) return;
   if (i >= a.n) return;
   if (a.core[i]) return;
   const Query q = load_point<D>(a.xs, a.n, i);
@@ -466,8 +503,8 @@ template <int D>
 __global__ void k_core_dbx(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool mine = p < m && a.prim_cnt[p] > 0;  // dense cells are core by construction
+  const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
+  const bool mine = p >= 0 && p < m && a.prim_cnt[p] > 0;  // dense cells are core by construction
   const int i = mine ? a.prim_start[p] : 0;
   const Query q = load_point<D>(a.xs, a.n, i);
   const float eps2 = a.eps2;
@@ -504,8 +541,8 @@ template <int D, bool ALL_CORE, bool FIRST>
 __global__ void k_main_dbx_points(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool pt = p < m && a.prim_cnt[p] > 0;
+  const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
+  const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
   const int i = pt ? a.prim_start[p] : 0;
   const bool ci = pt && (ALL_CORE || a.core[i]);
   const bool mine = pt && (FIRST || ci);
@@ -566,13 +603,18 @@ __global__ void k_main_dbx_points(TravArgs a) {
 template <int D, bool ALL_CORE, bool FIRST>
 __global__ void k_main_dbx_cells(TravArgs a) {
   const int m = tree_m(a.t);
-  const int nd = *a.d_ndense;
   const int lane = lane_id();
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int wave = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const float eps2 = a.eps2;
   int* labels = a.labels;
-  for (int w = wave; w < nd; w += nwaves) {
+  // wavefront w takes a contiguous slice of the dense-cell list (filled in
+  // roughly increasing key order), so neighbouring cells share an XCD's L2
+  const int nd = *a.d_ndense;
+  const int per = (nd + nwaves - 1) / nwaves;
+  const int dbeg = wave * per, dend = min(nd, dbeg + per);
+  for (int w = dbeg; w < dend; ++w) {
+   {
     const int A = a.dense_list[w];
     const int sa = a.prim_start[A], na = -a.prim_cnt[A];
     const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
@@ -610,6 +652,7 @@ __global__ void k_main_dbx_cells(TravArgs a) {
      }
       return false;
     });
+   }
   }
 }
 
@@ -618,8 +661,8 @@ template <int D>
 __global__ void k_border_dbx(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool pt = p < m && a.prim_cnt[p] > 0;
+  const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
+  const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
   const int i = pt ? a.prim_start[p] : 0;
   const bool mine = pt && !a.core[i];
   const Query q = load_point<D>(a.xs, a.n, i);
@@ -675,7 +718,11 @@ __global__ void k_debug_walk(TreeView t, int m, int mask, int* out_leaves, int* 
   *out_count = cnt;
 }
 
-inline dim3 grid_of(int64_t n, int block) { return dim3(static_cast<unsigned>(ceil_div(n, block))); }
+// Kernels indexed with xcd_spread(): every XCD needs ceil(ceil(n/8)/block)
+// workgroups of its own, so the grid is 8 times that.
+inline dim3 grid_of(int64_t n, int block) {
+  return dim3(static_cast<unsigned>(kNumXcd * ceil_div(ceil_div(n, kNumXcd), block)));
+}
 
 }  // namespace
 
