@@ -8,6 +8,15 @@ scatter). The workload is the dense-clump 3D set: 8,388,608 points, 500 clumps
 of sigma 5e-4 holding 80% of them, uniform background, eps = 0.002, minPts = 10.
 DenseBox is the headline algorithm; FDbscan is measured beside it.
 
+A second leg clusters a batch of 4096 uneven 3D clouds (1024-65535 points each,
+every cloud with its own eps) in one call and reports clouds/s beside a loop of
+one call per cloud over the same data, and whether both give identical labels.
+
+A third leg replays an open-loop request stream (Poisson arrivals, clouds of
+10k-2M points, 2D and 3D, mixed eps and minPts) against the continuous-batching
+server and against a plain one-job-at-a-time server, and reports p50/p99
+latency, throughput and whether each keeps up.
+
 Prints one JSON line. `roofline` describes the dominant kernel (its duration is
 measured with HIP events on the library's stream over the timed steps);
 `cpu_baseline` times the CPU oracle on a spatial window of the same workload.
@@ -54,6 +63,15 @@ def parse():
                     help="volume fraction of the spatial window the CPU oracle clusters")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--batched-algo", default="fdbscan", choices=["none", "densebox", "fdbscan"],
+                    help="algorithm of the batched many-cloud leg (none = skip it)")
+    ap.add_argument("--clouds", type=int, default=4096, help="clouds in the batched leg")
+    ap.add_argument("--served-algo", default="densebox", choices=["none", "densebox", "fdbscan"],
+                    help="algorithm of the served leg (none = skip it)")
+    ap.add_argument("--requests", type=int, default=22000, help="requests in the served trace")
+    ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="HBM budget of the served batches")
+    ap.add_argument("--pool-per-dim", type=int, default=32, help="resident clouds per dimension")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (PMC calibration)")
     return ap.parse_args()
@@ -81,6 +99,150 @@ def time_algo(fdb, h, pts, eps, min_pts, algo, steps, warmup, leaf, block):
     ms = (t1 - t0) * 1e3 / steps
     per_call = {k2: v / max(calls, 1) for k2, v in stages.items()}
     return dict(ms=ms, k=k, stages=per_call, info=h.last_info(), sizes=h.last_counts())
+
+
+def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
+    """Batched clustering of many uneven 3D clouds (each with its own eps and minPts)
+    in one call, against the same clouds clustered one call at a time."""
+    import torch
+    from workloads.gen import batched_clouds
+    t0 = time.perf_counter()
+    clouds, eps, mp = batched_clouds(num_clouds)
+    sizes = np.array([c.shape[0] for c in clouds], dtype=np.int64)
+    offs = np.zeros(num_clouds + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    n = int(offs[-1])
+    log(f"[bench] batched workload: {num_clouds} clouds, {n} points ({time.perf_counter() - t0:.1f} s to generate)")
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(np.concatenate(clouds)).to(dev)
+    del clouds
+    d_off = torch.from_numpy(offs).to(dev)
+    d_eps = torch.from_numpy(eps).to(dev)
+    d_mp = torch.from_numpy(mp).to(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    core = torch.empty(n, dtype=torch.uint8, device=dev)
+    ncl = torch.empty(num_clouds, dtype=torch.int32, device=dev)
+    ws = torch.empty(fdb.workspace_bytes_batched(n, num_clouds, 3, algo), dtype=torch.uint8, device=dev)
+    kw = dict(algo=algo, handle=h, labels=labels, is_core=core, num_clusters=ncl, workspace=ws)
+    for _ in range(max(warmup, 1)):
+        fdb.dbscan_batched(pts, d_off, d_eps, d_mp, **kw)
+    torch.cuda.synchronize()
+    info = h.last_info()
+    h.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fdb.dbscan_batched(pts, d_off, d_eps, d_mp, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    stages, calls = h.stage_times()
+    h.set_timing(False)
+    # one call per cloud, outputs written in place, one workspace sized for the largest cloud
+    opt = fdb.make_options(algo)
+    lws = torch.empty(fdb.workspace_bytes(int(sizes.max()), 3, algo), dtype=torch.uint8, device=dev)
+    lab2 = torch.empty_like(labels)
+    core2 = torch.empty_like(core)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    bp, lp, cp, wp, wsz = pts.data_ptr(), lab2.data_ptr(), core2.data_ptr(), lws.data_ptr(), lws.numel()
+
+    def loop():
+        for c in range(num_clouds):
+            b, nc = int(offs[c]), int(sizes[c])
+            h.dbscan_raw(bp + 12 * b, nc, 3, float(eps[c]), int(mp[c]), lp + 4 * b, cp + b, stream, opt, False,
+                         wp, wsz)
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(loop_passes):
+        loop()
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3 / loop_passes
+    same = bool(torch.equal(labels, lab2) and torch.equal(core, core2))
+    return dict(ms=ms, loop_ms=loop_ms, n=n, identical=same, info=info,
+                stages={k2: v / max(calls, 1) for k2, v in stages.items()},
+                clusters=int(ncl.sum().item()))
+
+
+def replay(fdb, mode, algo, budget, max_batch, ptrs, req, out, warm_s):
+    """Replay the request trace open-loop against one server; returns its stats over
+    the requests that arrive after the warm-up period."""
+    srv = fdb.Server(0, budget_bytes=budget, max_batch=max_batch, mode=mode, algo=algo)
+    arrival, dim, n, eps, mp, off = (req["arrival_s"], req["dim"], req["n"], req["eps"], req["min_pts"],
+                                     req["out_off"])
+    first = int(np.searchsorted(arrival, warm_s))
+    base = out.data_ptr()
+    lag = 0.0
+    t0 = time.perf_counter() + 0.05
+    next_log = 2.0
+    try:
+        for r in range(len(arrival)):
+            ta = t0 + arrival[r]
+            now = time.perf_counter()
+            while now < ta:
+                now = time.perf_counter()
+            lag = max(lag, now - ta)
+            srv.submit_raw(ptrs[r], int(n[r]), int(dim[r]), float(eps[r]), int(mp[r]), base + 4 * int(off[r]))
+            if arrival[r] >= next_log:
+                log(f"[bench]   {mode}: {r + 1} requests submitted")
+                next_log += 2.0
+        srv.drain()
+        st = srv.stats(first)
+        st_all = srv.stats(0)
+    finally:
+        srv.close()
+    window = float(arrival[-1] - arrival[first]) if len(arrival) > first + 1 else 0.0
+    offered = (len(arrival) - first) / window if window > 0 else 0.0
+    served = st["jobs"] / st["span_s"] if st["span_s"] > 0 else 0.0
+    return {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+            "mean_ms": round(st["mean_us"] / 1e3, 3), "max_ms": round(st["max_us"] / 1e3, 3),
+            "jobs_per_s": round(served, 1), "offered_jobs_per_s": round(offered, 1),
+            "mpts_per_s": round(st["points"] / st["span_s"] / 1e6, 1) if st["span_s"] > 0 else 0.0,
+            "saturated": bool(served < 0.95 * offered), "jobs": st["jobs"], "batches": st["batches"],
+            "max_batch_jobs": st["max_batch_jobs"], "max_queue": st["max_queue"],
+            "busy_frac": round(st_all["busy_s"] / st_all["span_s"], 3) if st_all["span_s"] > 0 else None,
+            "client_lag_max_us": round(float(lag) * 1e6, 1)}
+
+
+def time_served(fdb, algo, requests, rate, budget_gib, pool_per_dim, warm_s=1.0):
+    """Served leg: the same open-loop trace replayed on the continuous-batching server
+    and on the plain one-job-at-a-time server; every request's labels must agree."""
+    import torch
+    from workloads.gen import served_trace
+    t0 = time.perf_counter()
+    pool, req = served_trace(requests=requests, rate=rate, pool_per_dim=pool_per_dim)
+    log(f"[bench] served trace: {requests} requests at {rate:g}/s, pool of {2 * pool_per_dim} clouds "
+        f"({time.perf_counter() - t0:.1f} s to generate)")
+    dev = torch.device("cuda:0")
+    pool_dev = {d: [torch.from_numpy(c).to(dev) for c in pool[d]] for d in pool}
+    del pool
+    ptrs = [pool_dev[int(d)][int(c)].data_ptr() for d, c in zip(req["dim"], req["cloud"])]
+    req["out_off"] = np.concatenate([[0], np.cumsum(req["n"])[:-1]]).astype(np.int64)
+    total = int(req["n"].sum())
+    out = torch.empty(total, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    budget = int(budget_gib * (1 << 30))
+    res = {}
+    rng = np.random.default_rng(0)
+    first = int(np.searchsorted(req["arrival_s"], warm_s))
+    sample = rng.choice(np.arange(first, requests), size=min(64, requests - first), replace=False)
+    kept = {}
+    for mode in ("batched", "fifo"):
+        log(f"[bench] serving the trace ({mode})")
+        res[mode] = replay(fdb, mode, algo, budget, 4096, ptrs, req, out, warm_s)
+        log(f"[bench]   {mode}: {res[mode]}")
+        got = {int(r): out[int(req['out_off'][r]):int(req['out_off'][r]) + int(req['n'][r])].cpu() for r in sample}
+        kept[mode] = got
+    same = all(torch.equal(kept["batched"][r], kept["fifo"][r]) for r in kept["batched"])
+    del out, pool_dev
+    torch.cuda.empty_cache()
+    return {"workload": f"{requests} requests, Poisson arrivals at {rate:g}/s (first {warm_s:g} s not counted), "
+                        f"sizes log-uniform 10240-2097151 from a pool of {2 * pool_per_dim} clouds, d in {{2,3}}, "
+                        f"minPts in {{2,5,10}}, eps 0.005-0.02",
+            "algo": algo, "hbm_budget_gib": budget_gib, "mean_points": round(float(req["n"].mean()), 1),
+            "batched": res["batched"], "fifo": res["fifo"],
+            "p99_speedup_vs_fifo": round(res["fifo"]["p99_ms"] / res["batched"]["p99_ms"], 3)
+            if res["batched"]["p99_ms"] > 0 else None,
+            "identical_labels_sampled": same, "sampled_requests": len(sample)}
 
 
 def algorithmic_bytes(stage, n, sizes):
@@ -242,6 +404,29 @@ def main():
                          "roofline": res[a]["roofline"]} for a in algos},
         "src_hash": source_hash(),
     }
+    if args.batched_algo != "none":
+        del pts
+        torch.cuda.empty_cache()
+        log(f"[bench] batched leg ({args.batched_algo})")
+        b = time_batched(fdb, h, args.batched_algo, args.steps, args.warmup, args.clouds, 1)
+        log(f"[bench] batched: {b['ms']:.2f} ms per batch, loop {b['loop_ms']:.2f} ms, identical={b['identical']}")
+        for st, v in sorted(b["stages"].items(), key=lambda kv: -kv[1]):
+            log(f"    {st:12s} {v:9.3f} ms")
+        out["batched"] = {
+            "workload": f"{args.clouds} 3D clouds of 1024-65535 points (log-uniform), 1-20 clumps each, "
+                        f"eps 0.005-0.02 per cloud, minPts 5; {b['n']} points",
+            "algo": args.batched_algo, "ms_per_batch": round(b["ms"], 3),
+            "clouds_per_s": round(args.clouds / (b["ms"] / 1e3), 1),
+            "mpts_per_s": round(b["n"] / (b["ms"] / 1e3) / 1e6, 3),
+            "loop_ms": round(b["loop_ms"], 3),
+            "loop_clouds_per_s": round(args.clouds / (b["loop_ms"] / 1e3), 1),
+            "speedup_vs_loop": round(b["loop_ms"] / b["ms"], 3),
+            "identical_to_loop": b["identical"], "clusters": b["clusters"], "info": b["info"],
+            "stages_ms": {k2: round(v, 4) for k2, v in b["stages"].items()}}
+    if args.served_algo != "none":
+        log(f"[bench] served leg ({args.served_algo})")
+        out["served"] = time_served(fdb, args.served_algo, args.requests, args.rate, args.budget_gib,
+                                    args.pool_per_dim)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu oracle on a {args.cpu_window:g} window")
         out["cpu_baseline"] = cpu_baseline(w.points, w.eps, w.min_pts, args.cpu_window)

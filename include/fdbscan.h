@@ -84,7 +84,9 @@ enum {
   FDB_INFO_DENSEBOX_FALLBACK = 1u, /* DenseBox asked for, but the grid could not be indexed in 64-bit
                                       keys (eps tiny against the extent): FDbscan ran instead. */
   FDB_INFO_NONFINITE = 2u,         /* a NaN or infinite coordinate was seen; labels are undefined */
-  FDB_INFO_INTERNAL = 4u           /* a kernel stopped a walk that broke its own bounds; labels undefined */
+  FDB_INFO_INTERNAL = 4u,          /* a kernel stopped a walk that broke its own bounds; labels undefined */
+  FDB_INFO_BAD_PARAMS = 8u         /* batch: some cloud's eps is not finite and > 0, or its minPts < 1;
+                                      that cloud's labels are undefined */
 };
 
 /* Create a handle bound to HIP device `device`. *out receives the handle. */
@@ -121,6 +123,37 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
                       const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
                       void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Cluster a batch of independent point clouds in one launch sequence (every
+ * stage is one kernel launch for the whole batch; nothing waits for the GPU).
+ * Cloud c is points[offsets[c] .. offsets[c+1]) (row-major [*][dim] float32, as
+ * in fdb_dbscan) and is clustered on its own with eps[c] and min_pts[c]; its
+ * labels (in input order, at the same positions) and is_core flags are exactly
+ * what fdb_dbscan would give for that cloud alone, and num_clusters[c] its K.
+ *   n_total       offsets[num_clouds]; 0 <= n_total < 2^30 (host value).
+ *   offsets       device int64 [num_clouds+1], nondecreasing, offsets[0] = 0,
+ *                 offsets[num_clouds] = n_total. Offsets outside [0, n_total] are
+ *                 clamped (never read out of bounds) and raise FDB_INFO_BAD_PARAMS.
+ *   num_clouds    1 .. 2^24.
+ *   eps, min_pts  device float32 / int32 [num_clouds]; a cloud with eps not finite
+ *                 and > 0, or min_pts < 1, raises FDB_INFO_BAD_PARAMS.
+ *   labels        device int32 [n_total] out; is_core device uint8 [n_total] or NULL.
+ *   num_clusters  device int32 [num_clouds] out, or NULL: K of each cloud, or -1
+ *                 where that cloud's labels are undefined (a coordinate that is not
+ *                 finite, bad eps/min_pts, or offsets out of order); other clouds'
+ *                 results stay exact.
+ *   workspace     >= fdb_workspace_bytes_batched() bytes, or NULL (handle-owned).
+ * The core pass runs for every cloud (also minPts <= 2: same result). The
+ * batch-wide error bits (FDB_INFO_NONFINITE, FDB_INFO_BAD_PARAMS,
+ * FDB_INFO_INTERNAL) are read with fdb_last_info().
+ */
+fdb_status fdb_workspace_bytes_batched(int64_t n_total, int32_t num_clouds, int32_t dim, const fdb_options* opt,
+                                       size_t* h_out);
+fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                              int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                              const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Wait for the stream of the last fdb_dbscan call on h and return its FDB_INFO_* bits. */
 fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info);
 
@@ -148,6 +181,80 @@ fdb_status fdb_stage_times(fdb_handle* h, int32_t max, const char** h_names, dou
    in walk order (h_leaves holds m entries). m <= 2^24. */
 fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int32_t mask, int32_t leaf_size,
                           int32_t* h_gamma, int32_t* h_other, int32_t* h_leaves, int32_t* h_num_leaves);
+
+/*
+ * Served clustering: a stream of independent jobs (each one cloud with its own
+ * eps and minPts, as in fdb_dbscan) on one device. The method itself is the
+ * per-cloud clustering of Sections 4.1-4.2; serving many clouds at once is not
+ * in the paper. A server owns one worker thread, one stream, and one device
+ * arena of hbm_budget_bytes allocated at creation; jobs never allocate.
+ *   FDB_SERVE_BATCHED  continuous batching: whenever the device is free, the
+ *                      worker takes the waiting jobs of the oldest job's dim, in
+ *                      arrival order, while the batch (its fdb_dbscan_batched
+ *                      workspace plus gathered points, labels, flags and
+ *                      per-job arrays) fits in the budget and holds at most
+ *                      max_batch jobs, and runs them as one batched launch
+ *                      sequence; a job arriving meanwhile joins the next batch.
+ *   FDB_SERVE_FIFO     one job at a time with fdb_dbscan, in arrival order (the
+ *                      plain server; the arena is its workspace).
+ * A job's labels, is_core and K equal what fdb_dbscan gives for it alone
+ * (canonical border mode; opt->border = FDB_BORDER_FIRST gives a valid
+ * first-claim assignment instead).
+ */
+typedef struct fdb_server fdb_server;
+
+enum { FDB_SERVE_BATCHED = 0, FDB_SERVE_FIFO = 1 };
+
+typedef struct {
+  const float* points; /* device [n][dim] float32; must stay unchanged until the job is done */
+  int64_t n;           /* 0 <= n < 2^30; n = 0 completes at submission with K = 0 */
+  int32_t dim;         /* 2 or 3 */
+  float eps;           /* finite, > 0 */
+  int32_t min_pts;     /* >= 1 */
+  int32_t* labels;     /* device int32 [n] out (input order; -1 noise, else 0..K-1) */
+  uint8_t* is_core;    /* device uint8 [n] out, or NULL */
+} fdb_job;
+
+typedef struct {
+  int32_t done;         /* 1 once the outputs are final (the device work has completed) */
+  int32_t status;       /* fdb_status of the job once done: FDB_OK, FDB_ERR_NONFINITE, ... */
+  int32_t num_clusters; /* K once done (-1 when the labels are undefined) */
+  int32_t batch_jobs;   /* jobs in the launch that ran it (0 while queued) */
+  double queue_us;      /* submission -> start of its batch (-1 while queued) */
+  double latency_us;    /* submission -> outputs final (-1 until done) */
+} fdb_job_result;
+
+typedef struct {
+  int64_t jobs;           /* completed jobs with n > 0 among the tickets counted */
+  int64_t points;         /* their points */
+  int64_t batches;        /* launches since creation */
+  int64_t max_queue;      /* longest queue seen since creation */
+  int32_t max_batch_jobs; /* most jobs in one launch since creation */
+  double span_s;          /* first submission -> last completion of the counted jobs */
+  double busy_s;          /* worker time spent running launches since creation */
+  double p50_us, p99_us;  /* latency percentiles (nearest rank) of the counted jobs */
+  double mean_us, max_us;
+} fdb_serve_stats;
+
+/* Create a server on `device`. max_batch in 1 .. 2^20 (ignored in FIFO mode);
+   hbm_budget_bytes >= 1 MiB. FDB_ERR_NOMEM if the arena cannot be allocated. */
+fdb_status fdb_server_create(int device, size_t hbm_budget_bytes, int32_t max_batch, int32_t mode,
+                             const fdb_options* opt, fdb_server** out);
+/* Queue a job (thread-safe, never waits for the device). The job's points must
+   be ready on the device (the caller's stream synchronised) before this call.
+   FDB_ERR_INVALID for bad arguments, FDB_ERR_NOMEM if the job alone does not fit
+   in the budget. *h_ticket identifies the job (0, 1, 2, ... in submission order). */
+fdb_status fdb_server_submit(fdb_server* s, const fdb_job* job, int64_t* h_ticket);
+/* State of a job without waiting, or waiting until it is done (h_out may be NULL). */
+fdb_status fdb_server_poll(fdb_server* s, int64_t ticket, fdb_job_result* h_out);
+fdb_status fdb_server_wait(fdb_server* s, int64_t ticket, fdb_job_result* h_out);
+/* Wait until every job submitted so far is done. */
+fdb_status fdb_server_drain(fdb_server* s);
+/* Latency and throughput over the jobs with ticket >= first_ticket (e.g. to leave
+   out a warm-up period). */
+fdb_status fdb_server_stats(fdb_server* s, int64_t first_ticket, fdb_serve_stats* h_out);
+/* Run every queued job, stop the worker and free the server's memory. */
+void fdb_server_destroy(fdb_server* s);
 
 /* Static description of a status code. */
 const char* fdb_status_string(fdb_status s);

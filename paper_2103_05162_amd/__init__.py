@@ -7,11 +7,12 @@ include/fdbscan.h); this package marshals torch tensors into that ABI.
 """
 from __future__ import annotations
 
-from ._lib import (FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FdbError, Handle, load, make_options,
-                   status_string, workspace_bytes)
+from ._lib import (FDB_INFO_BAD_PARAMS, FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError,
+                   Handle, Server, load, make_options, status_string, workspace_bytes, workspace_bytes_batched)
 
-__all__ = ["dbscan", "Handle", "FdbError", "workspace_bytes", "default_handle", "load", "make_options",
-           "status_string", "FDB_INFO_DENSEBOX_FALLBACK", "FDB_INFO_NONFINITE"]
+__all__ = ["dbscan", "dbscan_batched", "Handle", "Server", "FdbError", "workspace_bytes", "workspace_bytes_batched",
+           "default_handle", "load", "make_options", "status_string", "FDB_INFO_DENSEBOX_FALLBACK",
+           "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL", "FDB_INFO_BAD_PARAMS"]
 
 _handles: dict[int, Handle] = {}
 
@@ -54,3 +55,46 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     k = h.dbscan_raw(pts.data_ptr() if n else 0, n, d, eps, min_pts, labels.data_ptr() if n else 0,
                      is_core.data_ptr() if n else 0, stream, opt, want_k, ws_ptr, ws_size)
     return labels, is_core.bool(), k
+
+
+def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border: str = "canonical",
+                   leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
+                   num_clusters=None, workspace=None):
+    """Cluster a batch of clouds in one launch sequence.
+
+    points: [N, d] float32 on a HIP device (clouds concatenated); offsets: int64
+    [B+1] (cloud c = points[offsets[c]:offsets[c+1]]); eps: float32 [B];
+    min_pts: int32 [B] (all on the same device). Returns (labels int32 [N],
+    is_core bool [N], num_clusters int32 [B]); cloud c's labels are its own
+    (-1 noise, else 0..K_c-1) and equal what dbscan() gives for it alone.
+    Asynchronous: nothing waits for the GPU.
+    """
+    import torch
+
+    pts = points.contiguous()
+    if pts.dtype != torch.float32 or pts.dim() != 2 or pts.shape[1] not in (2, 3):
+        raise ValueError("points must be float32 with shape [N, 2] or [N, 3]")
+    n, d = pts.shape
+    dev = pts.device
+    offs = offsets.to(device=dev, dtype=torch.int64).contiguous()
+    b = offs.numel() - 1
+    e = eps.to(device=dev, dtype=torch.float32).contiguous()
+    mp = min_pts.to(device=dev, dtype=torch.int32).contiguous()
+    if e.numel() != b or mp.numel() != b:
+        raise ValueError("eps and min_pts need one entry per cloud")
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    h = handle if handle is not None else default_handle(idx)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    if is_core is None:
+        is_core = torch.empty(n, dtype=torch.uint8, device=dev)
+    if num_clusters is None:
+        num_clusters = torch.empty(b, dtype=torch.int32, device=dev)
+    opt = make_options(algo, border, leaf_size, block_size)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
+        else (None, 0)
+    h.dbscan_batched_raw(pts.data_ptr() if n else 0, n, offs.data_ptr(), b, d, e.data_ptr(), mp.data_ptr(),
+                         labels.data_ptr() if n else 0, is_core.data_ptr() if n else 0, num_clusters.data_ptr(),
+                         stream, opt, ws_ptr, ws_size)
+    return labels, is_core.bool(), num_clusters

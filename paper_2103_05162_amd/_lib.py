@@ -12,10 +12,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdbscan.so")
 
-FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE = range(5)
+FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL = range(6)
 FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX = 0, 1
 FDB_BORDER_CANONICAL, FDB_BORDER_FIRST = 0, 1
-FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE = 1, 2
+FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FDB_INFO_INTERNAL, FDB_INFO_BAD_PARAMS = 1, 2, 4, 8
 
 ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX}
 BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST}
@@ -24,6 +24,27 @@ BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST}
 class FdbOptions(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("border", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FdbJob(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("min_pts", ctypes.c_int32), ("labels", ctypes.c_void_p), ("is_core", ctypes.c_void_p)]
+
+
+class FdbJobResult(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("num_clusters", ctypes.c_int32),
+                ("batch_jobs", ctypes.c_int32), ("queue_us", ctypes.c_double), ("latency_us", ctypes.c_double)]
+
+
+class FdbServeStats(ctypes.Structure):
+    _fields_ = [("jobs", ctypes.c_int64), ("points", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_queue", ctypes.c_int64), ("max_batch_jobs", ctypes.c_int32), ("span_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double)]
+
+
+FDB_SERVE_BATCHED, FDB_SERVE_FIFO = 0, 1
+SERVE_MODES = {"batched": FDB_SERVE_BATCHED, "fifo": FDB_SERVE_FIFO}
 
 
 class FdbError(RuntimeError):
@@ -56,6 +77,11 @@ def load() -> ctypes.CDLL:
     lib.fdb_dbscan.argtypes = [vp, vp, i64, i32, ctypes.c_float, i32, ctypes.POINTER(FdbOptions), vp, vp,
                                ctypes.POINTER(i32), vp, sz, vp]
     lib.fdb_dbscan.restype = ctypes.c_int
+    lib.fdb_workspace_bytes_batched.argtypes = [i64, i32, i32, ctypes.POINTER(FdbOptions), ctypes.POINTER(sz)]
+    lib.fdb_workspace_bytes_batched.restype = ctypes.c_int
+    lib.fdb_dbscan_batched.argtypes = [vp, vp, i64, vp, i32, i32, vp, vp, ctypes.POINTER(FdbOptions), vp, vp, vp, vp,
+                                       sz, vp]
+    lib.fdb_dbscan_batched.restype = ctypes.c_int
     lib.fdb_last_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.fdb_last_info.restype = ctypes.c_int
     lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
@@ -68,6 +94,20 @@ def load() -> ctypes.CDLL:
     lib.fdb_stage_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fdb_stage_times.restype = ctypes.c_int
+    lib.fdb_server_create.argtypes = [ctypes.c_int, sz, i32, i32, ctypes.POINTER(FdbOptions), ctypes.POINTER(vp)]
+    lib.fdb_server_create.restype = ctypes.c_int
+    lib.fdb_server_submit.argtypes = [vp, ctypes.POINTER(FdbJob), ctypes.POINTER(i64)]
+    lib.fdb_server_submit.restype = ctypes.c_int
+    lib.fdb_server_poll.argtypes = [vp, i64, ctypes.POINTER(FdbJobResult)]
+    lib.fdb_server_poll.restype = ctypes.c_int
+    lib.fdb_server_wait.argtypes = [vp, i64, ctypes.POINTER(FdbJobResult)]
+    lib.fdb_server_wait.restype = ctypes.c_int
+    lib.fdb_server_drain.argtypes = [vp]
+    lib.fdb_server_drain.restype = ctypes.c_int
+    lib.fdb_server_stats.argtypes = [vp, i64, ctypes.POINTER(FdbServeStats)]
+    lib.fdb_server_stats.restype = ctypes.c_int
+    lib.fdb_server_destroy.argtypes = [vp]
+    lib.fdb_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -85,6 +125,14 @@ def make_options(algo="fdbscan", border="canonical", leaf_size=0, block_size=0, 
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     b = BORDERS[border] if isinstance(border, str) else int(border)
     return FdbOptions(a, b, int(leaf_size), int(block_size), int(flags))
+
+
+def workspace_bytes_batched(n_total: int, num_clouds: int, dim: int, algo="fdbscan") -> int:
+    out = ctypes.c_size_t(0)
+    opt = make_options(algo)
+    _check(load().fdb_workspace_bytes_batched(int(n_total), int(num_clouds), int(dim), ctypes.byref(opt),
+                                              ctypes.byref(out)), "fdb_workspace_bytes_batched")
+    return int(out.value)
 
 
 def workspace_bytes(n: int, dim: int, algo="fdbscan") -> int:
@@ -129,6 +177,20 @@ class Handle:
         _check(st, "fdb_dbscan")
         return int(k.value) if want_k else None
 
+    def dbscan_batched_raw(self, points_ptr: int, n_total: int, offsets_ptr: int, num_clouds: int, dim: int,
+                           eps_ptr: int, min_pts_ptr: int, labels_ptr: int, core_ptr: int | None,
+                           num_clusters_ptr: int | None, stream: int, options: FdbOptions | None = None,
+                           workspace_ptr: int | None = None, workspace_size: int = 0) -> None:
+        """fdb_dbscan_batched on raw device pointers (asynchronous)."""
+        vp = ctypes.c_void_p
+        st = self._lib.fdb_dbscan_batched(self.ptr, vp(points_ptr), int(n_total), vp(offsets_ptr), int(num_clouds),
+                                          int(dim), vp(eps_ptr), vp(min_pts_ptr),
+                                          ctypes.byref(options) if options is not None else None, vp(labels_ptr),
+                                          vp(core_ptr) if core_ptr else None,
+                                          vp(num_clusters_ptr) if num_clusters_ptr else None,
+                                          vp(workspace_ptr) if workspace_ptr else None, int(workspace_size), vp(stream))
+        _check(st, "fdb_dbscan_batched")
+
     def last_info(self) -> int:
         v = ctypes.c_uint32(0)
         _check(self._lib.fdb_last_info(self.ptr, ctypes.byref(v)), "fdb_last_info")
@@ -168,3 +230,59 @@ class Handle:
         _check(self._lib.fdb_stage_times(self.ptr, cap, names, ms, ctypes.byref(cnt), ctypes.byref(calls)),
                "fdb_stage_times")
         return {names[i].decode(): ms[i] for i in range(min(cnt.value, cap))}, int(calls.value)
+
+
+def _result(r: FdbJobResult) -> dict:
+    return {"done": bool(r.done), "status": int(r.status), "num_clusters": int(r.num_clusters),
+            "batch_jobs": int(r.batch_jobs), "queue_us": float(r.queue_us), "latency_us": float(r.latency_us)}
+
+
+class Server:
+    """fdb_server: a job queue served by continuous batching ("batched") or one job
+    at a time ("fifo") inside a fixed device-memory budget."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 8 << 30, max_batch: int = 4096, mode: str = "batched",
+                 algo="fdbscan", border="canonical"):
+        self._lib = load()
+        p = ctypes.c_void_p()
+        opt = make_options(algo, border)
+        _check(self._lib.fdb_server_create(int(device), int(budget_bytes), int(max_batch), SERVE_MODES[mode],
+                                           ctypes.byref(opt), ctypes.byref(p)), "fdb_server_create")
+        self.ptr = p
+
+    def submit_raw(self, points_ptr: int, n: int, dim: int, eps: float, min_pts: int, labels_ptr: int,
+                   core_ptr: int | None = None) -> int:
+        job = FdbJob(ctypes.c_void_p(points_ptr or None), int(n), int(dim), ctypes.c_float(eps), int(min_pts),
+                     ctypes.c_void_p(labels_ptr or None), ctypes.c_void_p(core_ptr) if core_ptr else None)
+        t = ctypes.c_int64(-1)
+        _check(self._lib.fdb_server_submit(self.ptr, ctypes.byref(job), ctypes.byref(t)), "fdb_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> dict:
+        r = FdbJobResult()
+        _check(self._lib.fdb_server_poll(self.ptr, int(ticket), ctypes.byref(r)), "fdb_server_poll")
+        return _result(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = FdbJobResult()
+        _check(self._lib.fdb_server_wait(self.ptr, int(ticket), ctypes.byref(r)), "fdb_server_wait")
+        return _result(r)
+
+    def drain(self) -> None:
+        _check(self._lib.fdb_server_drain(self.ptr), "fdb_server_drain")
+
+    def stats(self, first_ticket: int = 0) -> dict:
+        st = FdbServeStats()
+        _check(self._lib.fdb_server_stats(self.ptr, int(first_ticket), ctypes.byref(st)), "fdb_server_stats")
+        return {k: getattr(st, k) for k, _ in FdbServeStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "ptr", None):
+            self._lib.fdb_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

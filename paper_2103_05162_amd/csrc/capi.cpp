@@ -10,6 +10,7 @@
 // fused traversal -> the same tail.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,11 +24,12 @@ namespace fdb {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Plan make_plan(int64_t n, int dim, int algo) {
+Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   Plan p;
   p.n = n;
   p.dim = dim;
   p.algo = algo;
+  p.num_clouds = num_clouds;
   const size_t N = static_cast<size_t>(n > 0 ? n : 1);
   p.sort_tiles = ceil_div(static_cast<int64_t>(N), kSortTile);
   p.scan_blocks = ceil_div(static_cast<int64_t>(N), kScanTile);
@@ -81,6 +83,17 @@ Plan make_plan(int64_t n, int dim, int algo) {
     p.prim_hi = take(N * 16);
     p.prim_key = take(N * 8);
     p.dense_list = take(N * 4);
+  }
+  p.cl_lo = p.cl_scale = p.cl_eps2 = p.cl_minpts = p.cl_root = p.cl_end = p.cl_flags = 0;
+  if (num_clouds > 0) {
+    const size_t B = static_cast<size_t>(num_clouds);
+    p.cl_lo = take(B * 16);
+    p.cl_scale = take(B * 16);
+    p.cl_eps2 = take(B * 4);
+    p.cl_minpts = take(B * 4);
+    p.cl_root = take(B * 4);
+    p.cl_end = take(B * 4);
+    p.cl_flags = take(B * 4);
   }
   p.bytes = off;
   return p;
@@ -495,7 +508,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.xs = xs;
   ta.n = n;
   ta.eps2 = eps2;
-  ta.packet_ext2 = 4.0f * eps2;  // group extent <= 2 eps
+  ta.packet_ext_eps2 = 4.0f;  // packet when the queries' box is at most 2 eps wide
   ta.packet_leaf = 32;
   ta.min_pts = min_pts;
   ta.labels = lab;
@@ -601,6 +614,189 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     if (h->h_pinned[8] & FDB_INFO_INTERNAL) return FDB_ERR_INTERNAL;
   }
   return FDB_OK;
+}
+
+fdb_status fdb_workspace_bytes_batched(int64_t n_total, int32_t num_clouds, int32_t dim, const fdb_options* opt,
+                                       size_t* h_out) {
+  if (!h_out) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o) || (dim != 2 && dim != 3) || n_total < 0 || n_total > fdb::kMaxPoints || num_clouds < 1 ||
+      num_clouds > (1 << 24))
+    return FDB_ERR_INVALID;
+  *h_out = fdb::make_plan(n_total, dim, o.algo, num_clouds).bytes;
+  return FDB_OK;
+}
+
+fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                              int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                              const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
+                              void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace fdb;
+  if (!h) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o) || (dim != 2 && dim != 3) || n_total < 0 || n_total > kMaxPoints || num_clouds < 1 ||
+      num_clouds > (1 << 24) || !offsets || !eps || !min_pts)
+    return FDB_ERR_INVALID;
+  if (n_total > 0 && (!points || !labels)) return FDB_ERR_INVALID;
+  DeviceGuard guard(h->device);
+  h->last_stream = stream;
+  h->host_info = 0;
+  h->last_misc = nullptr;
+  hipStream_t s = stream;
+  if (n_total == 0) {
+    if (num_clusters) fill_u32(reinterpret_cast<uint32_t*>(num_clusters), 0, num_clouds, s);
+    return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
+  }
+  const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
+  const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
+  const bool densebox = o.algo == FDB_ALGO_DENSEBOX;
+  const bool first_border = o.border == FDB_BORDER_FIRST;
+  const Plan plan = make_plan(n_total, dim, o.algo, num_clouds);
+  void* ws = workspace;
+  if (ws) {
+    if (workspace_bytes < plan.bytes) return FDB_ERR_NOMEM;
+  } else {
+    if (h->ws_bytes < plan.bytes) {
+      if (h->ws) {
+        if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+      }
+      if (hipMalloc(&h->ws, plan.bytes) != hipSuccess) return FDB_ERR_NOMEM;
+      h->ws_bytes = plan.bytes;
+    }
+    ws = h->ws;
+  }
+  (void)hipGetLastError();
+  Stager st(h, s);
+  if (h->timing) ++h->timed_calls;
+  const int64_t n = n_total;
+  int cb = 1;
+  while ((int64_t(1) << cb) < num_clouds) ++cb;
+  const int bpd = std::min(dim == 3 ? 21 : 31, (64 - cb) / dim);  // key bits per axis below the cloud id
+  const int shift = dim * bpd;
+  int* misc = at<int>(ws, plan.misc);
+  void* keys[2] = {at<void>(ws, plan.keys0), at<void>(ws, plan.keys1)};
+  uint32_t* vals[2] = {at<uint32_t>(ws, plan.vals0), at<uint32_t>(ws, plan.vals1)};
+  float* xs = at<float>(ws, plan.xs);
+  int* lab = at<int>(ws, plan.labels);
+  uint8_t* core = at<uint8_t>(ws, plan.core);
+  float4* cl_lo = at<float4>(ws, plan.cl_lo);
+  float4* cl_scale = at<float4>(ws, plan.cl_scale);
+  float* cl_eps2 = at<float>(ws, plan.cl_eps2);
+  int* cl_minpts = at<int>(ws, plan.cl_minpts);
+  int* cl_root = at<int>(ws, plan.cl_root);
+  int* cl_end = at<int>(ws, plan.cl_end);
+
+  st.mark("clouds");
+  fill_u32(h->d_info, 0, 1, s);
+  fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
+  int* cl_flags = at<int>(ws, plan.cl_flags);
+  batch_prep(points, offsets, num_clouds, n, dim, eps, min_pts, bpd, densebox, cl_lo, cl_scale, cl_eps2, cl_minpts,
+             cl_flags, h->d_info, s);
+  st.mark("keys");
+  batch_keys(points, offsets, num_clouds, n, dim, cl_lo, cl_scale, bpd, shift, static_cast<uint64_t*>(keys[0]),
+             vals[0], s);
+  st.mark("sort");
+  const int cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, shift + cb, at<uint32_t>(ws, plan.hist),
+                             at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr),
+                             at<uint64_t>(ws, plan.status), h->d_info, s);
+  const uint32_t* perm = vals[cur];
+  const uint64_t* pkeys = static_cast<const uint64_t*>(keys[cur]);
+  st.mark("permute");
+  launch_permute(points, n, dim, perm, xs, h->d_info, s);
+
+  TravArgs ta{};
+  ta.xs = xs;
+  ta.n = n;
+  ta.eps2 = 0.0f;
+  ta.packet_ext_eps2 = 4.0f;
+  ta.packet_leaf = 32;
+  ta.min_pts = 0;
+  ta.labels = lab;
+  ta.core = core;
+  ta.cid = at<int>(ws, plan.cid);
+  ta.border = at<int>(ws, plan.border);
+  ta.block = block;
+  ta.info = h->d_info;
+  ta.t.node_a = at<float4>(ws, plan.node_a);
+  ta.t.node_b = at<float4>(ws, plan.node_b);
+  ta.t.rope = at<int>(ws, plan.rope);
+  ta.t.leaf_rope = at<int>(ws, plan.leaf_rope);
+  ta.t.leaf_size = leaf;
+  ta.t.m_cap = static_cast<int>(n);
+  ta.pkeys = pkeys;
+  ta.key_shift = shift;
+  ta.num_clouds = num_clouds;
+  ta.cloud_root = cl_root;
+  ta.cloud_end = cl_end;
+  ta.cloud_eps2 = cl_eps2;
+  ta.cloud_minpts = cl_minpts;
+
+  if (densebox) {
+    st.mark("dense_cells");
+    densebox_cells(keys[cur], true, n, dim, xs, 0.0f, 0, at<int>(ws, plan.cell_id), at<int>(ws, plan.cell_start),
+                   at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense), at<float4>(ws, plan.cell_lo),
+                   at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag), at<int>(ws, plan.prim_of),
+                   at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt), at<float4>(ws, plan.prim_lo),
+                   at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key), at<int>(ws, plan.dense_list), lab,
+                   core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2);
+    st.mark("lbvh");
+    build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
+               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
+               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
+    batch_roots(offsets, num_clouds, n, at<int>(ws, plan.cand), misc + kMiscNumPrims, at<int>(ws, plan.other),
+                cl_root, cl_end, h->d_info, s);
+    ta.t.d_m = misc + kMiscNumPrims;
+    ta.prim_of = at<int>(ws, plan.prim_of);
+    ta.prim_start = at<int>(ws, plan.prim_start);
+    ta.prim_cnt = at<int>(ws, plan.prim_cnt);
+    ta.prim_lo = at<float4>(ws, plan.prim_lo);
+    ta.prim_hi = at<float4>(ws, plan.prim_hi);
+    ta.dense_list = at<int>(ws, plan.dense_list);
+    ta.d_ndense = misc + kMiscNumDense;
+  } else {
+    launch_init_labels(lab, n, s);
+    st.mark("lbvh");
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
+               at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
+               at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
+               nullptr, h->d_info, s);
+    batch_roots(offsets, num_clouds, n, nullptr, nullptr, at<int>(ws, plan.other), cl_root, cl_end, h->d_info, s);
+    ta.t.d_m = nullptr;
+  }
+  st.mark("core");
+  launch_core(ta, dim, densebox, s);
+  if (densebox) {
+    st.mark("main_cells");
+    launch_main(ta, dim, true, false, first_border, 1, s);
+    st.mark("main_points");
+    launch_main(ta, dim, true, false, first_border, 2, s);
+  } else {
+    st.mark("main");
+    launch_main(ta, dim, false, false, first_border, 0, s);
+  }
+  st.mark("finalize");
+  launch_finalize(lab, n, h->d_info, s);
+  st.mark("cluster_ids");
+  int* rank = at<int>(ws, plan.rank);
+  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<int>(ws, plan.lflag), rank,
+                at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false);
+  batch_cluster_ids(lab, core, at<int>(ws, plan.minorig), rank, pkeys, shift, offsets, num_clouds, n,
+                    misc + kMiscNumClusters, cl_flags, at<int>(ws, plan.cid), num_clusters, s);
+  if (!first_border) {
+    st.mark("border");
+    launch_border(ta, dim, densebox, s);
+  }
+  st.mark("scatter");
+  launch_scatter(lab, core, perm, at<int>(ws, plan.cid), at<int>(ws, plan.border), first_border, !first_border, n,
+                 labels, is_core, h->d_info, s);
+  st.finish();
+  return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
 }
 
 }  // extern "C"

@@ -33,10 +33,13 @@ struct Plan {
   // DenseBox
   size_t cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt,
       prim_lo, prim_hi, prim_key, dense_list;
+  // batches
+  int num_clouds = 0;
+  size_t cl_lo, cl_scale, cl_eps2, cl_minpts, cl_root, cl_end, cl_flags;
   int64_t sort_tiles = 0, scan_blocks = 0;
 };
 
-Plan make_plan(int64_t n, int dim, int algo);
+Plan make_plan(int64_t n, int dim, int algo, int num_clouds = 0);
 
 // Small device-side scalars kept in the workspace's misc block.
 enum MiscSlot : int {
@@ -99,7 +102,8 @@ void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, con
                     int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo,
                     float4* cell_hi, int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo,
                     float4* prim_hi, void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
-                    int* bsums, int64_t scan_blocks, hipStream_t s);
+                    int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift = 0,
+                    const int* cl_minpts = nullptr, const float* cl_eps2 = nullptr);
 
 // k_trav.hip
 struct TravArgs {
@@ -107,7 +111,7 @@ struct TravArgs {
   const float* xs;  // sorted SoA coordinates: x[n], y[n], z[n]
   int64_t n;
   float eps2;
-  float packet_ext2;  // a wavefront walks as one packet if its queries' box is at most this (squared extent)
+  float packet_ext_eps2;  // a wavefront walks as one packet if its queries' box extent^2 <= this * eps^2
   int packet_leaf;    // bucket size of packet walks (<= 64: a bucket is loaded one point per lane)
   int min_pts;
   int* labels;
@@ -122,6 +126,15 @@ struct TravArgs {
   const float4* prim_hi;
   const int* dense_list;  // dense-cell primitive indices
   const int* d_ndense;    // their number (device)
+  // batches (null pkeys = one cloud): cloud of sorted point i = pkeys[i] >> key_shift;
+  // per cloud: first node and last primitive of its subtree, eps^2, minPts
+  const uint64_t* pkeys;
+  int key_shift;
+  int num_clouds;
+  const int* cloud_root;
+  const int* cloud_end;
+  const float* cloud_eps2;
+  const int* cloud_minpts;
   uint32_t* info;  // FDB_INFO_* bits; kernels raise FDB_INFO_INTERNAL on a broken walk
   int block;
 };
@@ -137,11 +150,41 @@ void launch_init_labels(int* labels, int64_t n, hipStream_t s);
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s);
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
-                   int* lflag, int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s);
+                   int* lflag, int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
+                   bool ids = true);
+
+// k_batch.hip
+void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float* eps,
+                const int32_t* min_pts, int bpd, bool densebox, float4* cl_lo, float4* cl_scale, float* cl_eps2,
+                int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s);
+void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
+                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, hipStream_t s);
+void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,
+                 int* root, int* end, uint32_t* info, hipStream_t s);
+void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const int* rank,
+                       const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds, int64_t n,
+                       const int* total, const int* cl_flags, int* cid, int32_t* num_clusters, hipStream_t s);
 void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid,
                     const int* border, bool first_border, bool have_border, int64_t n, int32_t* out_labels,
                     uint8_t* out_core, uint32_t* info, hipStream_t s);
 void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums, int64_t blocks, int* d_total,
                  hipStream_t s);
+
+// k_serve.hip: one job of a served batch - its own buffers and its place in the
+// batch (first point off; first workgroup gblk of the gather and sblk of the
+// scatter, each workgroup moving kSegVec * 256 elements).
+constexpr int kSegVec = 4;
+struct JobSeg {
+  const float* points;
+  int32_t* labels;
+  uint8_t* core;
+  int64_t n;
+  int64_t off;
+  int32_t gblk, sblk;
+};
+int64_t seg_blocks(int64_t elems);
+void launch_gather(const JobSeg* seg, int num, int64_t total_blocks, int dim, float* dst, hipStream_t s);
+void launch_scatter_jobs(const JobSeg* seg, int num, int64_t total_blocks, const int32_t* labels,
+                         const uint8_t* core, hipStream_t s);
 
 }  // namespace fdb

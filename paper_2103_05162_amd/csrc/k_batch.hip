@@ -1,0 +1,280 @@
+// Batches of independent point clouds in one launch sequence. Every cloud keeps
+// its own eps and minPts; the result per cloud is the one a separate call
+// would give. Keys put the cloud id above the Morton bits, so one sort orders
+// all clouds and, in Karras' hierarchy, the points (or DenseBox primitives) of
+// one cloud - all keys sharing that prefix - form exactly one subtree: the node
+// whose range is the cloud's range, which is internal node first or last of
+// that range (a Karras node's index is one end of its range), or a leaf.
+#include "fdb_device.hpp"
+#include "fdb_internal.hpp"
+#include "fdbscan.h"
+
+namespace fdb {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kCloudNonfinite = 1, kCloudBadParams = 2, kCloudBadRange = 4;
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {  // 21 bits -> every third bit of 63
+  uint64_t x = v & 0x1fffffu;
+  x = (x | x << 32) & 0x001f00000000ffffull;
+  x = (x | x << 16) & 0x001f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint64_t spread2(uint32_t v) {  // 32 bits -> every other bit of 64
+  uint64_t x = v;
+  x = (x | x << 16) & 0x0000ffff0000ffffull;
+  x = (x | x << 8) & 0x00ff00ff00ff00ffull;
+  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | x << 2) & 0x3333333333333333ull;
+  x = (x | x << 1) & 0x5555555555555555ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t quantize(float v, float lo, float scale, uint32_t maxq) {
+  float t = fmaxf((v - lo) * scale, 0.0f);
+  float fmax = static_cast<float>(maxq);
+  return t >= fmax ? maxq : static_cast<uint32_t>(t);
+}
+
+// One workgroup per cloud: bounds, validity of its parameters, eps^2, and the
+// cloud's key scale (points normalised to its box, or DenseBox cells of side
+// eps/sqrt(d), slightly shrunk; the exactness guard covers any rounding).
+// Cloud c's range, clamped into [0, n] (offsets come from the caller's device
+// memory and cannot be checked on the host without waiting).
+__device__ __forceinline__ void cloud_range(const int64_t* off, int c, int64_t n, int64_t& b, int64_t& e) {
+  b = off[c];
+  e = off[c + 1];
+  b = b < 0 ? 0 : (b > n ? n : b);
+  e = e < b ? b : (e > n ? n : e);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cloud_prep(const float* __restrict__ pts, const int64_t* __restrict__ off,
+                                                       int num_clouds, int64_t n, const float* __restrict__ eps,
+                                                       const int32_t* __restrict__ mp, int bpd, int densebox,
+                                                       float4* __restrict__ cl_lo, float4* __restrict__ cl_scale,
+                                                       float* __restrict__ cl_eps2, int* __restrict__ cl_minpts,
+                                                       int* __restrict__ cl_flags, uint32_t* __restrict__ info) {
+  const int c = blockIdx.x;
+  int64_t b, e;
+  cloud_range(off, c, n, b, e);
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      float v = pts[i * D + k];
+      bad |= !isfinite(v);
+      lo[k] = fminf(lo[k], v);
+      hi[k] = fmaxf(hi[k], v);
+    }
+  }
+  __shared__ float s_lo[kBlock / 64][3], s_hi[kBlock / 64][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
+      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 3; ++k) {
+      s_lo[w][k] = lo[k];
+      s_hi[w][k] = hi[k];
+    }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int flags = s_bad ? kCloudNonfinite : 0;
+  if (off[c] != b || off[c + 1] != e || (c == 0 && b != 0) || (c == num_clouds - 1 && e != n)) flags |= kCloudBadRange;
+  for (int j = 1; j < kBlock / 64; ++j)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], s_lo[j][k]);
+      hi[k] = fmaxf(hi[k], s_hi[j][k]);
+    }
+  const float ec = eps[c];
+  const int mc = mp[c];
+  if (!(ec > 0.0f) || !isfinite(ec) || mc < 1) flags |= kCloudBadParams;
+  cl_flags[c] = flags;
+  if (flags & kCloudNonfinite) atomicOr(info, FDB_INFO_NONFINITE);
+  if (flags & (kCloudBadParams | kCloudBadRange)) atomicOr(info, FDB_INFO_BAD_PARAMS);
+  const float e2 = ec * ec;
+  cl_eps2[c] = e2;
+  cl_minpts[c] = mc;
+  const uint32_t maxq = (1u << bpd) - 1u;
+  float sc[3] = {0.0f, 0.0f, 0.0f};
+  for (int k = 0; k < D; ++k) {
+    if (!(lo[k] <= hi[k])) lo[k] = hi[k] = 0.0f;  // empty cloud
+    if (densebox) {
+      const double side = static_cast<double>(ec) / sqrt(static_cast<double>(D)) * (1.0 - 1.0 / 1048576.0);
+      sc[k] = side > 0.0 ? static_cast<float>(1.0 / side) : 0.0f;
+    } else {
+      const float ext = hi[k] - lo[k];
+      sc[k] = ext > 0.0f ? static_cast<float>(maxq) / ext : 0.0f;
+    }
+  }
+  cl_lo[c] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+  cl_scale[c] = make_float4(sc[0], sc[1], sc[2], 0.0f);
+}
+
+// Keys (cloud id << shift | Morton of the point's, or its cell's, coordinates)
+// and the identity permutation; one workgroup per cloud.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_batch_keys(const float* __restrict__ pts, const int64_t* __restrict__ off,
+                                                       int64_t n, const float4* __restrict__ cl_lo,
+                                                       const float4* __restrict__ cl_scale, int bpd, int shift,
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int c = blockIdx.x;
+  int64_t b, e;
+  cloud_range(off, c, n, b, e);
+  const float4 lo4 = cl_lo[c], sc4 = cl_scale[c];
+  const float lo[3] = {lo4.x, lo4.y, lo4.z}, sc[3] = {sc4.x, sc4.y, sc4.z};
+  const uint32_t maxq = (1u << bpd) - 1u;
+  const uint64_t prefix = static_cast<uint64_t>(c) << shift;
+  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
+    uint32_t q[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) q[k] = quantize(pts[i * D + k], lo[k], sc[k], maxq);
+    uint64_t code;
+    if constexpr (D == 3)
+      code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    else
+      code = (spread2(q[0]) << 1) | spread2(q[1]);
+    keys[i] = prefix | code;
+    vals[i] = static_cast<uint32_t>(i);
+  }
+}
+
+// Subtree of each cloud: its primitive range [a, b] and the node covering it.
+// FDbscan primitives are points (the range is the cloud's own); DenseBox
+// primitive ranges come from the primitive index of each cloud's first point
+// (a cloud's first point always opens a primitive: cells never span clouds).
+__global__ __launch_bounds__(kBlock) void k_cloud_roots(const int64_t* __restrict__ off, int num_clouds, int64_t n,
+                                                        const int* __restrict__ pidx, const int* __restrict__ d_m,
+                                                        const int* __restrict__ other, int* __restrict__ root,
+                                                        int* __restrict__ end, uint32_t* __restrict__ info) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= num_clouds) return;
+  int64_t b, e;
+  cloud_range(off, c, n, b, e);
+  if (e <= b) {  // empty cloud: no queries ever reach it
+    root[c] = static_cast<int>(kEnd);
+    end[c] = -1;
+    return;
+  }
+  int pa, pb;
+  if (pidx) {
+    const int m = *d_m;
+    pa = pidx[b];
+    pb = e < n ? pidx[e] - 1 : m - 1;
+  } else {
+    pa = static_cast<int>(b);
+    pb = static_cast<int>(e - 1);
+  }
+  end[c] = pb;
+  if (pa == pb) {
+    root[c] = static_cast<int>(kLeaf | static_cast<uint32_t>(pa));
+  } else if (other[pa] == pb) {
+    root[c] = pa;
+  } else if (other[pb] == pa) {
+    root[c] = pb;
+  } else {
+    atomicOr(info, kInternalBit);
+    root[c] = static_cast<int>(kEnd);
+  }
+}
+
+// Per-cloud cluster ids: rank is the exclusive scan, in input order, of the
+// flags marking each cluster's smallest core input index, so a cloud's ids are
+// rank minus the rank at its first input index, and its K the rank difference
+// across the cloud.
+__device__ __forceinline__ int rank_at(const int* rank, int64_t x, int64_t n, const int* total) {
+  return x < n ? rank[x] : *total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_cluster_ids(const int* __restrict__ labels,
+                                                              const uint8_t* __restrict__ core,
+                                                              const int* __restrict__ minorig,
+                                                              const int* __restrict__ rank,
+                                                              const uint64_t* __restrict__ pkeys, int shift,
+                                                              const int64_t* __restrict__ off, int num_clouds,
+                                                              int64_t n, const int* __restrict__ total,
+                                                              int* __restrict__ cid) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    if (!(core[i] && labels[i] == i)) continue;
+    const int c = min(static_cast<int>(pkeys[i] >> shift), num_clouds - 1);
+    int64_t b, e;
+    cloud_range(off, c, n, b, e);
+    cid[i] = rank[minorig[i]] - rank_at(rank, b, n, total);
+  }
+}
+
+// K per cloud, or -1 where the cloud's labels are undefined (a coordinate that
+// is not finite, eps or minPts out of range, offsets out of order).
+__global__ __launch_bounds__(kBlock) void k_batch_counts(const int* __restrict__ rank, const int64_t* __restrict__ off,
+                                                         int num_clouds, int64_t n, const int* __restrict__ total,
+                                                         const int* __restrict__ cl_flags,
+                                                         int32_t* __restrict__ num_clusters) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= num_clouds) return;
+  int64_t b, e;
+  cloud_range(off, c, n, b, e);
+  num_clusters[c] = cl_flags[c] ? -1 : rank_at(rank, e, n, total) - rank_at(rank, b, n, total);
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = ceil_div(n, kBlock * 4);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return static_cast<int>(g);
+}
+
+}  // namespace
+
+void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float* eps,
+                const int32_t* min_pts, int bpd, bool densebox, float4* cl_lo, float4* cl_scale, float* cl_eps2,
+                int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_cloud_prep<3>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, num_clouds, n, eps, min_pts,
+                       bpd, densebox ? 1 : 0, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
+  else
+    hipLaunchKernelGGL(k_cloud_prep<2>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, num_clouds, n, eps, min_pts,
+                       bpd, densebox ? 1 : 0, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
+}
+
+void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
+                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_batch_keys<3>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
+                       shift, keys, vals);
+  else
+    hipLaunchKernelGGL(k_batch_keys<2>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
+                       shift, keys, vals);
+}
+
+void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,
+                 int* root, int* end, uint32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_cloud_roots, dim3(static_cast<unsigned>(ceil_div(num_clouds, kBlock))), dim3(kBlock), 0, s,
+                     off, num_clouds, n, pidx, d_m, other, root, end, info);
+}
+
+void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const int* rank,
+                       const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds, int64_t n,
+                       const int* total, const int* cl_flags, int* cid, int32_t* num_clusters, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_cluster_ids, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, minorig, rank, pkeys,
+                     shift, off, num_clouds, n, total, cid);
+  if (num_clusters)
+    hipLaunchKernelGGL(k_batch_counts, dim3(static_cast<unsigned>(ceil_div(num_clouds, kBlock))), dim3(kBlock), 0, s,
+                       rank, off, num_clouds, n, total, cl_flags, num_clusters);
+}
+
+}  // namespace fdb

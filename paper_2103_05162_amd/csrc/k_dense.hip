@@ -38,15 +38,30 @@ __global__ __launch_bounds__(kBlock) void k_cell_start(const int* __restrict__ h
   if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[*num_cells] = static_cast<int>(n);
 }
 
+// Per-cloud parameters of a batch (null cl_minpts: one cloud with the scalars).
+struct CloudParams {
+  const uint64_t* keys;  // sorted point keys; cloud = key >> shift
+  int shift;
+  const int* minpts;
+  const float* eps2;
+};
+
+__device__ __forceinline__ int cell_minpts(const CloudParams& cp, int head, int min_pts) {
+  return cp.minpts ? cp.minpts[cp.keys[head] >> cp.shift] : min_pts;
+}
+__device__ __forceinline__ float cell_eps2(const CloudParams& cp, int head, float eps2) {
+  return cp.eps2 ? cp.eps2[cp.keys[head] >> cp.shift] : eps2;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cell_candidates(const int* __restrict__ cell_start,
                                                             const int* __restrict__ num_cells, int min_pts,
-                                                            int* __restrict__ cand, int* __restrict__ num_cand,
-                                                            uint8_t* __restrict__ dense) {
+                                                            CloudParams cp, int* __restrict__ cand,
+                                                            int* __restrict__ num_cand, uint8_t* __restrict__ dense) {
   const int nc = *num_cells;
   for (int c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
     int cnt = cell_start[c + 1] - cell_start[c];
     dense[c] = 0;
-    if (cnt >= min_pts) cand[atomicAdd(num_cand, 1)] = c;
+    if (cnt >= cell_minpts(cp, cell_start[c], min_pts)) cand[atomicAdd(num_cand, 1)] = c;
   }
 }
 
@@ -54,9 +69,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_candidates(const int* __restric
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__ xs, int64_t n,
                                                        const int* __restrict__ cell_start, const int* __restrict__ cand,
-                                                       const int* __restrict__ num_cand, float eps2,
-                                                       uint8_t* __restrict__ dense, float4* __restrict__ cell_lo,
-                                                       float4* __restrict__ cell_hi) {
+                                                       const int* __restrict__ num_cand, float eps2_all,
+                                                       CloudParams cp, uint8_t* __restrict__ dense,
+                                                       float4* __restrict__ cell_lo, float4* __restrict__ cell_hi) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * kBlock) >> 6;
@@ -81,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__
       }
     if (lane == 0) {
       if (D == 2) lo[2] = hi[2] = 0.0f;
+      const float eps2 = cell_eps2(cp, s, eps2_all);
       bool ok = dist2v<D>(hi[0], hi[1], hi[2], lo[0], lo[1], lo[2]) <= eps2;
       dense[c] = ok ? 1 : 0;
       cell_lo[c] = make_float4(lo[0], lo[1], lo[2], 0.0f);
@@ -154,7 +170,8 @@ template <typename K>
 void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
              int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag, int* prim_of,
              int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* dense_list,
-             int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, hipStream_t s) {
+             int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, const CloudParams& cp,
+             hipStream_t s) {
   int* d_cells = misc + kMiscNumCells;
   int* d_cand = misc + kMiscNumCand;
   int* d_prims = misc + kMiscNumPrims;
@@ -164,15 +181,15 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   device_scan(pflag, cell_id, n, nullptr, bsums, scan_blocks, d_cells, s);
   hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(kBlock), 0, s, pflag, n, cell_id, cell_start, d_cells);
   fill_u32(reinterpret_cast<uint32_t*>(d_cand), 0, 1, s);
-  hipLaunchKernelGGL(k_cell_candidates, dim3(g), dim3(kBlock), 0, s, cell_start, d_cells, min_pts, cand, d_cand,
+  hipLaunchKernelGGL(k_cell_candidates, dim3(g), dim3(kBlock), 0, s, cell_start, d_cells, min_pts, cp, cand, d_cand,
                      dense);
   const int gb = 2048;  // 8192 wavefronts, grid-stride over candidate cells
   if (dim == 3)
-    hipLaunchKernelGGL(k_cell_boxes<3>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, dense,
-                       cell_lo, cell_hi);
+    hipLaunchKernelGGL(k_cell_boxes<3>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+                       dense, cell_lo, cell_hi);
   else
-    hipLaunchKernelGGL(k_cell_boxes<2>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, dense,
-                       cell_lo, cell_hi);
+    hipLaunchKernelGGL(k_cell_boxes<2>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+                       dense, cell_lo, cell_hi);
   hipLaunchKernelGGL(k_prim_flags, dim3(g), dim3(kBlock), 0, s, cell_id, cell_start, dense, n, pflag);
   int* pidx = cand;  // candidates are no longer needed; reuse for primitive indices
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
@@ -192,15 +209,16 @@ void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, con
                     int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo, float4* cell_hi,
                     int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
                     void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc, int* bsums,
-                    int64_t scan_blocks, hipStream_t s) {
+                    int64_t scan_blocks, hipStream_t s, int key_shift, const int* cl_minpts, const float* cl_eps2) {
+  CloudParams cp{static_cast<const uint64_t*>(sorted_keys), key_shift, cl_minpts, cl_eps2};
   if (key64)
     cells_t(static_cast<const uint64_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
             cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint64_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, s);
+            static_cast<uint64_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
   else
     cells_t(static_cast<const uint32_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
             cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint32_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, s);
+            static_cast<uint32_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
 }
 
 }  // namespace fdb

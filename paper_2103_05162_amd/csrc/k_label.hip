@@ -248,13 +248,13 @@ void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_
 }
 
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig, int* lflag,
-                   int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s) {
+                   int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s, bool ids) {
   const int g = grid_for(n);
   fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
   hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
   hipLaunchKernelGGL(k_leaders, dim3(g), dim3(kBlock), 0, s, labels, core, perm, minorig, n, lflag);
   device_scan(lflag, rank, n, nullptr, bsums, scan_blocks, d_k, s);
-  hipLaunchKernelGGL(k_cluster_ids, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, rank, n, cid);
+  if (ids) hipLaunchKernelGGL(k_cluster_ids, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, rank, n, cid);
 }
 
 void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid, const int* border,

@@ -1,14 +1,19 @@
-// Traversal kernels: one thread per query point in Morton order (Section 4.1),
+// Traversal kernels: one query per lane in Morton order (Section 4.1),
 // stack-less top-down walks over the LBVH using escape links.
 //   core   - preprocessing: count neighbours, stop at minPts (Section 3.2).
 //   main   - the fused phase: union (or claim) on discovery, nothing stored
-//            (Algorithm 3); the walk is masked so thread i only reaches
+//            (Algorithm 3); the walk is masked so query i only reaches
 //            primitives above its own, handling every pair once (Section 4.1,
 //            Figure 1).
 //   border - canonical labels: a non-core point takes the smallest cluster id
 //            among its core neighbours.
 // DenseBox variants (Section 4.2) walk a tree over dense-cell boxes plus the
 // points outside dense cells; a box hit scans the cell's points.
+//
+// Every walk has a scope: the subtree it starts from, the last primitive of
+// that subtree, eps^2 and minPts. A single cloud's scope is the whole tree; in
+// a batch the keys carry the cloud id above the Morton bits, so each cloud is
+// one subtree, and a query's scope is its cloud's (with its own eps, minPts).
 #include "fdb_device.hpp"
 #include "fdb_internal.hpp"
 
@@ -18,6 +23,13 @@ namespace {
 
 struct Query {
   float x, y, z;
+};
+
+struct Scope {
+  uint32_t start;  // first node of the walk (internal node, or kLeaf | leaf)
+  int end;         // last primitive of the subtree
+  float eps2;
+  int min_pts;
 };
 
 template <int D>
@@ -35,22 +47,48 @@ __device__ __forceinline__ bool near(const float* __restrict__ xs, int64_t n, in
   return dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2;
 }
 
-// Walk the tree, calling visit(prim) for every primitive whose leaf (or bucket)
-// the walk reaches; visit returns true to stop. With MASKED, subtrees whose
-// primitives all have index <= mask are never entered: at a node whose left
-// child ends at or below the mask, the walk goes straight to the right child,
-// and buckets start above the mask. Every node the walk reaches then holds a
-// primitive above the mask.
+__device__ __forceinline__ int tree_m(const TreeView& t) { return t.d_m ? *t.d_m : t.m_cap; }
+
+__device__ __forceinline__ int cloud_of(const TravArgs& a, int i) {
+  return min(static_cast<int>(a.pkeys[i] >> a.key_shift), a.num_clouds - 1);
+}
+
+// Scope of the query at sorted point index i.
+template <bool BATCHED>
+__device__ __forceinline__ Scope scope_of(const TravArgs& a, int m, int i) {
+  Scope s;
+  if (BATCHED) {
+    const int c = cloud_of(a, i);
+    s.start = static_cast<uint32_t>(a.cloud_root[c]);
+    s.end = a.cloud_end[c];
+    s.eps2 = a.cloud_eps2[c];
+    s.min_pts = a.cloud_minpts[c];
+  } else {
+    s.start = m == 1 ? kLeaf : 0u;
+    s.end = m - 1;
+    s.eps2 = a.eps2;
+    s.min_pts = a.min_pts;
+  }
+  return s;
+}
+
+// Walk the subtree of sc, calling visit(prim) for every primitive whose leaf
+// (or bucket) the walk reaches; visit returns true to stop. With MASKED,
+// subtrees whose primitives all have index <= mask are never entered: at a node
+// whose left child ends at or below the mask, the walk goes straight to the
+// right child, and buckets start above the mask. Every node the walk reaches
+// then holds a primitive above the mask. The walk ends where an escape link
+// would leave the subtree (past primitive sc.end).
 //
 // A pre-order walk reaches each node at most once, so more than 2m steps, or a
 // reference outside the tree, means the tree is broken: the walk then stops and
 // raises the internal-error bit instead of looping or reading out of bounds.
 template <int D, bool MASKED, typename F>
-__device__ __forceinline__ void traverse(const TreeView& t, int m, const Query& q, float eps2, int mask,
+__device__ __forceinline__ void traverse(const TreeView& t, int m, const Scope& sc, const Query& q, int mask,
                                          uint32_t* info, F&& visit) {
   if (m <= 0) return;
-  if (MASKED && mask >= m - 1) return;
-  uint32_t node = m == 1 ? kLeaf : 0u;
+  if (MASKED && mask >= sc.end) return;
+  uint32_t node = sc.start;
   int64_t steps = 0;
   const int64_t max_steps = 2 * int64_t(m) + 2;
   while (node != kEnd) {
@@ -64,7 +102,7 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Query& 
         atomicOr(info, kInternalBit);
         return;
       }
-      if (visit(l)) return;
+      if (visit(l) || l >= sc.end) return;
       node = static_cast<uint32_t>(t.leaf_rope[l]);
       continue;
     }
@@ -72,15 +110,16 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Query& 
       atomicOr(info, kInternalBit);
       return;
     }
-    float4 a = t.node_a[node];
-    float4 b = t.node_b[node];
-    if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > eps2) {
+    const float4 a = t.node_a[node];
+    const float4 b = t.node_b[node];
+    const int k = static_cast<int>(node);
+    const int o = __float_as_int(a.w), g = __float_as_int(b.w);
+    const int first = o < k ? o : k, last = o > k ? o : k;
+    if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > sc.eps2) {
+      if (last >= sc.end) return;
       node = static_cast<uint32_t>(t.rope[node]);
       continue;
     }
-    int k = static_cast<int>(node);
-    int o = __float_as_int(a.w), g = __float_as_int(b.w);
-    int first = o < k ? o : k, last = o > k ? o : k;
     if (first < 0 || last >= m || g < first || g >= last) {
       atomicOr(info, kInternalBit);
       return;
@@ -90,10 +129,70 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Query& 
       if (MASKED && s <= mask) s = mask + 1;
       for (int l = s; l <= last; ++l)
         if (visit(l)) return;
+      if (last >= sc.end) return;
       node = static_cast<uint32_t>(t.rope[node]);
       continue;
     }
     if (MASKED && g <= mask)
+      node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+    else
+      node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+  }
+}
+
+// Wave-uniform walk for a box query (every point of box [lo,hi]), masked like
+// traverse(): visit(first, last) is called with the same primitive range on
+// every lane, for each bucket (a subtree of at most leaf_size primitives, cut
+// to primitives above the mask) and each single leaf the walk reaches.
+template <int D, typename F>
+__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Scope& sc, const float* lo,
+                                             const float* hi, int mask, int leaf_size, uint32_t* info, F&& visit) {
+  if (m <= 0 || mask >= sc.end) return;
+  uint32_t node = sc.start;
+  int64_t steps = 0;
+  const int64_t max_steps = 2 * int64_t(m) + 2;
+  while (node != kEnd) {
+    node = __builtin_amdgcn_readfirstlane(node);
+    if (++steps > max_steps) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (node & kLeaf) {
+      int l = static_cast<int>(node & ~kLeaf);
+      if (l >= m) {
+        atomicOr(info, kInternalBit);
+        return;
+      }
+      if (visit(l, l) || l >= sc.end) return;
+      node = static_cast<uint32_t>(t.leaf_rope[l]);
+      continue;
+    }
+    if (node >= static_cast<uint32_t>(m - 1)) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    const float4 na = t.node_a[node];
+    const float4 nb = t.node_b[node];
+    const int k = static_cast<int>(node);
+    const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
+    const int first = o < k ? o : k, last = o > k ? o : k;
+    if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > sc.eps2) {
+      if (last >= sc.end) return;
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    if (first < 0 || last >= m || g < first || g >= last) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    if (last - first < leaf_size) {
+      int s = first <= mask ? mask + 1 : first;
+      if (s <= last && visit(s, last)) return;
+      if (last >= sc.end) return;
+      node = static_cast<uint32_t>(t.rope[node]);
+      continue;
+    }
+    if (g <= mask)
       node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
     else
       node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
@@ -119,126 +218,58 @@ __device__ __forceinline__ bool known_same_set(int* labels, int x, int root) {
   return false;
 }
 
-__device__ __forceinline__ int tree_m(const TreeView& t) { return t.d_m ? *t.d_m : t.m_cap; }
-
-// Wave-uniform walk for a box query (every point of box [lo,hi]), masked like
-// traverse(): visit(first, last) is called with the same primitive range on
-// every lane, for each bucket (a subtree of at most leaf_size primitives, cut
-// to primitives above the mask) and each single leaf the walk reaches.
-template <int D, typename F>
-__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const float* lo, const float* hi, float eps2,
-                                             int mask, int leaf_size, uint32_t* info, F&& visit) {
-  if (m <= 0 || mask >= m - 1) return;
-  uint32_t node = m == 1 ? kLeaf : 0u;
-  int64_t steps = 0;
-  const int64_t max_steps = 2 * int64_t(m) + 2;
-  while (node != kEnd) {
-    node = __builtin_amdgcn_readfirstlane(node);
-    if (++steps > max_steps) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    if (node & kLeaf) {
-      int l = static_cast<int>(node & ~kLeaf);
-      if (l >= m) {
-        atomicOr(info, kInternalBit);
-        return;
-      }
-      if (visit(l, l)) return;
-      node = static_cast<uint32_t>(t.leaf_rope[l]);
-      continue;
-    }
-    if (node >= static_cast<uint32_t>(m - 1)) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    float4 na = t.node_a[node];
-    float4 nb = t.node_b[node];
-    if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > eps2) {
-      node = static_cast<uint32_t>(t.rope[node]);
-      continue;
-    }
-    int k = static_cast<int>(node);
-    int o = __float_as_int(na.w), g = __float_as_int(nb.w);
-    int first = o < k ? o : k, last = o > k ? o : k;
-    if (first < 0 || last >= m || g < first || g >= last) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    if (last - first < leaf_size) {
-      int s = first <= mask ? mask + 1 : first;
-      if (s <= last && visit(s, last)) return;
-      node = static_cast<uint32_t>(t.rope[node]);
-      continue;
-    }
-    if (g <= mask)
-      node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
-    else
-      node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
-  }
-}
-
 __device__ __forceinline__ float readlane_f(float v, int k) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
 // ---------------------------------------------------------------- FDbscan ----
 
-template <int D>
+template <int D, bool B>
 __global__ void k_core_fdb(TravArgs a) {
-  int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
-  if (i < 0) return;
-  if (i >= a.n) return;
+  const int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  if (i < 0 || i >= a.n) return;
+  const int m = tree_m(a.t);
+  const Scope sc = scope_of<B>(a, m, static_cast<int>(i));
   const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
-  const int need = a.min_pts;
   int cnt = 0;
-  traverse<D, false>(a.t, tree_m(a.t), q, eps2, 0, a.info, [&](int j) {
-    if (near<D>(a.xs, a.n, j, q, eps2)) return ++cnt >= need;
+  traverse<D, false>(a.t, m, sc, q, 0, a.info, [&](int j) {
+    if (near<D>(a.xs, a.n, j, q, sc.eps2)) return ++cnt >= sc.min_pts;
     return false;
   });
-  a.core[i] = cnt >= need ? 1 : 0;
+  a.core[i] = cnt >= sc.min_pts ? 1 : 0;
 }
 
-// Fused main phase. A wavefront whose 64 queries (consecutive in Morton order)
-// lie within a small box walks the tree once for the whole group ("packet"):
-// each candidate point is loaded once for all lanes and each lane tests it
-// against its own query (and j > i, so every pair is still seen once). A
-// candidate already in the lane's set needs no test: the union would change
-// nothing. Wavefronts whose queries are spread out walk per lane.
-template <int D, bool ALL_CORE, bool FIRST>
-__device__ __forceinline__ void main_pair(const TravArgs& a, int i, bool ci, int j, bool cj, int& root,
-                                          bool& done) {
+// First-claim main phase (the paper's border rule): per-lane walks, or a packet
+// walk when the wavefront's queries lie in a small box. In a packet each lane
+// still decides its own pairs.
+__device__ __forceinline__ void main_pair_first(const TravArgs& a, int i, bool ci, int j, bool cj, int& root,
+                                                bool& done) {
   int* labels = a.labels;
   if (ci && cj) {
     if (!known_same_set(labels, j, root)) root = uf_union(labels, root, j, a.info);
-    return;
-  }
-  if (FIRST) {
-    if (ci) {
-      uf_claim(labels, j, i);
-    } else if (cj) {
-      uf_claim(labels, i, j);
-      done = true;  // i is a member now (by this or an earlier claim)
-    }
+  } else if (ci) {
+    uf_claim(labels, j, i);
+  } else if (cj) {
+    uf_claim(labels, i, j);
+    done = true;  // i is a member now (by this or an earlier claim)
   }
 }
 
-template <int D, bool ALL_CORE, bool FIRST>
-__global__ void k_main_fdb(TravArgs a) {
+template <int D, bool B>
+__global__ void k_main_fdb_first(TravArgs a) {
   const int64_t i64 = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
   const bool valid = i64 >= 0 && i64 < a.n;
   const int i = valid ? static_cast<int>(i64) : 0;
-  const bool ci = valid && (ALL_CORE || a.core[i]);
-  const bool mine = valid && (FIRST || ci);  // canonical mode: border points are settled later
-  const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
+  const bool ci = valid && a.core[i];
+  const bool mine = valid;
   const int m = tree_m(a.t);
-  int* labels = a.labels;
+  const Scope sc = scope_of<B>(a, m, i);
+  const Query q = load_point<D>(a.xs, a.n, i);
   int root = i;
   bool done = !mine;
-
-  // group box of this wavefront's queries
+  const uint64_t any_mine = ballot(mine);
+  if (!any_mine) return;
+  const int first_lane = __ffsll(static_cast<unsigned long long>(any_mine)) - 1;
   float lo[3], hi[3];
   lo[0] = mine ? q.x : INFINITY; hi[0] = mine ? q.x : -INFINITY;
   lo[1] = mine ? q.y : INFINITY; hi[1] = mine ? q.y : -INFINITY;
@@ -249,99 +280,205 @@ __global__ void k_main_fdb(TravArgs a) {
       lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
       hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
     }
-  const uint64_t any_mine = ballot(mine);
-  if (!any_mine) return;
   float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
   if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
-  const bool packet = ext * ext <= a.packet_ext2;
-
-  if (packet) {
+  const int c0 = B ? __shfl(cloud_of(a, i), first_lane) : 0;
+  const bool one_cloud = !B || !ballot(mine && cloud_of(a, i) != c0);
+  const int i0 = __shfl(i, first_lane);
+  const Scope ps = scope_of<B>(a, m, i0);
+  if (one_cloud && ext * ext <= a.packet_ext_eps2 * ps.eps2) {
     const int lane = lane_id();
-    const int first_lane = __ffsll(static_cast<unsigned long long>(any_mine)) - 1;
-    const int i0 = __shfl(i, first_lane);
-    // The wavefront's own queries are the sorted range [p0, p1].
-    const int p0 = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x & ~63, a.n));
-    const int p1 = p0 + 63;
-    bool common = false;
-    int r = 0;
-    if (!FIRST) {
-      // Phase A: pairs inside the packet, lane against lane.
-      for (int k = 0; k < 64; ++k) {
-        if (!((any_mine >> k) & 1)) continue;
-        const int jk = p0 + k;
-        const float px = readlane_f(q.x, k), py = readlane_f(q.y, k), pz = readlane_f(q.z, k);
-        if (mine && jk > i && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 && !known_same_set(labels, jk, root))
-          root = uf_union(labels, root, jk, a.info);
-      }
-      // One root for every query of the packet? Then a candidate already in that
-      // set needs no test, and a hit needs one union for the whole packet.
-      if (mine) root = uf_find(labels, root, a.info);
-      r = __shfl(root, first_lane);
-      common = !ballot(mine && root != r);
-    }
-    traverse_box<D>(a.t, m, lo, hi, eps2, i0, a.packet_leaf, a.info, [&](int s, int e) {
-      // the lanes load the bucket's points once; each is then broadcast to all
+    traverse_box<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, [&](int s, int e) {
       const int cnt = e - s + 1;  // <= packet_leaf <= 64
       float cx = 0.0f, cy = 0.0f, cz = 0.0f;
-      int cc = 0, cl = 0;
+      int cc = 0;
       if (lane < cnt) {
         const int j = s + lane;
         cx = a.xs[j];
         cy = a.xs[a.n + j];
         cz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
-        cc = (ALL_CORE || a.core[j]) ? 1 : 0;
-        cl = labels[j];
+        cc = a.core[j] ? 1 : 0;
       }
       for (int k = 0; k < cnt; ++k) {
         const int j = s + k;
         const bool cj = __builtin_amdgcn_readlane(cc, k) != 0;
-        if (!FIRST && !cj) continue;
-        const int lj = __builtin_amdgcn_readlane(cl, k);
-        if (!FIRST) {
-          if (j <= p1) continue;  // inside the packet: done in phase A (j > i0 by the mask)
-          if (common) {
-            if (lj == r) continue;
-            const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
-            const uint64_t hit = ballot(mine && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2);
-            if (!hit) continue;
-            const int leader = __ffsll(static_cast<unsigned long long>(hit)) - 1;
-            int nr = r;
-            if (lane == leader && !known_same_set(labels, j, r)) nr = uf_union(labels, r, j, a.info);
-            r = __shfl(nr, leader);
-            continue;
-          }
-        }
-        bool act = !done && j > i;
-        if (act && ci && cj && lj == root) act = false;  // already one set
+        const bool act = !done && j > i;
         if (!ballot(act)) continue;
         const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
-        if (act && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2)
-          main_pair<D, ALL_CORE, FIRST>(a, i, ci, j, cj, root, done);
+        if (act && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= ps.eps2) main_pair_first(a, i, ci, j, cj, root, done);
       }
       return false;
     });
     return;
   }
   if (!mine) return;
-  traverse<D, true>(a.t, m, q, eps2, i, a.info, [&](int j) {
-    if (!near<D>(a.xs, a.n, j, q, eps2)) return false;
-    const bool cj = ALL_CORE || a.core[j];
-    main_pair<D, ALL_CORE, FIRST>(a, i, ci, j, cj, root, done);
+  traverse<D, true>(a.t, m, sc, q, i, a.info, [&](int j) {
+    if (!near<D>(a.xs, a.n, j, q, sc.eps2)) return false;
+    main_pair_first(a, i, ci, j, a.core[j] != 0, root, done);
     return done;
   });
 }
 
-template <int D>
+// Canonical (and minPts <= 2) main phase, Q queries per lane: a wavefront owns
+// 64*Q consecutive queries. When they lie in a small box (and, in a batch, in
+// one cloud) they walk as one packet: the lanes load a bucket of candidates
+// once and broadcast it. Phase A unions the packet's own pairs; if then every
+// query shares one root r, a candidate whose label is r is skipped untested and
+// a candidate within eps of any query costs one union for the whole packet.
+template <int D, bool ALL_CORE, bool B, int Q>
+__global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
+  const int lane = lane_id();
+  const int64_t bbase = xcd_spread(blockIdx.x, 256 * Q, 0, a.n);
+  if (bbase < 0) return;
+  const int64_t base = bbase + int64_t(threadIdx.x >> 6) * 64 * Q;  // this wavefront's first query
+  if (base >= a.n) return;
+  const int m = tree_m(a.t);
+  int* labels = a.labels;
+  int idx[Q], root[Q];
+  bool mine[Q];
+  Query q[Q];
+  uint64_t mm[Q];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int s = 0; s < Q; ++s) {
+    const int64_t i64 = base + s * 64 + lane;
+    const bool valid = i64 < a.n;
+    idx[s] = valid ? static_cast<int>(i64) : 0;
+    mine[s] = valid && (ALL_CORE || a.core[idx[s]]);
+    q[s] = load_point<D>(a.xs, a.n, idx[s]);
+    root[s] = idx[s];
+    if (mine[s]) {
+      lo[0] = fminf(lo[0], q[s].x); hi[0] = fmaxf(hi[0], q[s].x);
+      lo[1] = fminf(lo[1], q[s].y); hi[1] = fmaxf(hi[1], q[s].y);
+      lo[2] = fminf(lo[2], q[s].z); hi[2] = fmaxf(hi[2], q[s].z);
+    }
+    mm[s] = ballot(mine[s]);
+  }
+  uint64_t any = 0;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) any |= mm[s];
+  if (!any) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+    }
+  float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
+  if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
+  int first_slot = 0;
+#pragma unroll
+  for (int s = Q - 1; s >= 0; --s)
+    if (mm[s]) first_slot = s;
+  const int fl = __ffsll(static_cast<unsigned long long>(mm[first_slot])) - 1;
+  const int i0 = static_cast<int>(base) + first_slot * 64 + fl;
+  const Scope ps = scope_of<B>(a, m, i0);
+  bool other_cloud = false;
+  if (B) {
+#pragma unroll
+    for (int s = 0; s < Q; ++s) other_cloud |= mine[s] && cloud_of(a, idx[s]) != cloud_of(a, i0);
+  }
+  const bool packet = !ballot(other_cloud) && ext * ext <= a.packet_ext_eps2 * ps.eps2;
+
+  if (!packet) {  // spread out: every query walks on its own
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      if (!mine[s]) continue;
+      const int i = idx[s];
+      const Query qs = q[s];
+      const Scope sc = scope_of<B>(a, m, i);
+      int rs = root[s];
+      traverse<D, true>(a.t, m, sc, qs, i, a.info, [&](int j) {
+        if (!near<D>(a.xs, a.n, j, qs, sc.eps2)) return false;
+        if (!(ALL_CORE || a.core[j])) return false;
+        if (!known_same_set(labels, j, rs)) rs = uf_union(labels, rs, j, a.info);
+        return false;
+      });
+    }
+    return;
+  }
+  const float eps2 = ps.eps2;
+
+  // Phase A: pairs inside the packet.
+#pragma unroll
+  for (int ks = 0; ks < Q; ++ks) {
+    for (int kl = 0; kl < 64; ++kl) {
+      if (!((mm[ks] >> kl) & 1)) continue;
+      const int jk = static_cast<int>(base) + ks * 64 + kl;
+      const float px = readlane_f(q[ks].x, kl), py = readlane_f(q[ks].y, kl), pz = readlane_f(q[ks].z, kl);
+#pragma unroll
+      for (int s = 0; s < Q; ++s)
+        if (mine[s] && jk > idx[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2 &&
+            !known_same_set(labels, jk, root[s]))
+          root[s] = uf_union(labels, root[s], jk, a.info);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < Q; ++s)
+    if (mine[s]) root[s] = uf_find(labels, root[s], a.info);
+  int rl = 0;
+#pragma unroll
+  for (int s = 0; s < Q; ++s)
+    if (s == first_slot) rl = root[s];
+  int r = __shfl(rl, fl);
+  bool differ = false;
+#pragma unroll
+  for (int s = 0; s < Q; ++s) differ |= mine[s] && root[s] != r;
+  const bool common = !ballot(differ);
+  const int p1 = static_cast<int>(base) + 64 * Q - 1;
+
+  traverse_box<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, [&](int s0, int e0) {
+    const int cnt = e0 - s0 + 1;  // <= packet_leaf <= 64
+    float cx = 0.0f, cy = 0.0f, cz = 0.0f;
+    int cc = 0, cl = 0;
+    if (lane < cnt) {
+      const int j = s0 + lane;
+      cx = a.xs[j];
+      cy = a.xs[a.n + j];
+      cz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
+      cc = (ALL_CORE || a.core[j]) ? 1 : 0;
+      cl = labels[j];
+    }
+    for (int k = 0; k < cnt; ++k) {
+      const int j = s0 + k;
+      if (j <= p1) continue;  // inside the packet: phase A (and j > i0 by the mask)
+      if (!__builtin_amdgcn_readlane(cc, k)) continue;
+      const int lj = __builtin_amdgcn_readlane(cl, k);
+      if (common && lj == r) continue;
+      const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
+      if (common) {
+        bool h = false;
+#pragma unroll
+        for (int s = 0; s < Q; ++s) h |= mine[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2;
+        const uint64_t hit = ballot(h);
+        if (!hit) continue;
+        const int leader = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+        int nr = r;
+        if (lane == leader && !known_same_set(labels, j, r)) nr = uf_union(labels, r, j, a.info);
+        r = __shfl(nr, leader);
+      } else {
+#pragma unroll
+        for (int s = 0; s < Q; ++s)
+          if (mine[s] && lj != root[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2 &&
+              !known_same_set(labels, j, root[s]))
+            root[s] = uf_union(labels, root[s], j, a.info);
+      }
+    }
+    return false;
+  });
+}
+
+template <int D, bool B>
 __global__ void k_border_fdb(TravArgs a) {
-  int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
-  if (i < 0) return;
-  if (i >= a.n) return;
+  const int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  if (i < 0 || i >= a.n) return;
   if (a.core[i]) return;
+  const int m = tree_m(a.t);
+  const Scope sc = scope_of<B>(a, m, static_cast<int>(i));
   const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
   int best = 0x7fffffff;
-  traverse<D, false>(a.t, tree_m(a.t), q, eps2, 0, a.info, [&](int j) {
-    if (!a.core[j] || !near<D>(a.xs, a.n, j, q, eps2)) return false;
+  traverse<D, false>(a.t, m, sc, q, 0, a.info, [&](int j) {
+    if (!a.core[j] || !near<D>(a.xs, a.n, j, q, sc.eps2)) return false;
     int c = a.cid[a.labels[j]];
     best = c < best ? c : best;
     return best == 0;
@@ -352,7 +489,7 @@ __global__ void k_border_fdb(TravArgs a) {
 // --------------------------------------------------------------- DenseBox ----
 // Primitive p covers sorted points [prim_start[p], prim_start[p] + |cnt|):
 // cnt > 0 is a single point, cnt < 0 a dense cell (all core, one cluster).
-// Points outside dense cells query one thread per point primitive (so
+// Points outside dense cells query one lane per point primitive (so
 // wavefronts are full and in Morton order); a dense cell queries once, one
 // wavefront per cell, whose 64 lanes test the cell's points together.
 
@@ -405,6 +542,24 @@ __device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_
   return false;
 }
 
+// Number of points of the cell [s, s+c) within eps of p, counted 64 at a time
+// until at least `want` (whole wavefront).
+template <int D>
+__device__ __forceinline__ int cell_count_near(const float* __restrict__ xs, int64_t n, int s, int c, float px,
+                                               float py, float pz, float eps2, int want) {
+  const int lane = lane_id();
+  int found = 0;
+  for (int base = 0; base < c && found < want; base += 64) {
+    bool h = false;
+    if (base + lane < c) {
+      const int64_t j = s + base + lane;
+      h = dist2v<D>(xs[j], xs[n + j], D == 3 ? xs[2 * n + j] : 0.0f, px, py, pz) <= eps2;
+    }
+    found += __popcll(ballot(h));
+  }
+  return found;
+}
+
 // Resumable per-lane walk, one primitive (or one internal node) per step, so
 // that a wavefront can pause between steps: the sparse-point kernels below run
 // their lanes in lock-step and, whenever some lanes have reached a dense cell,
@@ -413,16 +568,18 @@ __device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_
 struct Walk {
   uint32_t node;  // next node to examine, kEnd when finished
   int cur, end;   // pending bucket primitives [cur, end]; empty when cur > end
+  int last;       // last primitive of the scope
   int64_t steps;  // remaining step budget (see traverse())
 };
 
 template <bool MASKED>
-__device__ __forceinline__ void walk_init(Walk& w, int m, int mask, bool on) {
+__device__ __forceinline__ void walk_init(Walk& w, int m, const Scope& sc, int mask, bool on) {
   w.cur = 1;
   w.end = 0;
+  w.last = sc.end;
   w.steps = 2 * int64_t(m) + 2;
-  if (!on || m <= 0 || (MASKED && mask >= m - 1)) w.node = kEnd;
-  else w.node = m == 1 ? kLeaf : 0u;
+  if (!on || m <= 0 || (MASKED && mask >= sc.end)) w.node = kEnd;
+  else w.node = sc.start;
 }
 
 __device__ __forceinline__ bool walk_done(const Walk& w) { return w.node == kEnd && w.cur > w.end; }
@@ -445,7 +602,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
       w.node = kEnd;
       return -1;
     }
-    w.node = static_cast<uint32_t>(t.leaf_rope[l]);
+    w.node = l >= w.last ? kEnd : static_cast<uint32_t>(t.leaf_rope[l]);
     return l;
   }
   if (node >= static_cast<uint32_t>(m - 1)) {
@@ -455,13 +612,13 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   }
   const float4 a = t.node_a[node];
   const float4 b = t.node_b[node];
-  if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > eps2) {
-    w.node = static_cast<uint32_t>(t.rope[node]);
-    return -1;
-  }
   const int k = static_cast<int>(node);
   const int o = __float_as_int(a.w), g = __float_as_int(b.w);
   const int first = o < k ? o : k, last = o > k ? o : k;
+  if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > eps2) {
+    w.node = last >= w.last ? kEnd : static_cast<uint32_t>(t.rope[node]);
+    return -1;
+  }
   if (first < 0 || last >= m || g < first || g >= last) {
     atomicOr(info, kInternalBit);
     w.node = kEnd;
@@ -470,7 +627,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   if (last - first < t.leaf_size) {
     w.cur = (MASKED && first <= mask) ? mask + 1 : first;
     w.end = last;
-    w.node = static_cast<uint32_t>(t.rope[node]);
+    w.node = last >= w.last ? kEnd : static_cast<uint32_t>(t.rope[node]);
     return w.cur <= w.end ? w.cur++ : -1;
   }
   if (MASKED && g <= mask)
@@ -480,64 +637,45 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   return -1;
 }
 
-// Number of points of the cell [s, s+c) within eps of p, counted 64 at a time
-// until at least `want` (whole wavefront).
-template <int D>
-__device__ __forceinline__ int cell_count_near(const float* __restrict__ xs, int64_t n, int s, int c, float px,
-                                               float py, float pz, float eps2, int want) {
-  const int lane = lane_id();
-  int found = 0;
-  for (int base = 0; base < c && found < want; base += 64) {
-    bool h = false;
-    if (base + lane < c) {
-      const int64_t j = s + base + lane;
-      h = dist2v<D>(xs[j], xs[n + j], D == 3 ? xs[2 * n + j] : 0.0f, px, py, pz) <= eps2;
-    }
-    found += __popcll(ballot(h));
-  }
-  return found;
-}
-
 // Core pass for points outside dense cells (one lane per point primitive).
-template <int D>
+template <int D, bool B>
 __global__ void k_core_dbx(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
   const bool mine = p >= 0 && p < m && a.prim_cnt[p] > 0;  // dense cells are core by construction
   const int i = mine ? a.prim_start[p] : 0;
+  const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
-  const int need = a.min_pts;
   int cnt = 0;
   Walk w;
-  walk_init<false>(w, m, 0, mine);
+  walk_init<false>(w, m, sc, 0, mine);
   bool active = mine && !walk_done(w);
   while (ballot(active)) {
     int pend = -1;
     if (active) {
-      const int r = walk_step<D, false>(w, a.t, m, q, eps2, 0, a.info);
+      const int r = walk_step<D, false>(w, a.t, m, q, sc.eps2, 0, a.info);
       if (r >= 0) {
         const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) cnt += near<D>(a.xs, a.n, s, q, eps2) ? 1 : 0;
-        else if (box_near<D>(a, r, q, eps2)) pend = r;
+        if (c > 0) cnt += near<D>(a.xs, a.n, s, q, sc.eps2) ? 1 : 0;
+        else if (box_near<D>(a, r, q, sc.eps2)) pend = r;
       }
     }
     for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
       const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
       const int r = __shfl(pend, L);
-      const int want = need - __shfl(cnt, L);
+      const int want = __shfl(sc.min_pts - cnt, L);
       const int found = cell_count_near<D>(a.xs, a.n, a.prim_start[r], -a.prim_cnt[r], __shfl(q.x, L),
-                                           __shfl(q.y, L), __shfl(q.z, L), eps2, want);
+                                           __shfl(q.y, L), __shfl(q.z, L), readlane_f(sc.eps2, L), want);
       if (lane == L) cnt += found;
     }
-    if (active && (cnt >= need || walk_done(w))) active = false;
+    if (active && (cnt >= sc.min_pts || walk_done(w))) active = false;
   }
-  if (mine) a.core[i] = cnt >= need ? 1 : 0;
+  if (mine) a.core[i] = cnt >= sc.min_pts ? 1 : 0;
 }
 
 // Main phase, points outside dense cells: pairs with primitives above their own.
-template <int D, bool ALL_CORE, bool FIRST>
+template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_points(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
@@ -546,21 +684,21 @@ __global__ void k_main_dbx_points(TravArgs a) {
   const int i = pt ? a.prim_start[p] : 0;
   const bool ci = pt && (ALL_CORE || a.core[i]);
   const bool mine = pt && (FIRST || ci);
+  const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
   int* labels = a.labels;
   int root = i;
   Walk w;
-  walk_init<true>(w, m, p, mine);
+  walk_init<true>(w, m, sc, p, mine);
   bool active = mine && !walk_done(w);
   while (ballot(active)) {
     int pend = -1;
     if (active) {
-      const int r = walk_step<D, true>(w, a.t, m, q, eps2, p, a.info);
+      const int r = walk_step<D, true>(w, a.t, m, q, sc.eps2, p, a.info);
       if (r >= 0) {
         const int c = a.prim_cnt[r], s = a.prim_start[r];
         if (c > 0) {
-          if (near<D>(a.xs, a.n, s, q, eps2)) {
+          if (near<D>(a.xs, a.n, s, q, sc.eps2)) {
             const bool cj = ALL_CORE || a.core[s];
             if (ci && cj) {
               if (!known_same_set(labels, s, root)) root = uf_union(labels, root, s, a.info);
@@ -571,7 +709,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
               active = false;  // i is a member now (by this or an earlier claim)
             }
           }
-        } else if (box_near<D>(a, r, q, eps2) && !(ci && known_same_set(labels, s, root))) {
+        } else if (box_near<D>(a, r, q, sc.eps2) && !(ci && known_same_set(labels, s, root))) {
           pend = r;
         }
       }
@@ -582,7 +720,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
       const int r = __shfl(pend, L);
       const int s = a.prim_start[r];
       const bool hit = cell_reaches_point<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
-                                             __shfl(q.z, L), eps2);
+                                             __shfl(q.z, L), readlane_f(sc.eps2, L));
       if (lane == L && hit) {
         if (ci) {
           root = uf_union(labels, root, s, a.info);
@@ -600,13 +738,12 @@ __global__ void k_main_dbx_points(TravArgs a) {
 // A's box, over primitives above A; a dense neighbour B joins A's set if some
 // pair is within eps, a core point if some point of A reaches it, and (first-
 // claim mode) a non-core point is claimed the same way.
-template <int D, bool ALL_CORE, bool FIRST>
+template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_cells(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int wave = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const float eps2 = a.eps2;
   int* labels = a.labels;
   // wavefront w takes a contiguous slice of the dense-cell list (filled in
   // roughly increasing key order), so neighbouring cells share an XCD's L2
@@ -614,50 +751,50 @@ __global__ void k_main_dbx_cells(TravArgs a) {
   const int per = (nd + nwaves - 1) / nwaves;
   const int dbeg = wave * per, dend = min(nd, dbeg + per);
   for (int w = dbeg; w < dend; ++w) {
-   {
     const int A = a.dense_list[w];
     const int sa = a.prim_start[A], na = -a.prim_cnt[A];
+    const Scope sc = scope_of<B>(a, m, sa);
+    const float eps2 = sc.eps2;
     const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
     const float alo[3] = {alo4.x, alo4.y, alo4.z}, ahi[3] = {ahi4.x, ahi4.y, ahi4.z};
     int root = sa;
-    traverse_box<D>(a.t, m, alo, ahi, eps2, A, a.t.leaf_size, a.info, [&](int r0, int r1) {
-     for (int r = r0; r <= r1; ++r) {
-      const int c = a.prim_cnt[r], s = a.prim_start[r];
-      if (c > 0) {
-        const int j = s;
-        const float px = a.xs[j], py = a.xs[a.n + j], pz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
-        if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) continue;
-        const bool cj = ALL_CORE || a.core[j];
-        if (cj) {
-          if (known_same_set(labels, j, root)) continue;
-          if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2)) {
-            int nr = 0;
-            if (lane == 0) nr = uf_union(labels, root, j, a.info);
-            root = __shfl(nr, 0);
+    traverse_box<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, [&](int r0, int r1) {
+      for (int r = r0; r <= r1; ++r) {
+        const int c = a.prim_cnt[r], s = a.prim_start[r];
+        if (c > 0) {
+          const int j = s;
+          const float px = a.xs[j], py = a.xs[a.n + j], pz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
+          if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) continue;
+          const bool cj = ALL_CORE || a.core[j];
+          if (cj) {
+            if (known_same_set(labels, j, root)) continue;
+            if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2)) {
+              int nr = 0;
+              if (lane == 0) nr = uf_union(labels, root, j, a.info);
+              root = __shfl(nr, 0);
+            }
+          } else if (FIRST) {
+            if (labels[j] != j) continue;
+            if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2) && lane == 0) uf_claim(labels, j, sa);
           }
-        } else if (FIRST) {
-          if (labels[j] != j) continue;
-          if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2) && lane == 0) uf_claim(labels, j, sa);
+          continue;
         }
-        continue;
+        const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
+        if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) continue;
+        if (known_same_set(labels, s, root)) continue;
+        if (cells_touch<D>(a.xs, a.n, sa, na, s, -c, blo, bhi, eps2)) {
+          int nr = 0;
+          if (lane == 0) nr = uf_union(labels, root, s, a.info);
+          root = __shfl(nr, 0);
+        }
       }
-      const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
-      if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) continue;
-      if (known_same_set(labels, s, root)) continue;
-      if (cells_touch<D>(a.xs, a.n, sa, na, s, -c, blo, bhi, eps2)) {
-        int nr = 0;
-        if (lane == 0) nr = uf_union(labels, root, s, a.info);
-        root = __shfl(nr, 0);
-      }
-     }
       return false;
     });
-   }
   }
 }
 
 // Canonical border pass for non-core points (all outside dense cells).
-template <int D>
+template <int D, bool B>
 __global__ void k_border_dbx(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
@@ -665,24 +802,24 @@ __global__ void k_border_dbx(TravArgs a) {
   const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
   const int i = pt ? a.prim_start[p] : 0;
   const bool mine = pt && !a.core[i];
+  const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
-  const float eps2 = a.eps2;
   int best = 0x7fffffff;
   Walk w;
-  walk_init<false>(w, m, 0, mine);
+  walk_init<false>(w, m, sc, 0, mine);
   bool active = mine && !walk_done(w);
   while (ballot(active)) {
     int pend = -1;
     if (active) {
-      const int r = walk_step<D, false>(w, a.t, m, q, eps2, 0, a.info);
+      const int r = walk_step<D, false>(w, a.t, m, q, sc.eps2, 0, a.info);
       if (r >= 0) {
         const int c = a.prim_cnt[r], s = a.prim_start[r];
         if (c > 0) {
-          if (a.core[s] && near<D>(a.xs, a.n, s, q, eps2)) {
+          if (a.core[s] && near<D>(a.xs, a.n, s, q, sc.eps2)) {
             const int id = a.cid[a.labels[s]];
             best = id < best ? id : best;
           }
-        } else if (box_near<D>(a, r, q, eps2) && a.cid[a.labels[s]] < best) {
+        } else if (box_near<D>(a, r, q, sc.eps2) && a.cid[a.labels[s]] < best) {
           pend = r;
         }
       }
@@ -692,7 +829,7 @@ __global__ void k_border_dbx(TravArgs a) {
       const int r = __shfl(pend, L);
       const int s = a.prim_start[r];
       const bool hit = cell_reaches_point<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
-                                             __shfl(q.z, L), eps2);
+                                             __shfl(q.z, L), readlane_f(sc.eps2, L));
       if (lane == L && hit) {
         const int id = a.cid[a.labels[s]];
         best = id < best ? id : best;
@@ -709,8 +846,9 @@ __global__ void k_debug_walk(TreeView t, int m, int mask, int* out_leaves, int* 
                              uint32_t* info) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   const Query q{0.0f, 0.0f, 0.0f};
+  const Scope sc{m == 1 ? kLeaf : 0u, m - 1, INFINITY, 0};
   int cnt = 0;
-  traverse<3, true>(t, m, q, INFINITY, mask, info, [&](int l) {
+  traverse<3, true>(t, m, sc, q, mask, info, [&](int l) {
     if (cnt < cap) out_leaves[cnt] = l;
     ++cnt;
     return false;
@@ -724,44 +862,69 @@ inline dim3 grid_of(int64_t n, int block) {
   return dim3(static_cast<unsigned>(kNumXcd * ceil_div(ceil_div(n, kNumXcd), block)));
 }
 
+template <int D, bool B>
+void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
+  const dim3 g = grid_of(a.n, a.block), b(a.block);
+  if (densebox) hipLaunchKernelGGL((k_core_dbx<D, B>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, 0, s, a);
+}
+
+// part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
+template <int D, bool ALL, bool FIRST, bool B>
+void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
+  const dim3 g = grid_of(a.n, a.block), b(a.block);
+  if (densebox) {
+    if (part != 2) hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST, B>), dim3(2048), dim3(256), 0, s, a);
+    if (part != 1) hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST, B>), g, b, 0, s, a);
+  } else if (FIRST) {
+    hipLaunchKernelGGL((k_main_fdb_first<D, B>), g, b, 0, s, a);
+  } else {
+    constexpr int kQ = 1;
+    const dim3 gq(static_cast<unsigned>(kNumXcd * ceil_div(ceil_div(a.n, kNumXcd), 256 * kQ)));
+    hipLaunchKernelGGL((k_main_fdb_q<D, ALL, B, kQ>), gq, dim3(256), 0, s, a);
+  }
+}
+
+template <int D, bool B>
+void border_t(const TravArgs& a, bool densebox, hipStream_t s) {
+  const dim3 g = grid_of(a.n, a.block), b(a.block);
+  if (densebox) hipLaunchKernelGGL((k_border_dbx<D, B>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_border_fdb<D, B>), g, b, 0, s, a);
+}
+
+template <int D>
+void main_dispatch(const TravArgs& a, bool densebox, bool all_core, bool first_border, int part, hipStream_t s) {
+  if (a.pkeys != nullptr) {  // batches always run the core pass
+    if (first_border) main_t<D, false, true, true>(a, densebox, part, s);
+    else main_t<D, false, false, true>(a, densebox, part, s);
+  } else if (all_core) {
+    main_t<D, true, false, false>(a, densebox, part, s);
+  } else if (first_border) {
+    main_t<D, false, true, false>(a, densebox, part, s);
+  } else {
+    main_t<D, false, false, false>(a, densebox, part, s);
+  }
+}
+
 }  // namespace
 
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
   if (a.n <= 0) return;
-  dim3 g = grid_of(a.n, a.block), b(a.block);
-  if (densebox) {
-    if (dim == 3) hipLaunchKernelGGL(k_core_dbx<3>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_core_dbx<2>, g, b, 0, s, a);
+  const bool B = a.pkeys != nullptr;
+  if (dim == 3) {
+    if (B) core_t<3, true>(a, densebox, s);
+    else core_t<3, false>(a, densebox, s);
   } else {
-    if (dim == 3) hipLaunchKernelGGL(k_core_fdb<3>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_core_fdb<2>, g, b, 0, s, a);
-  }
-}
-
-// part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
-template <int D, bool ALL, bool FIRST>
-static void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
-  dim3 g = grid_of(a.n, a.block), b(a.block);
-  if (densebox) {
-    if (part != 2) hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST>), dim3(2048), dim3(256), 0, s, a);
-    if (part != 1) hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST>), g, b, 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_main_fdb<D, ALL, FIRST>), g, b, 0, s, a);
+    if (B) core_t<2, true>(a, densebox, s);
+    else core_t<2, false>(a, densebox, s);
   }
 }
 
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
                  hipStream_t s) {
   if (a.n <= 0) return;
-  if (dim == 3) {
-    if (all_core) main_t<3, true, false>(a, densebox, part, s);
-    else if (first_border) main_t<3, false, true>(a, densebox, part, s);
-    else main_t<3, false, false>(a, densebox, part, s);
-  } else {
-    if (all_core) main_t<2, true, false>(a, densebox, part, s);
-    else if (first_border) main_t<2, false, true>(a, densebox, part, s);
-    else main_t<2, false, false>(a, densebox, part, s);
-  }
+  if (dim == 3) main_dispatch<3>(a, densebox, all_core, first_border, part, s);
+  else main_dispatch<2>(a, densebox, all_core, first_border, part, s);
 }
 
 void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int* out_count, int cap,
@@ -771,13 +934,13 @@ void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int*
 
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
   if (a.n <= 0) return;
-  dim3 g = grid_of(a.n, a.block), b(a.block);
-  if (densebox) {
-    if (dim == 3) hipLaunchKernelGGL(k_border_dbx<3>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_border_dbx<2>, g, b, 0, s, a);
+  const bool B = a.pkeys != nullptr;
+  if (dim == 3) {
+    if (B) border_t<3, true>(a, densebox, s);
+    else border_t<3, false>(a, densebox, s);
   } else {
-    if (dim == 3) hipLaunchKernelGGL(k_border_fdb<3>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(k_border_fdb<2>, g, b, 0, s, a);
+    if (B) border_t<2, true>(a, densebox, s);
+    else border_t<2, false>(a, densebox, s);
   }
 }
 

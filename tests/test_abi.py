@@ -71,3 +71,29 @@ def test_null_handle_is_rejected_before_any_gpu_call():
                           None) == _lib.FDB_ERR_INVALID
     lib.fdb_destroy(None)
     assert lib.fdb_create(None, 0) == _lib.FDB_ERR_INVALID
+
+
+def test_batched_and_server_arguments_are_checked_before_any_gpu_call():
+    from paper_2103_05162_amd import _lib
+    lib = _lib.load()
+    out = ctypes.c_size_t(0)
+    assert lib.fdb_workspace_bytes_batched(100, 0, 3, None, ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_workspace_bytes_batched(100, 4, 5, None, ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_workspace_bytes_batched(100, 4, 3, None, ctypes.byref(out)) == 0
+    one = out.value
+    assert lib.fdb_workspace_bytes_batched(100, 4096, 3, None, ctypes.byref(out)) == 0
+    assert out.value > one  # per-cloud arrays grow with the number of clouds
+    srv = ctypes.c_void_p()
+    opt = _lib.make_options("densebox")
+    assert lib.fdb_server_create(0, 1 << 30, 16, 7, ctypes.byref(opt), ctypes.byref(srv)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_server_create(0, 1 << 30, 0, 0, ctypes.byref(opt), ctypes.byref(srv)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_server_create(0, 1000, 16, 0, ctypes.byref(opt), ctypes.byref(srv)) == _lib.FDB_ERR_INVALID
+    bad = _lib.make_options("fdbscan", "canonical", leaf_size=-1)
+    assert lib.fdb_server_create(0, 1 << 30, 16, 0, ctypes.byref(bad), ctypes.byref(srv)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_server_create(0, 1 << 30, 16, 0, None, None) == _lib.FDB_ERR_INVALID
+    job = _lib.FdbJob(None, 0, 3, ctypes.c_float(0.1), 3, None, None)
+    t = ctypes.c_int64(0)
+    assert lib.fdb_server_submit(None, ctypes.byref(job), ctypes.byref(t)) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_server_poll(None, 0, None) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_server_drain(None) == _lib.FDB_ERR_INVALID
+    lib.fdb_server_destroy(None)

@@ -143,6 +143,33 @@ def batched_clouds(num_clouds: int = 4096, seed: int = 4, lo: int = 1024, hi: in
     return clouds, np.asarray(eps, dtype=np.float32), np.asarray(mp, dtype=np.int32)
 
 
+def served_trace(seed: int = 5, requests: int = 22000, rate: float = 2000.0, pool_per_dim: int = 48,
+                 lo: int = 10240, hi: int = 2097152, eps_lo: float = 0.005, eps_hi: float = 0.02,
+                 min_pts=(2, 5, 10)):
+    """Open-loop request stream for a clustering server: Poisson arrivals at `rate`
+    per second; each request draws d in {2, 3}, minPts from `min_pts` and eps
+    ~ U[eps_lo, eps_hi], and names one cloud of a resident pool (pool_per_dim
+    clouds per dimension, sizes floor(exp U(ln lo, ln hi)), drawn with
+    mixture_cloud), so request sizes follow the same log-uniform law.
+    Returns (pool: {2: [arrays], 3: [arrays]}, requests: dict of numpy arrays
+    arrival_s, dim, cloud, eps, min_pts, n)."""
+    rng = np.random.default_rng(seed)
+    pool = {}
+    for d in (2, 3):
+        pool[d] = []
+        for c in range(pool_per_dim):
+            crng = np.random.default_rng(np.random.SeedSequence([seed, d, c]))
+            n_c = int(math.floor(math.exp(crng.uniform(math.log(lo), math.log(hi)))))
+            pool[d].append(mixture_cloud(crng, n_c, d=d))
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=requests))
+    dim = rng.choice([2, 3], size=requests).astype(np.int32)
+    cloud = rng.integers(0, pool_per_dim, size=requests).astype(np.int32)
+    eps = rng.uniform(eps_lo, eps_hi, size=requests).astype(np.float32)
+    mp = rng.choice(np.asarray(min_pts, dtype=np.int32), size=requests).astype(np.int32)
+    n = np.array([pool[int(d)][int(c)].shape[0] for d, c in zip(dim, cloud)], dtype=np.int64)
+    return pool, {"arrival_s": arrival, "dim": dim, "cloud": cloud, "eps": eps, "min_pts": mp, "n": n}
+
+
 # The three single-cloud workloads (name -> (generator, eps, minPts)).
 CONFIGS = {
     "c1_blobs2d_16k": (blobs_2d, 0.01, 5),
