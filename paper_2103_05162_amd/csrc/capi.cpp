@@ -60,6 +60,11 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.gamma = take(N * 4);
   p.labels = take(N * 4);
   p.core = take(N);
+  p.lone = take(N);
+  p.qborder = take(N * 4);
+  p.brec_cap = std::max<int64_t>(4096, static_cast<int64_t>(N) / 8);
+  p.brec_i = take(static_cast<size_t>(p.brec_cap) * 4);
+  p.brec_nb = take(static_cast<size_t>(p.brec_cap) * kRecNb * 4);
   p.minorig = take(N * 4);
   p.lflag = take(N * 4);
   p.rank = take(N * 4);
@@ -67,7 +72,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.cid = take(N * 4);
   p.border = take(N * 4);
   p.cell_id = p.cell_start = p.cand = p.cell_dense = p.cell_lo = p.cell_hi = 0;
-  p.pflag = p.prim_of = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = p.dense_list = 0;
+  p.pflag = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = p.dense_list = 0;
   if (algo == FDB_ALGO_DENSEBOX) {
     p.cell_id = take(N * 4);
     p.cell_start = take((N + 1) * 4);
@@ -76,7 +81,6 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
     p.cell_lo = take(N * 16);
     p.cell_hi = take(N * 16);
     p.pflag = take(N * 4);
-    p.prim_of = take(N * 4);
     p.prim_start = take(N * 4);
     p.prim_cnt = take(N * 4);
     p.prim_lo = take(N * 16);
@@ -347,7 +351,7 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
   if (st == FDB_OK) {
     fill_u32(reinterpret_cast<uint32_t*>(xs), 0, 3 * M, s);
     fill_u32(h->d_info, 0, 1, s);
-    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
+    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
                h->d_info, s);
     TreeView t{na, nb, rope, lrope, m, nullptr, leaf_size};
     launch_debug_walk(t, m, mask, leaves, count, m, h->d_info, s);
@@ -538,17 +542,17 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     densebox_cells(keys[cur], gp.key64, n, dim, xs, eps2, min_pts, at<int>(ws, plan.cell_id),
                    at<int>(ws, plan.cell_start), at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense),
                    at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
-                   at<int>(ws, plan.prim_of), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
+                   at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
                    at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key),
                    at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
-               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<float4>(ws, plan.prim_hi), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
+               at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = misc + kMiscNumPrims;
-    ta.prim_of = at<int>(ws, plan.prim_of);
     ta.prim_start = at<int>(ws, plan.prim_start);
     ta.prim_cnt = at<int>(ws, plan.prim_cnt);
     ta.prim_lo = at<float4>(ws, plan.prim_lo);
@@ -566,7 +570,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
     launch_init_labels(lab, n, s);
     st.mark("lbvh");
-    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, nullptr, nullptr,
+               at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
                nullptr, h->d_info, s);
@@ -575,7 +580,15 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   }
 
   const bool all_core = min_pts <= 2;
+  ta.lone = all_core ? nullptr : at<uint8_t>(ws, plan.lone);
+  ta.qborder = at<int>(ws, plan.qborder);
+  ta.qborder_n = misc + kMiscBorderQ;
+  ta.brec_i = at<int>(ws, plan.brec_i);
+  ta.brec_nb = at<int>(ws, plan.brec_nb);
+  ta.brec_n = misc + kMiscBorderRec;
+  ta.brec_cap = static_cast<int>(plan.brec_cap);
   if (!all_core) {
+    fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
     st.mark("core");
     launch_core(ta, dim, densebox, s);
   }
@@ -592,7 +605,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   launch_finalize(lab, n, h->d_info, s);
   if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);
   st.mark("cluster_ids");
-  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<int>(ws, plan.lflag), at<int>(ws, plan.rank),
+  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), at<int>(ws, plan.rank),
                 at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s);
   const bool have_border = !all_core && !first_border;
   if (have_border) {
@@ -740,19 +753,19 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
     st.mark("dense_cells");
     densebox_cells(keys[cur], true, n, dim, xs, 0.0f, 0, at<int>(ws, plan.cell_id), at<int>(ws, plan.cell_start),
                    at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense), at<float4>(ws, plan.cell_lo),
-                   at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag), at<int>(ws, plan.prim_of),
+                   at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt), at<float4>(ws, plan.prim_lo),
                    at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key), at<int>(ws, plan.dense_list), lab,
                    core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2);
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
-               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<float4>(ws, plan.prim_hi), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
+               at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
     batch_roots(offsets, num_clouds, n, at<int>(ws, plan.cand), misc + kMiscNumPrims, at<int>(ws, plan.other),
                 cl_root, cl_end, h->d_info, s);
     ta.t.d_m = misc + kMiscNumPrims;
-    ta.prim_of = at<int>(ws, plan.prim_of);
     ta.prim_start = at<int>(ws, plan.prim_start);
     ta.prim_cnt = at<int>(ws, plan.prim_cnt);
     ta.prim_lo = at<float4>(ws, plan.prim_lo);
@@ -762,7 +775,8 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   } else {
     launch_init_labels(lab, n, s);
     st.mark("lbvh");
-    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, nullptr, nullptr,
+               at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
                nullptr, h->d_info, s);
@@ -770,6 +784,14 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
     ta.t.d_m = nullptr;
   }
   st.mark("core");
+  ta.lone = at<uint8_t>(ws, plan.lone);
+  ta.qborder = at<int>(ws, plan.qborder);
+  ta.qborder_n = misc + kMiscBorderQ;
+  ta.brec_i = at<int>(ws, plan.brec_i);
+  ta.brec_nb = at<int>(ws, plan.brec_nb);
+  ta.brec_n = misc + kMiscBorderRec;
+  ta.brec_cap = static_cast<int>(plan.brec_cap);
+  fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
   launch_core(ta, dim, densebox, s);
   if (densebox) {
     st.mark("main_cells");
@@ -784,9 +806,10 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   launch_finalize(lab, n, h->d_info, s);
   st.mark("cluster_ids");
   int* rank = at<int>(ws, plan.rank);
-  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<int>(ws, plan.lflag), rank,
-                at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false);
-  batch_cluster_ids(lab, core, at<int>(ws, plan.minorig), rank, pkeys, shift, offsets, num_clouds, n,
+  uint32_t* lbits = at<uint32_t>(ws, plan.lflag);
+  canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), lbits, rank, at<int>(ws, plan.bsums),
+                plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false);
+  batch_cluster_ids(lab, core, at<int>(ws, plan.minorig), lbits, rank, pkeys, shift, offsets, num_clouds, n,
                     misc + kMiscNumClusters, cl_flags, at<int>(ws, plan.cid), num_clusters, s);
   if (!first_border) {
     st.mark("border");

@@ -198,6 +198,17 @@ __device__ __forceinline__ int64_t xcd_spread(int b, int bdim, int tid, int64_t 
   return (b % kNumXcd) * chunk + off + tid;
 }
 
+// ---- canonical ids --------------------------------------------------------------
+// Cluster leaders are kept as one bit per input index (bits[o >> 5], bit o & 31);
+// wpre[w] is the number of leaders in words before w. The number of leaders at
+// input indices below x (x <= n) is then one load, one popcount and one add.
+__device__ __forceinline__ int leaders_before(const uint32_t* __restrict__ bits, const int* __restrict__ wpre,
+                                              int64_t x, int64_t n, const int* __restrict__ total) {
+  if (x >= n) return *total;
+  const int r = static_cast<int>(x & 31);
+  return wpre[x >> 5] + __popc(bits[x >> 5] & ((1u << r) - 1u));
+}
+
 // ---- wavefront helpers ---------------------------------------------------------
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -13,6 +13,7 @@ constexpr int kSortTile = 256 * kSortItems;    // keys per workgroup tile
 constexpr int kScanItems = 16;                 // items per thread in the device scan
 constexpr int kScanTile = 256 * kScanItems;
 constexpr int64_t kMaxPoints = (int64_t(1) << 30) - 1;
+constexpr int kRecNb = 8;  // neighbouring primitives recorded per non-core point
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -28,10 +29,11 @@ struct Plan {
   size_t bounds, misc, keys0, keys1, vals0, vals1, hist, digoff, tilectr, status;
   size_t xs;                       // dim * n floats, sorted SoA
   size_t node_a, node_b, rope, leaf_rope, parent, flags, other, gamma;
-  size_t labels, core;
+  size_t labels, core, lone, qborder, brec_i, brec_nb;
+  int64_t brec_cap = 0;
   size_t minorig, lflag, rank, bsums, cid, border;
   // DenseBox
-  size_t cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt,
+  size_t cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_start, prim_cnt,
       prim_lo, prim_hi, prim_key, dense_list;
   // batches
   int num_clouds = 0;
@@ -48,6 +50,8 @@ enum MiscSlot : int {
   kMiscNumCand = 2,      // DenseBox: cells with >= minPts points
   kMiscNumPrims = 3,     // DenseBox: m = dense cells + points outside them
   kMiscNumDense = 4,     // DenseBox: dense cells
+  kMiscBorderQ = 5,      // entries of the border query list (filled by the core pass)
+  kMiscBorderRec = 6,    // border neighbour records asked for by the core pass
   kMiscCount = 16
 };
 
@@ -87,7 +91,8 @@ int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64
 
 // k_tree.hip
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
-                const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
+                const float4* prim_lo, const float4* prim_hi, const int* prim_start, const int* prim_cnt,
+                float4* node_a, float4* node_b, int* rope,
                 int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m, uint32_t* info,
                 hipStream_t s);
 
@@ -100,7 +105,7 @@ struct GridParams {
 };
 void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2,
                     int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo,
-                    float4* cell_hi, int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo,
+                    float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
                     float4* prim_hi, void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
                     int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift = 0,
                     const int* cl_minpts = nullptr, const float* cl_eps2 = nullptr);
@@ -116,10 +121,24 @@ struct TravArgs {
   int min_pts;
   int* labels;
   uint8_t* core;
+  uint8_t* lone;  // set by the core pass: 1 = not core and no neighbour but itself (noise); NULL if no core pass
+  // Border work left by the core pass for non-core points with some neighbour
+  // other than themselves. Up to kRecNb neighbouring primitives of such a point
+  // (the point itself, or a dense cell's first point) are recorded, so the
+  // border pass needs no walk: record k is point brec_i[k] with neighbours
+  // brec_nb[k * kRecNb + t] (-1 = none); *brec_n counts the records asked for,
+  // of which the first brec_cap are stored. Points with more neighbouring
+  // primitives, or past the capacity, are listed in qborder (DenseBox: their
+  // primitive indices) and walk the tree again.
+  int* brec_i;
+  int* brec_nb;
+  int* brec_n;
+  int brec_cap;
+  int* qborder;
+  int* qborder_n;
   const int* cid;
   int* border;
   // DenseBox primitives (null for FDbscan)
-  const int* prim_of;
   const int* prim_start;
   const int* prim_cnt;  // > 0: a single point; < 0: -(count) points of a dense cell
   const float4* prim_lo;
@@ -149,8 +168,11 @@ void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int*
 void launch_init_labels(int* labels, int64_t n, hipStream_t s);
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s);
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
+// Canonical cluster ids (ids 0..K-1 in increasing order of each cluster's
+// smallest core input index). bits: ceil(n/32) leader words followed by as many
+// ints of scratch (fits the n-int lflag array); wpre: ceil(n/32) ints.
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
-                   int* lflag, int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
+                   uint32_t* bits, int* wpre, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
                    bool ids = true);
 
 // k_batch.hip
@@ -161,9 +183,10 @@ void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n,
                 const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, hipStream_t s);
 void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,
                  int* root, int* end, uint32_t* info, hipStream_t s);
-void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const int* rank,
-                       const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds, int64_t n,
-                       const int* total, const int* cl_flags, int* cid, int32_t* num_clusters, hipStream_t s);
+void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const uint32_t* bits,
+                       const int* wpre, const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds,
+                       int64_t n, const int* total, const int* cl_flags, int* cid, int32_t* num_clusters,
+                       hipStream_t s);
 void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid,
                     const int* border, bool first_border, bool have_border, int64_t n, int32_t* out_labels,
                     uint8_t* out_core, uint32_t* info, hipStream_t s);

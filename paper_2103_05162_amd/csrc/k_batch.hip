@@ -193,18 +193,16 @@ __global__ __launch_bounds__(kBlock) void k_cloud_roots(const int64_t* __restric
   }
 }
 
-// Per-cloud cluster ids: rank is the exclusive scan, in input order, of the
-// flags marking each cluster's smallest core input index, so a cloud's ids are
-// rank minus the rank at its first input index, and its K the rank difference
-// across the cloud.
-__device__ __forceinline__ int rank_at(const int* rank, int64_t x, int64_t n, const int* total) {
-  return x < n ? rank[x] : *total;
-}
+// Per-cloud cluster ids: a cluster's global id is the number of cluster
+// leaders (smallest core input index of a cluster) at smaller input indices, so
+// a cloud's ids are that count minus the count at the cloud's first input
+// index, and its K the difference across the cloud.
 
 __global__ __launch_bounds__(kBlock) void k_batch_cluster_ids(const int* __restrict__ labels,
                                                               const uint8_t* __restrict__ core,
                                                               const int* __restrict__ minorig,
-                                                              const int* __restrict__ rank,
+                                                              const uint32_t* __restrict__ bits,
+                                                              const int* __restrict__ wpre,
                                                               const uint64_t* __restrict__ pkeys, int shift,
                                                               const int64_t* __restrict__ off, int num_clouds,
                                                               int64_t n, const int* __restrict__ total,
@@ -214,13 +212,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_cluster_ids(const int* __restr
     const int c = min(static_cast<int>(pkeys[i] >> shift), num_clouds - 1);
     int64_t b, e;
     cloud_range(off, c, n, b, e);
-    cid[i] = rank[minorig[i]] - rank_at(rank, b, n, total);
+    cid[i] = leaders_before(bits, wpre, minorig[i], n, total) - leaders_before(bits, wpre, b, n, total);
   }
 }
 
 // K per cloud, or -1 where the cloud's labels are undefined (a coordinate that
 // is not finite, eps or minPts out of range, offsets out of order).
-__global__ __launch_bounds__(kBlock) void k_batch_counts(const int* __restrict__ rank, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_batch_counts(const uint32_t* __restrict__ bits,
+                                                         const int* __restrict__ wpre, const int64_t* __restrict__ off,
                                                          int num_clouds, int64_t n, const int* __restrict__ total,
                                                          const int* __restrict__ cl_flags,
                                                          int32_t* __restrict__ num_clusters) {
@@ -228,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_counts(const int* __restrict__
   if (c >= num_clouds) return;
   int64_t b, e;
   cloud_range(off, c, n, b, e);
-  num_clusters[c] = cl_flags[c] ? -1 : rank_at(rank, e, n, total) - rank_at(rank, b, n, total);
+  num_clusters[c] =
+      cl_flags[c] ? -1 : leaders_before(bits, wpre, e, n, total) - leaders_before(bits, wpre, b, n, total);
 }
 
 inline int grid_for(int64_t n) {
@@ -267,14 +267,15 @@ void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx,
                      off, num_clouds, n, pidx, d_m, other, root, end, info);
 }
 
-void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const int* rank,
-                       const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds, int64_t n,
-                       const int* total, const int* cl_flags, int* cid, int32_t* num_clusters, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_cluster_ids, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, minorig, rank, pkeys,
-                     shift, off, num_clouds, n, total, cid);
+void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const uint32_t* bits,
+                       const int* wpre, const uint64_t* pkeys, int shift, const int64_t* off, int num_clouds,
+                       int64_t n, const int* total, const int* cl_flags, int* cid, int32_t* num_clusters,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_cluster_ids, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, minorig, bits, wpre,
+                     pkeys, shift, off, num_clouds, n, total, cid);
   if (num_clusters)
     hipLaunchKernelGGL(k_batch_counts, dim3(static_cast<unsigned>(ceil_div(num_clouds, kBlock))), dim3(kBlock), 0, s,
-                       rank, off, num_clouds, n, total, cl_flags, num_clusters);
+                       bits, wpre, off, num_clouds, n, total, cl_flags, num_clusters);
 }
 
 }  // namespace fdb

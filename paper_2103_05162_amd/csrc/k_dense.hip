@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
                                                   const int* __restrict__ cell_id, const int* __restrict__ cell_start,
                                                   const uint8_t* __restrict__ dense, const float4* __restrict__ cell_lo,
                                                   const float4* __restrict__ cell_hi, const int* __restrict__ pidx,
-                                                  int* __restrict__ prim_of, int* __restrict__ prim_start,
+                                                  int* __restrict__ prim_start,
                                                   int* __restrict__ prim_cnt, float4* __restrict__ prim_lo,
                                                   float4* __restrict__ prim_hi, K* __restrict__ prim_key,
                                                   int* __restrict__ dense_list, int* __restrict__ num_dense,
@@ -133,7 +133,6 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
     const int s = cell_start[c];
     if (dense[c]) {
       const int p = pidx[s];
-      prim_of[i] = p;
       labels[i] = s;
       core[i] = 1;
       if (i == s) {
@@ -145,15 +144,11 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
         dense_list[atomicAdd(num_dense, 1)] = p;
       }
     } else {
-      const int p = pidx[i];
-      prim_of[i] = p;
+      const int p = pidx[i];  // a point primitive: its box is the point (never stored)
       labels[i] = i;
       core[i] = 0;
       prim_start[p] = i;
       prim_cnt[p] = 1;
-      float x = xs[i], y = xs[n + i], z = D == 3 ? xs[2 * n + i] : 0.0f;
-      prim_lo[p] = make_float4(x, y, z, 0.0f);
-      prim_hi[p] = make_float4(x, y, z, 0.0f);
       prim_key[p] = keys[i];
     }
   }
@@ -168,7 +163,7 @@ inline int grid_for(int64_t n) {
 
 template <typename K>
 void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
-             int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag, int* prim_of,
+             int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag,
              int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* dense_list,
              int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, const CloudParams& cp,
              hipStream_t s) {
@@ -195,11 +190,11 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
   if (dim == 3)
     hipLaunchKernelGGL((k_prims<3, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
-                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
+                       cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
   else
     hipLaunchKernelGGL((k_prims<2, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
-                       cell_lo, cell_hi, pidx, prim_of, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
+                       cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
 }
 
@@ -207,17 +202,17 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
 
 void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2, int min_pts,
                     int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo, float4* cell_hi,
-                    int* pflag, int* prim_of, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
+                    int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
                     void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc, int* bsums,
                     int64_t scan_blocks, hipStream_t s, int key_shift, const int* cl_minpts, const float* cl_eps2) {
   CloudParams cp{static_cast<const uint64_t*>(sorted_keys), key_shift, cl_minpts, cl_eps2};
   if (key64)
     cells_t(static_cast<const uint64_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
-            cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
+            cell_dense, cell_lo, cell_hi, pflag, prim_start, prim_cnt, prim_lo, prim_hi,
             static_cast<uint64_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
   else
     cells_t(static_cast<const uint32_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
-            cell_dense, cell_lo, cell_hi, pflag, prim_of, prim_start, prim_cnt, prim_lo, prim_hi,
+            cell_dense, cell_lo, cell_hi, pflag, prim_start, prim_cnt, prim_lo, prim_hi,
             static_cast<uint32_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
 }
 

@@ -86,23 +86,33 @@ __global__ __launch_bounds__(kBlock) void k_minorig(const int* __restrict__ labe
   }
 }
 
-// lflag[o] = 1 iff input index o is the smallest input index among the core
-// points of its cluster; its exclusive scan in input order is the cluster id.
-__global__ __launch_bounds__(kBlock) void k_leaders(const int* __restrict__ labels, const uint8_t* __restrict__ core,
-                                                    const uint32_t* __restrict__ perm, const int* __restrict__ minorig,
-                                                    int64_t n, int* __restrict__ lflag) {
+// Leader bit of each cluster: the smallest input index among its core points
+// (one atomic per cluster, at its root). A cluster's id is the number of
+// leaders at smaller input indices.
+__global__ __launch_bounds__(kBlock) void k_leader_bits(const int* __restrict__ labels,
+                                                        const uint8_t* __restrict__ core,
+                                                        const int* __restrict__ minorig, int64_t n,
+                                                        uint32_t* __restrict__ bits) {
   for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
-    int o = static_cast<int>(perm[i]);
-    lflag[o] = (core[i] && minorig[labels[i]] == o) ? 1 : 0;
+    if (!(core[i] && labels[i] == i)) continue;
+    const int o = minorig[i];
+    if (o >= 0 && o < n) atomicOr(bits + (o >> 5), 1u << (o & 31));
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_word_popc(const uint32_t* __restrict__ bits, int64_t words,
+                                                      int* __restrict__ cnt) {
+  for (int64_t w = blockIdx.x * int64_t(kBlock) + threadIdx.x; w < words; w += int64_t(gridDim.x) * kBlock)
+    cnt[w] = __popc(bits[w]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cluster_ids(const int* __restrict__ labels,
                                                         const uint8_t* __restrict__ core,
-                                                        const int* __restrict__ minorig, const int* __restrict__ rank,
-                                                        int64_t n, int* __restrict__ cid) {
+                                                        const int* __restrict__ minorig,
+                                                        const uint32_t* __restrict__ bits, const int* __restrict__ wpre,
+                                                        int64_t n, const int* __restrict__ total, int* __restrict__ cid) {
   for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    if (core[i] && labels[i] == i) cid[i] = rank[minorig[i]];
+    if (core[i] && labels[i] == i) cid[i] = leaders_before(bits, wpre, minorig[i], n, total);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ labels, const uint8_t* __restrict__ core,
@@ -187,31 +197,50 @@ __global__ __launch_bounds__(kBlock) void k_scan_bsums(int* __restrict__ bsums, 
   if (threadIdx.x == 0 && d_total) *d_total = s_carry;
 }
 
+// Tile position p lives at LDS word p + p/16: thread t's blocked items
+// [16t, 16t+16) then sit at 17t + k, so a blocked access hits distinct banks,
+// and global memory is read and written striped (coalesced).
+__device__ __forceinline__ int scan_lds(int p) { return p + (p >> 4); }
+
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int64_t n_cap,
                                                        const int* __restrict__ d_n, const int* __restrict__ bsums) {
+  static_assert(kScanItems == 16, "the LDS padding assumes 16 items per thread");
+  __shared__ int s_v[kScanTile + kScanTile / 16];
   __shared__ int s_w[kBlock / 64];
   __shared__ int s_carry;
   const int64_t n = d_n ? *d_n : n_cap;
   const int64_t base = blockIdx.x * int64_t(kScanTile);
-  // blocked layout: thread t owns items [t*kScanItems, (t+1)*kScanItems)
+  const int tid = threadIdx.x;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int p = k * kBlock + tid;
+    const int64_t i = base + p;
+    s_v[scan_lds(p)] = i < n ? in[i] : 0;
+  }
+  if (tid == 0) s_carry = bsums[blockIdx.x];
+  __syncthreads();
   int v[kScanItems];
   int sum = 0;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + int64_t(threadIdx.x) * kScanItems + k;
-    v[k] = i < n ? in[i] : 0;
+    v[k] = s_v[tid * 17 + k];
     sum += v[k];
   }
-  if (threadIdx.x == 0) s_carry = bsums[blockIdx.x];
-  int inc = wave_inclusive(sum);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+  const int inc = wave_inclusive(sum);
+  const int w = tid >> 6;
+  if ((tid & 63) == 63) s_w[w] = inc;
   __syncthreads();
   int run = s_carry + inc - sum;
   for (int j = 0; j < w; ++j) run += s_w[j];
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + int64_t(threadIdx.x) * kScanItems + k;
-    if (i < n) out[i] = run;
+    s_v[tid * 17 + k] = run;
     run += v[k];
+  }
+  __syncthreads();
+  for (int k = 0; k < kScanItems; ++k) {
+    const int p = k * kBlock + tid;
+    const int64_t i = base + p;
+    if (i < n) out[i] = s_v[scan_lds(p)];
   }
 }
 
@@ -247,14 +276,20 @@ void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_
   hipLaunchKernelGGL(k_core_from_sets, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, n);
 }
 
-void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig, int* lflag,
-                   int* rank, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s, bool ids) {
+void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
+                   uint32_t* bits, int* wpre, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
+                   bool ids) {
   const int g = grid_for(n);
+  const int64_t words = ceil_div(n, 32);
+  int* cnt = reinterpret_cast<int*>(bits + words);
   fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
+  fill_u32(bits, 0, words, s);
   hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
-  hipLaunchKernelGGL(k_leaders, dim3(g), dim3(kBlock), 0, s, labels, core, perm, minorig, n, lflag);
-  device_scan(lflag, rank, n, nullptr, bsums, scan_blocks, d_k, s);
-  if (ids) hipLaunchKernelGGL(k_cluster_ids, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, rank, n, cid);
+  hipLaunchKernelGGL(k_leader_bits, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, n, bits);
+  hipLaunchKernelGGL(k_word_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bits, words, cnt);
+  device_scan(cnt, wpre, words, nullptr, bsums, scan_blocks, d_k, s);
+  if (ids)
+    hipLaunchKernelGGL(k_cluster_ids, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, bits, wpre, n, d_k, cid);
 }
 
 void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid, const int* border,

@@ -218,6 +218,77 @@ __device__ __forceinline__ bool known_same_set(int* labels, int x, int root) {
   return false;
 }
 
+// Slot in a list (counter *n) for every thread where pred holds, -1 elsewhere:
+// one atomic per workgroup, threads in order within it. Every thread of the
+// workgroup must call it (it synchronises the workgroup); s_w holds 17 ints.
+__device__ __forceinline__ int block_reserve(int* n, bool pred, int* s_w) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t b = ballot(pred);
+  if (lane_id() == 0) s_w[w] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < nw; ++k) {
+      const int c = s_w[k];
+      s_w[k] = tot;
+      tot += c;
+    }
+    s_w[16] = tot ? atomicAdd(n, tot) : 0;
+  }
+  __syncthreads();
+  const int slot = s_w[16] + s_w[w] + __popcll(b & lanemask_lt());
+  __syncthreads();
+  return pred ? slot : -1;
+}
+
+// Up to kRecNb neighbouring primitives of one query, kept in registers.
+struct NbRec {
+  int nb[kRecNb];
+  int nn;
+};
+
+__device__ __forceinline__ void rec_init(NbRec& r) {
+  r.nn = 0;
+#pragma unroll
+  for (int t = 0; t < kRecNb; ++t) r.nb[t] = -1;
+}
+
+__device__ __forceinline__ void rec_add(NbRec& r, int j) {
+#pragma unroll
+  for (int t = 0; t < kRecNb; ++t)
+    if (t == r.nn) r.nb[t] = j;
+  ++r.nn;
+}
+
+// End of a core pass for query point i (primitive p): core and lone flags, and
+// what the border pass will need: nothing (core, or lone: border -1 now), a
+// neighbour record, or a walk. Called by every thread of the workgroup.
+__device__ __forceinline__ void core_epilogue(const TravArgs& a, bool mine, int i, int p, int cnt, int min_pts,
+                                              const NbRec& rec, int* s_w) {
+  const bool core = mine && cnt >= min_pts;
+  const bool lone = mine && cnt <= 1 && !core;
+  if (mine) {
+    a.core[i] = core ? 1 : 0;
+    a.lone[i] = lone ? 1 : 0;
+    if (lone) a.border[i] = -1;
+  }
+  const bool want = mine && !core && !lone;
+  const bool fits = want && rec.nn <= kRecNb;
+  const int slot = block_reserve(a.brec_n, fits, s_w);
+  const bool stored = fits && slot < a.brec_cap;
+  if (stored) {
+    a.brec_i[slot] = i;
+#pragma unroll
+    for (int t = 0; t < kRecNb; ++t) a.brec_nb[int64_t(slot) * kRecNb + t] = rec.nb[t];
+  }
+  const int wslot = block_reserve(a.qborder_n, want && !stored, s_w);
+  if (wslot >= 0) a.qborder[wslot] = p;
+}
+
+// A non-core point with no neighbour but itself (known once the core pass has
+// run) is noise: nothing to claim, no cluster to join.
+__device__ __forceinline__ bool is_lone(const TravArgs& a, int i) { return a.lone && a.lone[i]; }
+
 __device__ __forceinline__ float readlane_f(float v, int k) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
@@ -226,17 +297,23 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
 
 template <int D, bool B>
 __global__ void k_core_fdb(TravArgs a) {
-  const int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
-  if (i < 0 || i >= a.n) return;
+  __shared__ int s_w[17];
+  const int64_t i64 = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
+  const bool mine = i64 >= 0 && i64 < a.n;
+  const int i = mine ? static_cast<int>(i64) : 0;
   const int m = tree_m(a.t);
-  const Scope sc = scope_of<B>(a, m, static_cast<int>(i));
+  const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
   int cnt = 0;
-  traverse<D, false>(a.t, m, sc, q, 0, a.info, [&](int j) {
-    if (near<D>(a.xs, a.n, j, q, sc.eps2)) return ++cnt >= sc.min_pts;
-    return false;
-  });
-  a.core[i] = cnt >= sc.min_pts ? 1 : 0;
+  NbRec rec;
+  rec_init(rec);
+  if (mine)
+    traverse<D, false>(a.t, m, sc, q, 0, a.info, [&](int j) {
+      if (!near<D>(a.xs, a.n, j, q, sc.eps2)) return false;
+      if (j != i) rec_add(rec, j);
+      return ++cnt >= sc.min_pts;
+    });
+  core_epilogue(a, mine, i, i, cnt, sc.min_pts, rec, s_w);
 }
 
 // First-claim main phase (the paper's border rule): per-lane walks, or a packet
@@ -261,7 +338,7 @@ __global__ void k_main_fdb_first(TravArgs a) {
   const bool valid = i64 >= 0 && i64 < a.n;
   const int i = valid ? static_cast<int>(i64) : 0;
   const bool ci = valid && a.core[i];
-  const bool mine = valid;
+  const bool mine = valid && (ci || !is_lone(a, i));
   const int m = tree_m(a.t);
   const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
@@ -468,11 +545,34 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   });
 }
 
+// Border pass from the core pass's neighbour records (no walk): the smallest
+// cluster id among the recorded core neighbours.
+__global__ void k_border_rec(TravArgs a) {
+  const int nr = min(*a.brec_n, a.brec_cap);
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nr);
+  if (k < 0 || k >= nr) return;
+  const int i = a.brec_i[k];
+  int best = 0x7fffffff;
+#pragma unroll
+  for (int t = 0; t < kRecNb; ++t) {
+    const int j = a.brec_nb[k * kRecNb + t];
+    if (j >= 0 && a.core[j]) {
+      const int c = a.cid[a.labels[j]];
+      best = c < best ? c : best;
+    }
+  }
+  a.border[i] = best == 0x7fffffff ? -1 : best;
+}
+
+// Border pass over the listed queries: non-core points whose neighbours were
+// not all recorded (the core pass wrote -1 for lone points, and the records
+// cover the rest).
 template <int D, bool B>
 __global__ void k_border_fdb(TravArgs a) {
-  const int64_t i = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
-  if (i < 0 || i >= a.n) return;
-  if (a.core[i]) return;
+  const int nq = *a.qborder_n;
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nq);
+  if (k < 0 || k >= nq) return;
+  const int i = a.qborder[k];
   const int m = tree_m(a.t);
   const Scope sc = scope_of<B>(a, m, static_cast<int>(i));
   const Query q = load_point<D>(a.xs, a.n, i);
@@ -640,6 +740,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
 // Core pass for points outside dense cells (one lane per point primitive).
 template <int D, bool B>
 __global__ void k_core_dbx(TravArgs a) {
+  __shared__ int s_w[17];
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
@@ -648,6 +749,8 @@ __global__ void k_core_dbx(TravArgs a) {
   const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
   int cnt = 0;
+  NbRec rec;
+  rec_init(rec);
   Walk w;
   walk_init<false>(w, m, sc, 0, mine);
   bool active = mine && !walk_done(w);
@@ -657,24 +760,37 @@ __global__ void k_core_dbx(TravArgs a) {
       const int r = walk_step<D, false>(w, a.t, m, q, sc.eps2, 0, a.info);
       if (r >= 0) {
         const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) cnt += near<D>(a.xs, a.n, s, q, sc.eps2) ? 1 : 0;
-        else if (box_near<D>(a, r, q, sc.eps2)) pend = r;
+        if (c > 0) {
+          if (near<D>(a.xs, a.n, s, q, sc.eps2)) {
+            ++cnt;
+            if (s != i) rec_add(rec, s);
+          }
+        } else if (box_near<D>(a, r, q, sc.eps2)) {
+          pend = r;
+        }
       }
     }
     for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
       const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
       const int r = __shfl(pend, L);
       const int want = __shfl(sc.min_pts - cnt, L);
-      const int found = cell_count_near<D>(a.xs, a.n, a.prim_start[r], -a.prim_cnt[r], __shfl(q.x, L),
-                                           __shfl(q.y, L), __shfl(q.z, L), readlane_f(sc.eps2, L), want);
-      if (lane == L) cnt += found;
+      const int s = a.prim_start[r];
+      const int found = cell_count_near<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
+                                           __shfl(q.z, L), readlane_f(sc.eps2, L), want);
+      if (lane == L && found > 0) {
+        cnt += found;
+        rec_add(rec, s);  // a dense cell: all core, one cluster; its first point stands for it
+      }
     }
     if (active && (cnt >= sc.min_pts || walk_done(w))) active = false;
   }
-  if (mine) a.core[i] = cnt >= sc.min_pts ? 1 : 0;
+  core_epilogue(a, mine, i, p, cnt, sc.min_pts, rec, s_w);
 }
 
 // Main phase, points outside dense cells: pairs with primitives above their own.
+// One lane per point primitive; lanes whose point is not a query stay idle.
+// (Compacting the few core queries into full wavefronts was slower: their
+// wavefront-wide cell scans then run on too few wavefronts to fill the chip.)
 template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_points(TravArgs a) {
   const int m = tree_m(a.t);
@@ -683,7 +799,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
   const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
   const int i = pt ? a.prim_start[p] : 0;
   const bool ci = pt && (ALL_CORE || a.core[i]);
-  const bool mine = pt && (FIRST || ci);
+  const bool mine = pt && (ci || (FIRST && !is_lone(a, i)));
   const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
   int* labels = a.labels;
@@ -794,14 +910,17 @@ __global__ void k_main_dbx_cells(TravArgs a) {
 }
 
 // Canonical border pass for non-core points (all outside dense cells).
+// Queries: the listed non-core points whose neighbours were not all recorded
+// by the core pass (which wrote -1 for lone points; the records cover the rest).
 template <int D, bool B>
 __global__ void k_border_dbx(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
-  const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
-  const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
-  const int i = pt ? a.prim_start[p] : 0;
-  const bool mine = pt && !a.core[i];
+  const int nq = *a.qborder_n;
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nq);
+  const bool mine = k >= 0 && k < nq;
+  const int p = mine ? a.qborder[k] : 0;
+  const int i = mine ? a.prim_start[p] : 0;
   const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
   int best = 0x7fffffff;
@@ -888,6 +1007,7 @@ void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
 template <int D, bool B>
 void border_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
+  hipLaunchKernelGGL(k_border_rec, grid_of(a.brec_cap, 256), dim3(256), 0, s, a);
   if (densebox) hipLaunchKernelGGL((k_border_dbx<D, B>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_border_fdb<D, B>), g, b, 0, s, a);
 }

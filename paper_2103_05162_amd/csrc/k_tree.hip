@@ -86,18 +86,32 @@ struct Box {
   float lo[3], hi[3];
 };
 
+// Leaves are points (FDbscan: leaf l is sorted point l), or DenseBox
+// primitives: a dense cell's stored box, or the single point it starts at.
+struct LeafSrc {
+  const float4* lo;   // null: leaves are the sorted points
+  const float4* hi;
+  const int* start;
+  const int* cnt;
+};
+
 template <int D>
-__device__ __forceinline__ Box leaf_box(int l, const float* __restrict__ xs, int64_t n, const float4* prim_lo,
-                                        const float4* prim_hi) {
+__device__ __forceinline__ Box leaf_box(int l, const float* __restrict__ xs, int64_t n, const LeafSrc& ls) {
   Box b;
-  if (prim_lo) {
-    float4 a = prim_lo[l], c = prim_hi[l];
-    b.lo[0] = a.x; b.lo[1] = a.y; b.lo[2] = a.z;
-    b.hi[0] = c.x; b.hi[1] = c.y; b.hi[2] = c.z;
-  } else {
-    b.lo[0] = b.hi[0] = xs[l];
-    b.lo[1] = b.hi[1] = xs[n + l];
-    b.lo[2] = b.hi[2] = D == 3 ? xs[2 * n + l] : 0.0f;
+  int j = l;
+  if (ls.lo) {
+    if (ls.cnt[l] < 0) {
+      float4 a = ls.lo[l], c = ls.hi[l];
+      b.lo[0] = a.x; b.lo[1] = a.y; b.lo[2] = a.z;
+      b.hi[0] = c.x; b.hi[1] = c.y; b.hi[2] = c.z;
+      return b;
+    }
+    j = ls.start[l];
+  }
+  {
+    b.lo[0] = b.hi[0] = xs[j];
+    b.lo[1] = b.hi[1] = xs[n + j];
+    b.lo[2] = b.hi[2] = D == 3 ? xs[2 * n + j] : 0.0f;
   }
   return b;
 }
@@ -138,14 +152,13 @@ __device__ __forceinline__ Box load_node(const float4* node_a, const float4* nod
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
                                                   int64_t n,
-                                                  const float4* __restrict__ prim_lo, const float4* __restrict__ prim_hi,
-                                                  const int* __restrict__ other, const int* __restrict__ gamma,
+                                                  LeafSrc ls, const int* __restrict__ other, const int* __restrict__ gamma,
                                                   const int* __restrict__ parent, int* __restrict__ flags,
                                                   float4* node_a, float4* node_b, uint32_t* __restrict__ info) {
   const int m = d_m ? *d_m : m_cap;
   int l = blockIdx.x * kBlock + threadIdx.x;
   if (m < 2 || l >= m) return;
-  Box box = leaf_box<D>(l, xs, n, prim_lo, prim_hi);
+  Box box = leaf_box<D>(l, xs, n, ls);
   int prev = l;
   bool prev_leaf = true;
   int p = parent[(m - 1) + l];
@@ -166,9 +179,9 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
     const bool came_left = prev == g && prev_leaf == left_leaf;
     Box sib;
     if (came_left)
-      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, prim_lo, prim_hi) : load_node(node_a, node_b, g + 1);
+      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls) : load_node(node_a, node_b, g + 1);
     else
-      sib = left_leaf ? leaf_box<D>(g, xs, n, prim_lo, prim_hi) : load_node(node_a, node_b, g);
+      sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : load_node(node_a, node_b, g);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       box.lo[k] = fminf(box.lo[k], sib.lo[k]);
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
 // m_cap: number of primitives, or an upper bound when d_m (device) holds it.
 template <typename K>
 void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs, int64_t n_pts,
-             const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
+             const LeafSrc& ls, float4* node_a, float4* node_b, int* rope,
              int* leaf_rope, int* parent, int* flags, int* other, int* gamma, uint32_t* info, hipStream_t s) {
   if (m_cap <= 0) return;
   int g = static_cast<int>(ceil_div(m_cap, kBlock));
@@ -195,10 +208,10 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
   hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
   if (m_cap >= 2) {
     if (dim == 3)
-      hipLaunchKernelGGL(k_refit<3>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, prim_lo, prim_hi, other,
+      hipLaunchKernelGGL(k_refit<3>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other,
                          gamma, parent, flags, node_a, node_b, info);
     else
-      hipLaunchKernelGGL(k_refit<2>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, prim_lo, prim_hi, other,
+      hipLaunchKernelGGL(k_refit<2>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other,
                          gamma, parent, flags, node_a, node_b, info);
   }
 }
@@ -206,14 +219,16 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
 }  // namespace
 
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
-                const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* parent,
-                int* flags, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s) {
+                const float4* prim_hi, const int* prim_start, const int* prim_cnt, float4* node_a, float4* node_b,
+                int* rope, int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m,
+                uint32_t* info, hipStream_t s) {
+  const LeafSrc ls{prim_lo, prim_hi, prim_start, prim_cnt};
   if (key64)
-    build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, prim_lo, prim_hi, node_a, node_b, rope,
-            leaf_rope, parent, flags, other, gamma, info, s);
+    build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, parent,
+            flags, other, gamma, info, s);
   else
-    build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, prim_lo, prim_hi, node_a, node_b, rope,
-            leaf_rope, parent, flags, other, gamma, info, s);
+    build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, parent,
+            flags, other, gamma, info, s);
 }
 
 }  // namespace fdb

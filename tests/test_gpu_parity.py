@@ -236,3 +236,25 @@ def test_fdbscan_and_densebox_agree(dev):
     a = run_gpu(dev, pts, 0.01, 8, "fdbscan")
     b = run_gpu(dev, pts, 0.01, 8, "densebox")
     assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("d", [2, 3])
+def test_border_records_overflow_and_walk_fallback(dev, algo, d):
+    """Most points non-core with one neighbour (pairs): more border records than
+    the record buffer holds (n/8), so the rest take the walk path; plus blobs
+    whose fringe points have more neighbours than a record keeps (minPts 12)."""
+    rng = np.random.default_rng(40 + d)
+    eps = 0.01
+    npairs = 30000
+    side = int(np.ceil(npairs ** (1 / d)))
+    grid = np.stack(np.meshgrid(*[np.arange(side)] * d, indexing="ij"), -1).reshape(-1, d)[:npairs]
+    a = grid * (4 * eps) + rng.uniform(0, eps, size=(npairs, d))
+    off = rng.standard_normal((npairs, d))
+    off *= (0.5 * eps) / np.linalg.norm(off, axis=1, keepdims=True)
+    pairs = np.concatenate([a, a + off])
+    blobs = [rng.uniform(0, side * 4 * eps, size=d) + 0.6 * eps * rng.standard_normal((400, d)) for _ in range(12)]
+    pts = np.concatenate([pairs] + blobs).astype(np.float32)
+    pts = pts[rng.permutation(len(pts))]
+    for mp in (3, 12):
+        assert_exact(dev, pts, eps, mp, algo)
