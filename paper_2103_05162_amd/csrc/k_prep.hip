@@ -28,28 +28,12 @@ __global__ void k_fill_u8(uint8_t* __restrict__ p, uint8_t v, int64_t n) {
     p[i] = v;
 }
 
-// min/max per axis over all points; flags non-finite coordinates. bounds[0..2]
-// hold lo, bounds[4..6] hi, as order-preserving uints (pre-filled with
-// 0xffffffff / 0).
+// Workgroup reduction of per-thread axis bounds, then one atomic per axis.
+// bounds[0..2] hold lo, bounds[4..6] hi, as order-preserving uints (pre-filled
+// with 0xffffffff / 0).
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_bounds(const float* __restrict__ pts, int64_t n,
-                                                   uint32_t* __restrict__ bounds, uint32_t* __restrict__ info) {
-  float lo[D], hi[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    lo[k] = INFINITY;
-    hi[k] = -INFINITY;
-  }
-  bool bad = false;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      float v = pts[i * D + k];
-      bad |= !isfinite(v);
-      lo[k] = fminf(lo[k], v);
-      hi[k] = fmaxf(hi[k], v);
-    }
-  }
+__device__ __forceinline__ void bounds_reduce(float* lo, float* hi, bool bad, uint32_t* __restrict__ bounds,
+                                              uint32_t* __restrict__ info) {
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -84,6 +68,82 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float* __restrict__ pts
     }
   }
   if (threadIdx.x == 0 && s_bad) atomicOr(info, FDB_INFO_NONFINITE);
+}
+
+// min/max per axis over all points; flags non-finite coordinates (any layout).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bounds(const float* __restrict__ pts, int64_t n,
+                                                   uint32_t* __restrict__ bounds, uint32_t* __restrict__ info) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      float v = pts[i * D + k];
+      bad |= !isfinite(v);
+      lo[k] = fminf(lo[k], v);
+      hi[k] = fmaxf(hi[k], v);
+    }
+  }
+  bounds_reduce<D>(lo, hi, bad, bounds, info);
+}
+
+// Same over the coordinates as one flat float array read 16 bytes at a time
+// (pts 16-byte aligned). The grid stride is a multiple of D, so every chunk a
+// thread reads starts on the same axis: lane j of its float4s always holds
+// axis (4 c0 + j) mod D, and four running min/max pairs suffice.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bounds_v4(const float* __restrict__ pts, int64_t nflat,
+                                                      uint32_t* __restrict__ bounds, uint32_t* __restrict__ info) {
+  const float4* __restrict__ p4 = reinterpret_cast<const float4*>(pts);
+  const int64_t nch = nflat >> 2;
+  const int64_t T = int64_t(gridDim.x) * kBlock;
+  const int64_t c0 = blockIdx.x * int64_t(kBlock) + threadIdx.x;
+  float l4[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, h4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  auto take = [&](float4 v) {
+    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bad |= !isfinite(e[j]);
+      l4[j] = fminf(l4[j], e[j]);
+      h4[j] = fmaxf(h4[j], e[j]);
+    }
+  };
+  int64_t c = c0;
+  for (; c + 3 * T < nch; c += 4 * T) {
+    const float4 a = p4[c], b = p4[c + T], d = p4[c + 2 * T], f = p4[c + 3 * T];
+    take(a);
+    take(b);
+    take(d);
+    take(f);
+  }
+  for (; c < nch; c += T) take(p4[c]);
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = static_cast<int>((4 * c0 + j) % D);
+#pragma unroll
+    for (int kk = 0; kk < D; ++kk)
+      if (k == kk) {
+        lo[kk] = fminf(lo[kk], l4[j]);
+        hi[kk] = fmaxf(hi[kk], h4[j]);
+      }
+  }
+  if (c0 == 0) {  // the last nflat mod 4 coordinates
+    for (int64_t e = nch * 4; e < nflat; ++e) {
+      const float v = pts[e];
+      const int k = static_cast<int>(e % D);
+      bad |= !isfinite(v);
+#pragma unroll
+      for (int kk = 0; kk < D; ++kk)
+        if (k == kk) {
+          lo[kk] = fminf(lo[kk], v);
+          hi[kk] = fmaxf(hi[kk], v);
+        }
+    }
+  }
+  bounds_reduce<D>(lo, hi, bad, bounds, info);
 }
 
 __device__ __forceinline__ uint64_t spread3(uint32_t v) {  // 21 bits -> every third bit of 63
@@ -198,6 +258,16 @@ void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
 }
 
 void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint32_t* info, hipStream_t s) {
+  if ((reinterpret_cast<uintptr_t>(pts) & 15) == 0) {
+    const int64_t nflat = n * dim;
+    int g = grid_for(ceil_div(nflat, 4), kBlock * 8, 3072);
+    g = (g + dim - 1) / dim * dim;  // grid stride a multiple of dim
+    if (dim == 3)
+      hipLaunchKernelGGL(k_bounds_v4<3>, dim3(g), dim3(kBlock), 0, s, pts, nflat, bounds, info);
+    else
+      hipLaunchKernelGGL(k_bounds_v4<2>, dim3(g), dim3(kBlock), 0, s, pts, nflat, bounds, info);
+    return;
+  }
   int g = grid_for(n, kBlock * 16, 2048);
   if (dim == 3)
     hipLaunchKernelGGL(k_bounds<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, info);

@@ -241,24 +241,25 @@ __device__ __forceinline__ int block_reserve(int* n, bool pred, int* s_w) {
   return pred ? slot : -1;
 }
 
-// Up to kRecNb neighbouring primitives of one query, kept in registers.
+// Up to kRecNb neighbouring primitives of one query, kept in LDS: row t of the
+// workgroup's table (kRecNb x blockDim ints, dynamic shared memory) holds every
+// thread's t-th neighbour, so a neighbour costs one store.
 struct NbRec {
-  int nb[kRecNb];
+  int* col;  // &table[0][threadIdx.x]; entry t at col[t * blockDim.x]
   int nn;
 };
 
-__device__ __forceinline__ void rec_init(NbRec& r) {
+__device__ __forceinline__ void rec_init(NbRec& r, int* table) {
+  r.col = table + threadIdx.x;
   r.nn = 0;
-#pragma unroll
-  for (int t = 0; t < kRecNb; ++t) r.nb[t] = -1;
 }
 
 __device__ __forceinline__ void rec_add(NbRec& r, int j) {
-#pragma unroll
-  for (int t = 0; t < kRecNb; ++t)
-    if (t == r.nn) r.nb[t] = j;
+  if (r.nn < kRecNb) r.col[r.nn * blockDim.x] = j;
   ++r.nn;
 }
+
+__device__ __forceinline__ int rec_get(const NbRec& r, int t) { return r.col[t * blockDim.x]; }
 
 // End of a core pass for query point i (primitive p): core and lone flags, and
 // what the border pass will need: nothing (core, or lone: border -1 now), a
@@ -279,7 +280,7 @@ __device__ __forceinline__ void core_epilogue(const TravArgs& a, bool mine, int 
   if (stored) {
     a.brec_i[slot] = i;
 #pragma unroll
-    for (int t = 0; t < kRecNb; ++t) a.brec_nb[int64_t(slot) * kRecNb + t] = rec.nb[t];
+    for (int t = 0; t < kRecNb; ++t) a.brec_nb[int64_t(slot) * kRecNb + t] = t < rec.nn ? rec_get(rec, t) : -1;
   }
   const int wslot = block_reserve(a.qborder_n, want && !stored, s_w);
   if (wslot >= 0) a.qborder[wslot] = p;
@@ -298,6 +299,7 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
 template <int D, bool B>
 __global__ void k_core_fdb(TravArgs a) {
   __shared__ int s_w[17];
+  extern __shared__ int s_rec[];  // kRecNb * blockDim.x
   const int64_t i64 = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, a.n);
   const bool mine = i64 >= 0 && i64 < a.n;
   const int i = mine ? static_cast<int>(i64) : 0;
@@ -306,7 +308,7 @@ __global__ void k_core_fdb(TravArgs a) {
   const Query q = load_point<D>(a.xs, a.n, i);
   int cnt = 0;
   NbRec rec;
-  rec_init(rec);
+  rec_init(rec, s_rec);
   if (mine)
     traverse<D, false>(a.t, m, sc, q, 0, a.info, [&](int j) {
       if (!near<D>(a.xs, a.n, j, q, sc.eps2)) return false;
@@ -615,9 +617,12 @@ __device__ __forceinline__ bool cell_reaches_point(const float* __restrict__ xs,
   return false;
 }
 
-// Is some pair (a in cell A, b in cell B) within eps? (whole wavefront; lanes
-// hold A's points, B's points are streamed; A's points out of reach of B's box
-// sit out)
+// Is some pair (a in cell A, b in cell B) within eps? (whole wavefront.) A's
+// points are taken 64 at a time, keeping those within eps of B's box; B's
+// points are loaded 64 at a time too, keeping those within eps of the box of
+// the kept A points (box gaps never exceed point distances, so nothing that
+// could pass is dropped), and each kept B point is tested against all kept A
+// points at once.
 template <int D>
 __device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_t n, int sa, int na, int sb, int nb,
                                            float4 blo, float4 bhi, float eps2) {
@@ -633,10 +638,30 @@ __device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_
       act = box_dist2<D>(ax, ay, az, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) <= eps2;
     }
     if (!ballot(act)) continue;
-    for (int jb = sb; jb < sb + nb; ++jb) {
-      const float bx = xs[jb], by = xs[n + jb], bz = D == 3 ? xs[2 * n + jb] : 0.0f;
-      const bool h = act && dist2v<D>(ax, ay, az, bx, by, bz) <= eps2;
-      if (ballot(h)) return true;
+    float lo[3] = {act ? ax : INFINITY, act ? ay : INFINITY, act ? az : INFINITY};
+    float hi[3] = {act ? ax : -INFINITY, act ? ay : -INFINITY, act ? az : -INFINITY};
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
+        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
+      }
+    if (D == 2) lo[2] = hi[2] = 0.0f;
+    for (int bb = 0; bb < nb; bb += 64) {
+      bool near_b = bb + lane < nb;
+      float bx = 0.0f, by = 0.0f, bz = 0.0f;
+      if (near_b) {
+        const int64_t j = sb + bb + lane;
+        bx = xs[j];
+        by = xs[n + j];
+        bz = D == 3 ? xs[2 * n + j] : 0.0f;
+        near_b = box_dist2<D>(bx, by, bz, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]) <= eps2;
+      }
+      for (uint64_t bm = ballot(near_b); bm; bm &= bm - 1) {
+        const int k = __ffsll(static_cast<unsigned long long>(bm)) - 1;
+        const float px = readlane_f(bx, k), py = readlane_f(by, k), pz = readlane_f(bz, k);
+        if (ballot(act && dist2v<D>(ax, ay, az, px, py, pz) <= eps2)) return true;
+      }
     }
   }
   return false;
@@ -684,8 +709,22 @@ __device__ __forceinline__ void walk_init(Walk& w, int m, const Scope& sc, int m
 
 __device__ __forceinline__ bool walk_done(const Walk& w) { return w.node == kEnd && w.cur > w.end; }
 
-template <int D, bool MASKED>
-__device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, const Query& q, float eps2, int mask,
+// A box query (every point of [lo, hi]); walk_step takes it or a point.
+struct BoxQ {
+  float lo[3], hi[3];
+};
+
+template <int D>
+__device__ __forceinline__ float node_gap2(const Query& q, float4 a, float4 b) {
+  return box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z);
+}
+template <int D>
+__device__ __forceinline__ float node_gap2(const BoxQ& q, float4 a, float4 b) {
+  return boxbox_dist2<D>(q.lo, q.hi, a.x, a.y, a.z, b.x, b.y, b.z);
+}
+
+template <int D, bool MASKED, typename QT>
+__device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, const QT& q, float eps2, int mask,
                                          uint32_t* info) {
   if (w.cur <= w.end) return w.cur++;
   const uint32_t node = w.node;
@@ -715,7 +754,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   const int k = static_cast<int>(node);
   const int o = __float_as_int(a.w), g = __float_as_int(b.w);
   const int first = o < k ? o : k, last = o > k ? o : k;
-  if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > eps2) {
+  if (node_gap2<D>(q, a, b) > eps2) {
     w.node = last >= w.last ? kEnd : static_cast<uint32_t>(t.rope[node]);
     return -1;
   }
@@ -741,6 +780,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
 template <int D, bool B>
 __global__ void k_core_dbx(TravArgs a) {
   __shared__ int s_w[17];
+  extern __shared__ int s_rec[];  // kRecNb * blockDim.x
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
@@ -750,7 +790,7 @@ __global__ void k_core_dbx(TravArgs a) {
   const Query q = load_point<D>(a.xs, a.n, i);
   int cnt = 0;
   NbRec rec;
-  rec_init(rec);
+  rec_init(rec, s_rec);
   Walk w;
   walk_init<false>(w, m, sc, 0, mine);
   bool active = mine && !walk_done(w);
@@ -850,12 +890,19 @@ __global__ void k_main_dbx_points(TravArgs a) {
   }
 }
 
-// Main phase, dense cells: one wavefront per cell A walks the tree once with
-// A's box, over primitives above A; a dense neighbour B joins A's set if some
-// pair is within eps, a core point if some point of A reaches it, and (first-
-// claim mode) a non-core point is claimed the same way.
+// Main phase, dense cells, when there are few of them (at most
+// kCellsPerWaveMax): one wavefront per cell A walks the tree once with A's box,
+// over primitives above A; a dense neighbour B joins A's set if some pair is
+// within eps, a core point if some point of A reaches it, and (first-claim
+// mode) a non-core point is claimed the same way. Many cells go to
+// k_main_dbx_cells_lane instead (the two kernels are launched together and each
+// leaves the other's case alone).
+constexpr int kCellsPerWaveMax = 65536;
+
 template <int D, bool ALL_CORE, bool FIRST, bool B>
-__global__ void k_main_dbx_cells(TravArgs a) {
+__global__ void k_main_dbx_cells_wave(TravArgs a) {
+  const int nd = *a.d_ndense;
+  if (nd > kCellsPerWaveMax) return;
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int wave = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
@@ -863,7 +910,6 @@ __global__ void k_main_dbx_cells(TravArgs a) {
   int* labels = a.labels;
   // wavefront w takes a contiguous slice of the dense-cell list (filled in
   // roughly increasing key order), so neighbouring cells share an XCD's L2
-  const int nd = *a.d_ndense;
   const int per = (nd + nwaves - 1) / nwaves;
   const int dbeg = wave * per, dend = min(nd, dbeg + per);
   for (int w = dbeg; w < dend; ++w) {
@@ -906,6 +952,82 @@ __global__ void k_main_dbx_cells(TravArgs a) {
       }
       return false;
     });
+  }
+}
+
+// Main phase, dense cells, when there are many (more than kCellsPerWaveMax,
+// e.g. a batch of many clouds): one lane per dense cell A, walking (in
+// lock-step with the other lanes of its wavefront) with A's box over the
+// primitives above A, with the same rules as above; each pair test runs on the
+// whole wavefront (64 points per ballot), one pending lane after another.
+template <int D, bool ALL_CORE, bool FIRST, bool B>
+__global__ void k_main_dbx_cells_lane(TravArgs a) {
+  const int nd = *a.d_ndense;
+  if (nd <= kCellsPerWaveMax) return;
+  const int m = tree_m(a.t);
+  const int lane = lane_id();
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nd);
+  const bool mine = k >= 0 && k < nd;
+  const int A = mine ? a.dense_list[k] : 0;
+  const int sa = mine ? a.prim_start[A] : 0;
+  const int na = mine ? -a.prim_cnt[A] : 0;
+  const Scope sc = scope_of<B>(a, m, sa);
+  BoxQ qa;
+  {
+    const float4 lo = mine ? a.prim_lo[A] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 hi = mine ? a.prim_hi[A] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    qa.lo[0] = lo.x; qa.lo[1] = lo.y; qa.lo[2] = lo.z;
+    qa.hi[0] = hi.x; qa.hi[1] = hi.y; qa.hi[2] = hi.z;
+  }
+  int* labels = a.labels;
+  int root = sa;
+  Walk w;
+  walk_init<true>(w, m, sc, A, mine);
+  bool active = mine && !walk_done(w);
+  while (ballot(active)) {
+    int pend = -1;
+    if (active) {
+      const int r = walk_step<D, true>(w, a.t, m, qa, sc.eps2, A, a.info);
+      if (r >= 0) {
+        const int c = a.prim_cnt[r], s = a.prim_start[r];
+        if (c > 0) {
+          const float px = a.xs[s], py = a.xs[a.n + s], pz = D == 3 ? a.xs[2 * a.n + s] : 0.0f;
+          if (box_dist2<D>(px, py, pz, qa.lo[0], qa.lo[1], qa.lo[2], qa.hi[0], qa.hi[1], qa.hi[2]) <= sc.eps2) {
+            if (ALL_CORE || a.core[s]) {
+              if (!known_same_set(labels, s, root)) pend = r;
+            } else if (FIRST && labels[s] == s) {
+              pend = r;
+            }
+          }
+        } else {
+          const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
+          if (boxbox_dist2<D>(qa.lo, qa.hi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) <= sc.eps2 &&
+              !known_same_set(labels, s, root))
+            pend = r;
+        }
+      }
+    }
+    for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
+      const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+      const int r = __shfl(pend, L);
+      const int sA = __shfl(sa, L), nA = __shfl(na, L);
+      const float e2 = readlane_f(sc.eps2, L);
+      const int c = a.prim_cnt[r], s = a.prim_start[r];
+      bool hit;
+      if (c > 0) {
+        const float px = a.xs[s], py = a.xs[a.n + s], pz = D == 3 ? a.xs[2 * a.n + s] : 0.0f;
+        hit = cell_reaches_point<D>(a.xs, a.n, sA, nA, px, py, pz, e2);
+      } else {
+        hit = cells_touch<D>(a.xs, a.n, sA, nA, s, -c, a.prim_lo[r], a.prim_hi[r], e2);
+      }
+      if (lane == L && hit) {
+        if (c > 0 && !(ALL_CORE || a.core[s]))
+          uf_claim(labels, s, sA);  // first-claim mode: a non-core neighbour joins A's cluster
+        else
+          root = uf_union(labels, root, s, a.info);
+      }
+    }
+    if (active && walk_done(w)) active = false;
   }
 }
 
@@ -984,8 +1106,9 @@ inline dim3 grid_of(int64_t n, int block) {
 template <int D, bool B>
 void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
-  if (densebox) hipLaunchKernelGGL((k_core_dbx<D, B>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, 0, s, a);
+  const size_t lds = sizeof(int) * kRecNb * a.block;  // neighbour records
+  if (densebox) hipLaunchKernelGGL((k_core_dbx<D, B>), g, b, lds, s, a);
+  else hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, lds, s, a);
 }
 
 // part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
@@ -993,7 +1116,13 @@ template <int D, bool ALL, bool FIRST, bool B>
 void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
   if (densebox) {
-    if (part != 2) hipLaunchKernelGGL((k_main_dbx_cells<D, ALL, FIRST, B>), dim3(2048), dim3(256), 0, s, a);
+    if (part != 2) {
+      hipLaunchKernelGGL((k_main_dbx_cells_wave<D, ALL, FIRST, B>), dim3(2048), dim3(256), 0, s, a);
+      // dense cells hold >= minPts points each, so there are at most n / minPts
+      const int64_t max_cells = a.min_pts > 1 ? a.n / a.min_pts + 1 : a.n;
+      if (max_cells > kCellsPerWaveMax)
+        hipLaunchKernelGGL((k_main_dbx_cells_lane<D, ALL, FIRST, B>), grid_of(max_cells, a.block), b, 0, s, a);
+    }
     if (part != 1) hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST, B>), g, b, 0, s, a);
   } else if (FIRST) {
     hipLaunchKernelGGL((k_main_fdb_first<D, B>), g, b, 0, s, a);

@@ -258,3 +258,41 @@ def test_border_records_overflow_and_walk_fallback(dev, algo, d):
     pts = pts[rng.permutation(len(pts))]
     for mp in (3, 12):
         assert_exact(dev, pts, eps, mp, algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_unaligned_input_pointer(dev, algo):
+    """Points starting 12 bytes into an allocation (not 16-byte aligned) take the
+    scalar bounds path; labels must not change."""
+    import torch
+    import paper_2103_05162_amd as fdb
+    pts = _mixture(77, 20001, 3, 12, 0.01)
+    base = torch.from_numpy(np.concatenate([np.zeros((1, 3), np.float32), pts])).to(dev)
+    view = base[1:]
+    assert view.data_ptr() % 16 != 0
+    ref = oracle.dbscan(pts, 0.01, 5)
+    lab, core, k = fdb.dbscan(view, 0.01, 5, algo=algo)
+    torch.cuda.synchronize()
+    assert k == ref[2]
+    assert np.array_equal(lab.cpu().numpy(), ref[0]) and np.array_equal(core.cpu().numpy(), ref[1])
+
+
+@pytest.mark.parametrize("border", ["canonical", "first"])
+def test_many_dense_cells(dev, border):
+    """More dense cells than the wavefront-per-cell kernel takes (65,536): 100k
+    tight clumps of 12 points, each spread over a few cells that must merge."""
+    rng = np.random.default_rng(91)
+    k, per = 100_000, 12
+    centers = rng.uniform(0, 1, size=(k, 3))
+    pts = (np.repeat(centers, per, axis=0) + 5e-4 * rng.standard_normal((k * per, 3))).astype(np.float32)
+    pts = pts[rng.permutation(len(pts))]
+    eps, mp = 0.003, 5
+    ref = oracle.dbscan(pts, eps, mp)
+    _say(f"[gpu] many dense cells: n={len(pts)} K={ref[2]} ({border})")
+    if border == "canonical":
+        assert_exact(dev, pts, eps, mp, "densebox", ref=ref)
+        assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
+    else:
+        lab, core, kk = run_gpu(dev, pts, eps, mp, "densebox", border="first")
+        assert kk == ref[2]
+        assert_tolerance_mode(pts, eps, lab, core, ref[0], ref[1], oracle.check_border)
