@@ -63,7 +63,7 @@ def parse():
                     help="volume fraction of the spatial window the CPU oracle clusters")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
-    ap.add_argument("--batched-algo", default="fdbscan", choices=["none", "densebox", "fdbscan"],
+    ap.add_argument("--batched-algo", default="densebox", choices=["none", "densebox", "fdbscan"],
                     help="algorithm of the batched many-cloud leg (none = skip it)")
     ap.add_argument("--clouds", type=int, default=4096, help="clouds in the batched leg")
     ap.add_argument("--served-algo", default="densebox", choices=["none", "densebox", "fdbscan"],
