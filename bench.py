@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--batched-algo", default="densebox", choices=["none", "densebox", "fdbscan"],
                     help="algorithm of the batched many-cloud leg (none = skip it)")
     ap.add_argument("--clouds", type=int, default=4096, help="clouds in the batched leg")
+    ap.add_argument("--loop-passes", type=int, default=1,
+                    help="timed passes of the one-call-per-cloud loop beside the batch (0 = skip it)")
     ap.add_argument("--served-algo", default="densebox", choices=["none", "densebox", "fdbscan"],
                     help="algorithm of the served leg (none = skip it)")
     ap.add_argument("--requests", type=int, default=22000, help="requests in the served trace")
@@ -150,6 +152,9 @@ def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
             h.dbscan_raw(bp + 12 * b, nc, 3, float(eps[c]), int(mp[c]), lp + 4 * b, cp + b, stream, opt, False,
                          wp, wsz)
 
+    if loop_passes <= 0:
+        return dict(ms=ms, loop_ms=None, n=n, identical=None, info=info,
+                    stages={k2: v / max(calls, 1) for k2, v in stages.items()}, clusters=int(ncl.sum().item()))
     loop()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -408,8 +413,8 @@ def main():
         del pts
         torch.cuda.empty_cache()
         log(f"[bench] batched leg ({args.batched_algo})")
-        b = time_batched(fdb, h, args.batched_algo, args.steps, args.warmup, args.clouds, 1)
-        log(f"[bench] batched: {b['ms']:.2f} ms per batch, loop {b['loop_ms']:.2f} ms, identical={b['identical']}")
+        b = time_batched(fdb, h, args.batched_algo, args.steps, args.warmup, args.clouds, args.loop_passes)
+        log(f"[bench] batched: {b['ms']:.2f} ms per batch, loop {b['loop_ms']} ms, identical={b['identical']}")
         for st, v in sorted(b["stages"].items(), key=lambda kv: -kv[1]):
             log(f"    {st:12s} {v:9.3f} ms")
         out["batched"] = {
@@ -418,9 +423,9 @@ def main():
             "algo": args.batched_algo, "ms_per_batch": round(b["ms"], 3),
             "clouds_per_s": round(args.clouds / (b["ms"] / 1e3), 1),
             "mpts_per_s": round(b["n"] / (b["ms"] / 1e3) / 1e6, 3),
-            "loop_ms": round(b["loop_ms"], 3),
-            "loop_clouds_per_s": round(args.clouds / (b["loop_ms"] / 1e3), 1),
-            "speedup_vs_loop": round(b["loop_ms"] / b["ms"], 3),
+            "loop_ms": round(b["loop_ms"], 3) if b["loop_ms"] else None,
+            "loop_clouds_per_s": round(args.clouds / (b["loop_ms"] / 1e3), 1) if b["loop_ms"] else None,
+            "speedup_vs_loop": round(b["loop_ms"] / b["ms"], 3) if b["loop_ms"] else None,
             "identical_to_loop": b["identical"], "clusters": b["clusters"], "info": b["info"],
             "stages_ms": {k2: round(v, 4) for k2, v in b["stages"].items()}}
     if args.served_algo != "none":

@@ -10,6 +10,8 @@
 // evaluated with the same fp32 operations. Rounded subtraction is monotone, so
 // then every pair of points in the cell passes the test, whatever rounding the
 // cell index computation suffered.
+#include <algorithm>
+
 #include "fdb_device.hpp"
 #include "fdb_internal.hpp"
 
@@ -53,15 +55,48 @@ __device__ __forceinline__ float cell_eps2(const CloudParams& cp, int head, floa
   return cp.eps2 ? cp.eps2[cp.keys[head] >> cp.shift] : eps2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_candidates(const int* __restrict__ cell_start,
-                                                            const int* __restrict__ num_cells, int min_pts,
-                                                            CloudParams cp, int* __restrict__ cand,
-                                                            int* __restrict__ num_cand, uint8_t* __restrict__ dense) {
+// Append value to list (counter *n) on every thread where pred holds: one
+// atomic per workgroup, threads in order within it (lists stay roughly in key
+// order). Every thread of the workgroup must call it; s_w holds 17 ints. Many
+// workgroups appending to one counter serialise on it, so the kernels using
+// this run 1024-thread workgroups.
+constexpr int kPushBlock = 1024;
+__device__ __forceinline__ void block_push(int* list, int* n, bool pred, int value, int* s_w) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t b = ballot(pred);
+  if (lane_id() == 0) s_w[w] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < nw; ++k) {
+      const int c = s_w[k];
+      s_w[k] = tot;
+      tot += c;
+    }
+    s_w[16] = tot ? atomicAdd(n, tot) : 0;
+  }
+  __syncthreads();
+  if (pred) list[s_w[16] + s_w[w] + __popcll(b & lanemask_lt())] = value;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kPushBlock) void k_cell_candidates(const int* __restrict__ cell_start,
+                                                                const int* __restrict__ num_cells, int min_pts,
+                                                                CloudParams cp, int* __restrict__ cand,
+                                                                int* __restrict__ num_cand,
+                                                                uint8_t* __restrict__ dense) {
+  __shared__ int s_w[17];
   const int nc = *num_cells;
-  for (int c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
-    int cnt = cell_start[c + 1] - cell_start[c];
-    dense[c] = 0;
-    if (cnt >= cell_minpts(cp, cell_start[c], min_pts)) cand[atomicAdd(num_cand, 1)] = c;
+  // every thread of a workgroup runs the same trip count (block_push synchronises)
+  for (int base = blockIdx.x * kPushBlock; base < nc; base += gridDim.x * kPushBlock) {
+    const int c = base + static_cast<int>(threadIdx.x);
+    bool cand_c = false;
+    if (c < nc) {
+      const int cnt = cell_start[c + 1] - cell_start[c];
+      dense[c] = 0;
+      cand_c = cnt >= cell_minpts(cp, cell_start[c], min_pts);
+    }
+    block_push(cand, num_cand, cand_c, c, s_w);
   }
 }
 
@@ -118,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_prim_flags(const int* __restrict__ c
 // pidx holds the exclusive scan of pflag: the primitive index of every point
 // that opens a primitive (a point outside dense cells, or a dense cell's first).
 template <int D, typename K>
-__global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, const float* __restrict__ xs, int64_t n,
+__global__ __launch_bounds__(kPushBlock) void k_prims(const K* __restrict__ keys, const float* __restrict__ xs, int64_t n,
                                                   const int* __restrict__ cell_id, const int* __restrict__ cell_start,
                                                   const uint8_t* __restrict__ dense, const float4* __restrict__ cell_lo,
                                                   const float4* __restrict__ cell_hi, const int* __restrict__ pidx,
@@ -127,30 +162,40 @@ __global__ __launch_bounds__(kBlock) void k_prims(const K* __restrict__ keys, co
                                                   float4* __restrict__ prim_hi, K* __restrict__ prim_key,
                                                   int* __restrict__ dense_list, int* __restrict__ num_dense,
                                                   int* __restrict__ labels, uint8_t* __restrict__ core) {
-  for (int64_t i64 = blockIdx.x * int64_t(kBlock) + threadIdx.x; i64 < n; i64 += int64_t(gridDim.x) * kBlock) {
-    const int i = static_cast<int>(i64);
-    const int c = cell_id[i];
-    const int s = cell_start[c];
-    if (dense[c]) {
-      const int p = pidx[s];
-      labels[i] = s;
-      core[i] = 1;
-      if (i == s) {
-        prim_start[p] = s;
-        prim_cnt[p] = -(cell_start[c + 1] - s);
-        prim_lo[p] = cell_lo[c];
-        prim_hi[p] = cell_hi[c];
+  __shared__ int s_w[17];
+  // Every thread of a workgroup runs the same trip count and reaches the one
+  // block_push call of each trip (it synchronises the workgroup).
+  for (int64_t base = blockIdx.x * int64_t(kPushBlock); base < n; base += int64_t(gridDim.x) * kPushBlock) {
+    const int64_t i64 = base + threadIdx.x;
+    bool opens_dense = false;
+    int pd = 0;
+    if (i64 < n) {
+      const int i = static_cast<int>(i64);
+      const int c = cell_id[i];
+      const int s = cell_start[c];
+      opens_dense = dense[c] && i == s;
+      if (dense[c]) {
+        const int p = pidx[s];
+        labels[i] = s;
+        core[i] = 1;
+        if (opens_dense) {
+          prim_start[p] = s;
+          prim_cnt[p] = -(cell_start[c + 1] - s);
+          prim_lo[p] = cell_lo[c];
+          prim_hi[p] = cell_hi[c];
+          prim_key[p] = keys[i];
+          pd = p;
+        }
+      } else {
+        const int p = pidx[i];  // a point primitive: its box is the point (never stored)
+        labels[i] = i;
+        core[i] = 0;
+        prim_start[p] = i;
+        prim_cnt[p] = 1;
         prim_key[p] = keys[i];
-        dense_list[atomicAdd(num_dense, 1)] = p;
       }
-    } else {
-      const int p = pidx[i];  // a point primitive: its box is the point (never stored)
-      labels[i] = i;
-      core[i] = 0;
-      prim_start[p] = i;
-      prim_cnt[p] = 1;
-      prim_key[p] = keys[i];
     }
+    block_push(dense_list, num_dense, opens_dense, pd, s_w);
   }
 }
 
@@ -176,8 +221,9 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   device_scan(pflag, cell_id, n, nullptr, bsums, scan_blocks, d_cells, s);
   hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(kBlock), 0, s, pflag, n, cell_id, cell_start, d_cells);
   fill_u32(reinterpret_cast<uint32_t*>(d_cand), 0, 1, s);
-  hipLaunchKernelGGL(k_cell_candidates, dim3(g), dim3(kBlock), 0, s, cell_start, d_cells, min_pts, cp, cand, d_cand,
-                     dense);
+  const int gp = static_cast<int>(std::min<int64_t>(ceil_div(n, kPushBlock), 65536));
+  hipLaunchKernelGGL(k_cell_candidates, dim3(gp), dim3(kPushBlock), 0, s, cell_start, d_cells, min_pts, cp, cand,
+                     d_cand, dense);
   const int gb = 2048;  // 8192 wavefronts, grid-stride over candidate cells
   if (dim == 3)
     hipLaunchKernelGGL(k_cell_boxes<3>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
@@ -189,11 +235,11 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   int* pidx = cand;  // candidates are no longer needed; reuse for primitive indices
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
   if (dim == 3)
-    hipLaunchKernelGGL((k_prims<3, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+    hipLaunchKernelGGL((k_prims<3, K>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
                        cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
   else
-    hipLaunchKernelGGL((k_prims<2, K>), dim3(g), dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+    hipLaunchKernelGGL((k_prims<2, K>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
                        cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
 }

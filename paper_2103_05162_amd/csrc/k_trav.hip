@@ -261,6 +261,11 @@ __device__ __forceinline__ void rec_add(NbRec& r, int j) {
 
 __device__ __forceinline__ int rec_get(const NbRec& r, int t) { return r.col[t * blockDim.x]; }
 
+// Records tell a dense cell (stored as -2 - its first point) from a point.
+__device__ __forceinline__ int cell_ref(int s) { return -2 - s; }
+__device__ __forceinline__ bool is_cell_ref(int v) { return v < -1; }
+__device__ __forceinline__ int ref_point(int v) { return v < -1 ? -2 - v : v; }
+
 // End of a core pass for query point i (primitive p): core and lone flags, and
 // what the border pass will need: nothing (core, or lone: border -1 now), a
 // neighbour record, or a walk. Called by every thread of the workgroup.
@@ -273,6 +278,16 @@ __device__ __forceinline__ void core_epilogue(const TravArgs& a, bool mine, int 
     a.lone[i] = lone ? 1 : 0;
     if (lone) a.border[i] = -1;
   }
+  if (core) {
+    // A core point and a dense cell it reaches are a core pair: join them now,
+    // so the main phase finds them in one set and skips the cell scan.
+    const int nr = rec.nn < kRecNb ? rec.nn : kRecNb;
+    int root = i;
+    for (int t = 0; t < nr; ++t) {
+      const int v = rec_get(rec, t);
+      if (is_cell_ref(v)) root = uf_union(a.labels, root, ref_point(v), a.info);
+    }
+  }
   const bool want = mine && !core && !lone;
   const bool fits = want && rec.nn <= kRecNb;
   const int slot = block_reserve(a.brec_n, fits, s_w);
@@ -280,7 +295,8 @@ __device__ __forceinline__ void core_epilogue(const TravArgs& a, bool mine, int 
   if (stored) {
     a.brec_i[slot] = i;
 #pragma unroll
-    for (int t = 0; t < kRecNb; ++t) a.brec_nb[int64_t(slot) * kRecNb + t] = t < rec.nn ? rec_get(rec, t) : -1;
+    for (int t = 0; t < kRecNb; ++t)
+      a.brec_nb[int64_t(slot) * kRecNb + t] = t < rec.nn ? ref_point(rec_get(rec, t)) : -1;
   }
   const int wslot = block_reserve(a.qborder_n, want && !stored, s_w);
   if (wslot >= 0) a.qborder[wslot] = p;
@@ -819,7 +835,7 @@ __global__ void k_core_dbx(TravArgs a) {
                                            __shfl(q.z, L), readlane_f(sc.eps2, L), want);
       if (lane == L && found > 0) {
         cnt += found;
-        rec_add(rec, s);  // a dense cell: all core, one cluster; its first point stands for it
+        rec_add(rec, cell_ref(s));  // a dense cell: all core, one cluster; its first point stands for it
       }
     }
     if (active && (cnt >= sc.min_pts || walk_done(w))) active = false;
@@ -843,7 +859,8 @@ __global__ void k_main_dbx_points(TravArgs a) {
   const Scope sc = scope_of<B>(a, m, i);
   const Query q = load_point<D>(a.xs, a.n, i);
   int* labels = a.labels;
-  int root = i;
+  // the core pass may already have joined i to dense cells it reaches
+  int root = mine && ci ? uf_find(labels, i, a.info) : i;
   Walk w;
   walk_init<true>(w, m, sc, p, mine);
   bool active = mine && !walk_done(w);
