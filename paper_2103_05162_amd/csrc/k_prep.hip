@@ -260,7 +260,8 @@ void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
 void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint32_t* info, hipStream_t s) {
   if ((reinterpret_cast<uintptr_t>(pts) & 15) == 0) {
     const int64_t nflat = n * dim;
-    int g = grid_for(ceil_div(nflat, 4), kBlock * 8, 3072);
+    // few workgroups (each ends with one atomic per axis bound on shared words)
+    int g = grid_for(ceil_div(nflat, 4), kBlock * 8, 768);
     g = (g + dim - 1) / dim * dim;  // grid stride a multiple of dim
     if (dim == 3)
       hipLaunchKernelGGL(k_bounds_v4<3>, dim3(g), dim3(kBlock), 0, s, pts, nflat, bounds, info);

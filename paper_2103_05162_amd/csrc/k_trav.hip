@@ -110,14 +110,16 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Scope& 
       atomicOr(info, kInternalBit);
       return;
     }
+    // the escape link is loaded with the node, not after its box test fails
     const float4 a = t.node_a[node];
     const float4 b = t.node_b[node];
+    const uint32_t esc = static_cast<uint32_t>(t.rope[node]);
     const int k = static_cast<int>(node);
     const int o = __float_as_int(a.w), g = __float_as_int(b.w);
     const int first = o < k ? o : k, last = o > k ? o : k;
     if (box_dist2<D>(q.x, q.y, q.z, a.x, a.y, a.z, b.x, b.y, b.z) > sc.eps2) {
       if (last >= sc.end) return;
-      node = static_cast<uint32_t>(t.rope[node]);
+      node = esc;
       continue;
     }
     if (first < 0 || last >= m || g < first || g >= last) {
@@ -130,7 +132,7 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Scope& 
       for (int l = s; l <= last; ++l)
         if (visit(l)) return;
       if (last >= sc.end) return;
-      node = static_cast<uint32_t>(t.rope[node]);
+      node = esc;
       continue;
     }
     if (MASKED && g <= mask)
@@ -173,12 +175,13 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
     }
     const float4 na = t.node_a[node];
     const float4 nb = t.node_b[node];
+    const uint32_t esc = static_cast<uint32_t>(t.rope[node]);
     const int k = static_cast<int>(node);
     const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
     const int first = o < k ? o : k, last = o > k ? o : k;
     if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > sc.eps2) {
       if (last >= sc.end) return;
-      node = static_cast<uint32_t>(t.rope[node]);
+      node = esc;
       continue;
     }
     if (first < 0 || last >= m || g < first || g >= last) {
@@ -189,7 +192,7 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
       int s = first <= mask ? mask + 1 : first;
       if (s <= last && visit(s, last)) return;
       if (last >= sc.end) return;
-      node = static_cast<uint32_t>(t.rope[node]);
+      node = esc;
       continue;
     }
     if (g <= mask)
@@ -767,11 +770,12 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   }
   const float4 a = t.node_a[node];
   const float4 b = t.node_b[node];
+  const uint32_t esc = static_cast<uint32_t>(t.rope[node]);  // loaded with the node
   const int k = static_cast<int>(node);
   const int o = __float_as_int(a.w), g = __float_as_int(b.w);
   const int first = o < k ? o : k, last = o > k ? o : k;
   if (node_gap2<D>(q, a, b) > eps2) {
-    w.node = last >= w.last ? kEnd : static_cast<uint32_t>(t.rope[node]);
+    w.node = last >= w.last ? kEnd : esc;
     return -1;
   }
   if (first < 0 || last >= m || g < first || g >= last) {
@@ -782,7 +786,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   if (last - first < t.leaf_size) {
     w.cur = (MASKED && first <= mask) ? mask + 1 : first;
     w.end = last;
-    w.node = last >= w.last ? kEnd : static_cast<uint32_t>(t.rope[node]);
+    w.node = last >= w.last ? kEnd : esc;
     return w.cur <= w.end ? w.cur++ : -1;
   }
   if (MASKED && g <= mask)
