@@ -56,7 +56,14 @@ typedef enum {
 
 typedef enum {
   FDB_ALGO_FDBSCAN = 0,  /* LBVH over all points (Section 4.1) */
-  FDB_ALGO_DENSEBOX = 1  /* LBVH over dense eps/sqrt(d) grid cells + other points (Section 4.2) */
+  FDB_ALGO_DENSEBOX = 1, /* LBVH over dense eps/sqrt(d) grid cells + other points (Section 4.2) */
+  /* Choose per input (Sections 5-6 leave the choice to a rule of thumb). Measured
+     here, DenseBox is never more than ~15% slower than FDbscan (sparse data with
+     no dense cells) and up to 20x faster, and the share of points in dense cells
+     does not predict the rare cases FDbscan wins; so the choice is DenseBox,
+     and FDbscan when the grid cannot be keyed (FDB_INFO_AUTO_FDBSCAN then).
+     Batches (fdb_dbscan_batched) run DenseBox. */
+  FDB_ALGO_AUTO = 2
 } fdb_algo;
 
 typedef enum {
@@ -68,7 +75,11 @@ typedef enum {
   /* The paper's rule (Section 3.2): a border point joins the first cluster whose
      compare-and-swap claims it. Core flags, noise and the core partition are as in
      canonical mode; the choice among eligible clusters depends on timing. */
-  FDB_BORDER_FIRST = 1
+  FDB_BORDER_FIRST = 1,
+  /* DBSCAN* (Section 2.1 names it; Section 6 lists it as future work): border
+     points are not cluster members, so every non-core point is noise (-1). The
+     clusters, their ids and K are those of canonical mode. */
+  FDB_BORDER_NONE = 2
 } fdb_border;
 
 typedef struct {
@@ -85,8 +96,9 @@ enum {
                                       keys (eps tiny against the extent): FDbscan ran instead. */
   FDB_INFO_NONFINITE = 2u,         /* a NaN or infinite coordinate was seen; labels are undefined */
   FDB_INFO_INTERNAL = 4u,          /* a kernel stopped a walk that broke its own bounds; labels undefined */
-  FDB_INFO_BAD_PARAMS = 8u         /* batch: some cloud's eps is not finite and > 0, or its minPts < 1;
+  FDB_INFO_BAD_PARAMS = 8u,        /* batch: some cloud's eps is not finite and > 0, or its minPts < 1;
                                       that cloud's labels are undefined */
+  FDB_INFO_AUTO_FDBSCAN = 16u       /* FDB_ALGO_AUTO could not key the grid and ran FDbscan */
 };
 
 /* Create a handle bound to HIP device `device`. *out receives the handle. */

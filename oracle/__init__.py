@@ -121,6 +121,15 @@ def dbscan(points, eps: float, min_pts: int, method: str = "auto", threads: int 
     return labels, core.astype(bool), int(k)
 
 
+def dbscan_star(points, eps: float, min_pts: int, method: str = "auto", threads: int = 0):
+    """DBSCAN* (Section 2.1): the clusters are the connected components of the
+    core points, and every non-core point is noise. Cluster ids are the
+    canonical ones (they depend on core points only)."""
+    labels, core, k = dbscan(points, eps, min_pts, method, threads)
+    labels = np.where(core, labels, -1).astype(np.int32)
+    return labels, core, k
+
+
 def check_border(points, eps: float, is_core, labels, method: str = "auto", threads: int = 0) -> int:
     """Number of non-core points whose label breaks the definition: a labelled
     non-core point needs a same-label core within eps; a noise point needs none."""

@@ -7,12 +7,13 @@ include/fdbscan.h); this package marshals torch tensors into that ABI.
 """
 from __future__ import annotations
 
-from ._lib import (FDB_INFO_BAD_PARAMS, FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError,
+from ._lib import (FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS, FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL,
+                   FDB_INFO_NONFINITE, FdbError,
                    Handle, Server, load, make_options, status_string, workspace_bytes, workspace_bytes_batched)
 
 __all__ = ["dbscan", "dbscan_batched", "Handle", "Server", "FdbError", "workspace_bytes", "workspace_bytes_batched",
            "default_handle", "load", "make_options", "status_string", "FDB_INFO_DENSEBOX_FALLBACK",
-           "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL", "FDB_INFO_BAD_PARAMS"]
+           "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL", "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN"]
 
 _handles: dict[int, Handle] = {}
 
@@ -31,7 +32,8 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     """Cluster points ([n, 2] or [n, 3] float32 torch tensor on a HIP device).
 
     Returns (labels int32 [n], is_core bool [n], K). labels are in input order:
-    -1 noise, else a cluster id 0..K-1 (canonical order unless border="first").
+    -1 noise, else a cluster id 0..K-1 (canonical order unless border="first";
+    border="none" is DBSCAN*: every non-core point is noise).
     K is None when want_k is False (then the call does not wait for the GPU).
     """
     import torch

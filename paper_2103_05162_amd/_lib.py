@@ -13,12 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdbscan.so")
 
 FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL = range(6)
-FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX = 0, 1
-FDB_BORDER_CANONICAL, FDB_BORDER_FIRST = 0, 1
+FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX, FDB_ALGO_AUTO = 0, 1, 2
+FDB_BORDER_CANONICAL, FDB_BORDER_FIRST, FDB_BORDER_NONE = 0, 1, 2
 FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FDB_INFO_INTERNAL, FDB_INFO_BAD_PARAMS = 1, 2, 4, 8
+FDB_INFO_AUTO_FDBSCAN = 16
 
-ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX}
-BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST}
+ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX, "auto": FDB_ALGO_AUTO}
+BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST, "none": FDB_BORDER_NONE}
 
 
 class FdbOptions(ctypes.Structure):

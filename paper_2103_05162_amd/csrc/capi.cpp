@@ -50,8 +50,8 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.tilectr = take(64);
   p.status = take(static_cast<size_t>(p.sort_tiles) * 256 * 8);
   p.xs = take(static_cast<size_t>(dim) * N * 4);
-  p.node_a = take(N * 16);
-  p.node_b = take(N * 16);
+  p.node_a = take(N * 32);  // interleaved node records (kNodeStride float4 per node)
+  p.node_b = p.node_a + 16;
   p.rope = take(N * 4);
   p.leaf_rope = take(N * 4);
   p.parent = take(2 * N * 4);
@@ -73,7 +73,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.border = take(N * 4);
   p.cell_id = p.cell_start = p.cand = p.cell_dense = p.cell_lo = p.cell_hi = 0;
   p.pflag = p.prim_start = p.prim_cnt = p.prim_lo = p.prim_hi = p.prim_key = p.dense_list = 0;
-  if (algo == FDB_ALGO_DENSEBOX) {
+  if (algo != FDB_ALGO_FDBSCAN) {  // DenseBox, or the automatic choice (which starts as DenseBox)
     p.cell_id = take(N * 4);
     p.cell_start = take((N + 1) * 4);
     p.cand = take(N * 4);
@@ -209,8 +209,8 @@ fdb_status collect_timing(fdb_handle* h) {
 }
 
 bool valid_options(const fdb_options& o) {
-  if (o.algo != FDB_ALGO_FDBSCAN && o.algo != FDB_ALGO_DENSEBOX) return false;
-  if (o.border != FDB_BORDER_CANONICAL && o.border != FDB_BORDER_FIRST) return false;
+  if (o.algo != FDB_ALGO_FDBSCAN && o.algo != FDB_ALGO_DENSEBOX && o.algo != FDB_ALGO_AUTO) return false;
+  if (o.border != FDB_BORDER_CANONICAL && o.border != FDB_BORDER_FIRST && o.border != FDB_BORDER_NONE) return false;
   if (o.leaf_size < 0 || o.leaf_size > 1024) return false;
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64 != 0)) return false;
   if (o.flags != 0) return false;
@@ -335,8 +335,8 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
   char* p = static_cast<char*>(buf);
   uint64_t* keys = reinterpret_cast<uint64_t*>(p); p += M * 8;
   float* xs = reinterpret_cast<float*>(p); p += 3 * M * 4;
-  float4* na = reinterpret_cast<float4*>(p); p += M * 16;
-  float4* nb = reinterpret_cast<float4*>(p); p += M * 16;
+  float4* na = reinterpret_cast<float4*>(p); p += 2 * M * 16;  // interleaved node records
+  float4* nb = na + 1;
   int* rope = reinterpret_cast<int*>(p); p += M * 4;
   int* lrope = reinterpret_cast<int*>(p); p += M * 4;
   int* parent = reinterpret_cast<int*>(p); p += 2 * M * 4;
@@ -422,7 +422,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   }
   const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
   const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
-  bool densebox = o.algo == FDB_ALGO_DENSEBOX;
+  bool densebox = o.algo != FDB_ALGO_FDBSCAN;
+  const bool auto_algo = o.algo == FDB_ALGO_AUTO;
   const bool first_border = o.border == FDB_BORDER_FIRST;
   const Plan plan = make_plan(n, dim, o.algo);
   void* ws = workspace;
@@ -499,7 +500,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     const int maxbits = dim == 3 ? 21 : 32;
     if (!ok || bits > maxbits) {
       densebox = false;
-      h->host_info |= FDB_INFO_DENSEBOX_FALLBACK;
+      h->host_info |= auto_algo ? FDB_INFO_AUTO_FDBSCAN : FDB_INFO_DENSEBOX_FALLBACK;
     } else {
       gp.bits = bits;
       gp.key64 = bits * dim > 32;
@@ -527,7 +528,6 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.t.leaf_rope = at<int>(ws, plan.leaf_rope);
   ta.t.leaf_size = leaf;
 
-  h->last_densebox = densebox;
   if (densebox) {
     st.mark("cell_keys");
     launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], s);
@@ -545,6 +545,9 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
                    at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key),
                    at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
+  }
+  h->last_densebox = densebox;
+  if (densebox) {
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
@@ -561,6 +564,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     ta.d_ndense = misc + kMiscNumDense;
   } else {
     st.mark("morton");
+    fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
     launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], s);
     st.mark("sort");
     cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, dim == 3 ? 63 : 62, at<uint32_t>(ws, plan.hist),
@@ -607,7 +611,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   st.mark("cluster_ids");
   canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), at<int>(ws, plan.rank),
                 at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s);
-  const bool have_border = !all_core && !first_border;
+  const bool have_border = !all_core && o.border == FDB_BORDER_CANONICAL;  // DBSCAN*: non-core stays noise
   if (have_border) {
     st.mark("border");
     launch_border(ta, dim, densebox, s);
@@ -664,7 +668,7 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   }
   const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
   const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
-  const bool densebox = o.algo == FDB_ALGO_DENSEBOX;
+  const bool densebox = o.algo != FDB_ALGO_FDBSCAN;  // the automatic choice runs DenseBox for a batch
   const bool first_border = o.border == FDB_BORDER_FIRST;
   const Plan plan = make_plan(n_total, dim, o.algo, num_clouds);
   void* ws = workspace;
@@ -811,12 +815,13 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
                 plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false);
   batch_cluster_ids(lab, core, at<int>(ws, plan.minorig), lbits, rank, pkeys, shift, offsets, num_clouds, n,
                     misc + kMiscNumClusters, cl_flags, at<int>(ws, plan.cid), num_clusters, s);
-  if (!first_border) {
+  if (o.border == FDB_BORDER_CANONICAL) {
     st.mark("border");
     launch_border(ta, dim, densebox, s);
   }
   st.mark("scatter");
-  launch_scatter(lab, core, perm, at<int>(ws, plan.cid), at<int>(ws, plan.border), first_border, !first_border, n,
+  launch_scatter(lab, core, perm, at<int>(ws, plan.cid), at<int>(ws, plan.border), first_border,
+                 o.border == FDB_BORDER_CANONICAL, n,
                  labels, is_core, h->d_info, s);
   st.finish();
   return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;

@@ -55,6 +55,11 @@ enum MiscSlot : int {
   kMiscCount = 16
 };
 
+// Node records are interleaved: node k's two halves sit at node_a[kNodeStride * k]
+// and node_b[kNodeStride * k] with node_b = node_a + 1, so a node is 32
+// contiguous bytes (one cache line) rather than two lines in two arrays.
+constexpr int kNodeStride = 2;
+
 // Device view of an LBVH over m primitives. Internal node k: node_a[k] =
 // (lo.xyz, other end of its leaf range as int bits), node_b[k] = (hi.xyz, split
 // position gamma as int bits); its leaves are [min(k,other), max(k,other)], its

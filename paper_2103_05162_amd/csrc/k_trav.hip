@@ -111,8 +111,8 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Scope& 
       return;
     }
     // the escape link is loaded with the node, not after its box test fails
-    const float4 a = t.node_a[node];
-    const float4 b = t.node_b[node];
+    const float4 a = t.node_a[kNodeStride * size_t(node)];
+    const float4 b = t.node_b[kNodeStride * size_t(node)];
     const uint32_t esc = static_cast<uint32_t>(t.rope[node]);
     const int k = static_cast<int>(node);
     const int o = __float_as_int(a.w), g = __float_as_int(b.w);
@@ -173,8 +173,8 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
       atomicOr(info, kInternalBit);
       return;
     }
-    const float4 na = t.node_a[node];
-    const float4 nb = t.node_b[node];
+    const float4 na = t.node_a[kNodeStride * size_t(node)];
+    const float4 nb = t.node_b[kNodeStride * size_t(node)];
     const uint32_t esc = static_cast<uint32_t>(t.rope[node]);
     const int k = static_cast<int>(node);
     const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
@@ -768,8 +768,8 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
     w.node = kEnd;
     return -1;
   }
-  const float4 a = t.node_a[node];
-  const float4 b = t.node_b[node];
+  const float4 a = t.node_a[kNodeStride * size_t(node)];
+  const float4 b = t.node_b[kNodeStride * size_t(node)];
   const uint32_t esc = static_cast<uint32_t>(t.rope[node]);  // loaded with the node
   const int k = static_cast<int>(node);
   const int o = __float_as_int(a.w), g = __float_as_int(b.w);

@@ -128,8 +128,8 @@ __device__ __forceinline__ float lo32(uint64_t v) { return __uint_as_float(stati
 __device__ __forceinline__ float hi32(uint64_t v) { return __uint_as_float(static_cast<uint32_t>(v >> 32)); }
 
 __device__ __forceinline__ void store_node(float4* node_a, float4* node_b, int p, const Box& b, int o, int g) {
-  uint64_t* a = reinterpret_cast<uint64_t*>(node_a + p);
-  uint64_t* c = reinterpret_cast<uint64_t*>(node_b + p);
+  uint64_t* a = reinterpret_cast<uint64_t*>(node_a + kNodeStride * size_t(p));
+  uint64_t* c = reinterpret_cast<uint64_t*>(node_b + kNodeStride * size_t(p));
   st_agent64(a, pack2(b.lo[0], b.lo[1]));
   st_agent64(a + 1, pack2(b.lo[2], __int_as_float(o)));
   st_agent64(c, pack2(b.hi[0], b.hi[1]));
@@ -137,8 +137,8 @@ __device__ __forceinline__ void store_node(float4* node_a, float4* node_b, int p
 }
 
 __device__ __forceinline__ Box load_node(const float4* node_a, const float4* node_b, int k) {
-  const uint64_t* a = reinterpret_cast<const uint64_t*>(node_a + k);
-  const uint64_t* c = reinterpret_cast<const uint64_t*>(node_b + k);
+  const uint64_t* a = reinterpret_cast<const uint64_t*>(node_a + kNodeStride * size_t(k));
+  const uint64_t* c = reinterpret_cast<const uint64_t*>(node_b + kNodeStride * size_t(k));
   uint64_t a0 = ld_agent64(a), a1 = ld_agent64(a + 1), c0 = ld_agent64(c), c1 = ld_agent64(c + 1);
   Box b;
   b.lo[0] = lo32(a0); b.lo[1] = hi32(a0); b.lo[2] = lo32(a1);

@@ -151,3 +151,14 @@ def test_empty_batch(dev):
                                          torch.full((3,), 3, dtype=torch.int32, device=dev))
     torch.cuda.synchronize()
     assert k.cpu().tolist() == [0, 0, 0]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_batch_dbscan_star(dev, algo):
+    clouds, eps, mp = _random_batch(6, 3, 40)
+    offs, labels, core, k, info = _run_batch(dev, clouds, eps, mp, algo, border="none")
+    assert info == 0
+    for c, pts in enumerate(clouds):
+        rl, rc, rk = oracle.dbscan_star(pts, float(eps[c]), int(mp[c]))
+        sl = slice(offs[c], offs[c + 1])
+        assert k[c] == rk and np.array_equal(core[sl], rc) and np.array_equal(labels[sl], rl), c

@@ -296,3 +296,41 @@ def test_many_dense_cells(dev, border):
         lab, core, kk = run_gpu(dev, pts, eps, mp, "densebox", border="first")
         assert kk == ref[2]
         assert_tolerance_mode(pts, eps, lab, core, ref[0], ref[1], oracle.check_border)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("d,mp", [(2, 5), (3, 10), (3, 2), (2, 1)])
+def test_dbscan_star(dev, algo, d, mp):
+    """DBSCAN* (border="none"): canonical clusters, every non-core point noise."""
+    pts = _mixture(60 + d + mp, 30011, d, 10, 0.02)
+    eps = 0.01 if d == 2 else 0.02
+    rl, rc, rk = oracle.dbscan_star(pts, eps, mp)
+    lab, core, k = run_gpu(dev, pts, eps, mp, algo, border="none")
+    assert k == rk and np.array_equal(core, rc) and np.array_equal(lab, rl)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_c1_dbscan_star(dev, algo):
+    w = workload("c1_blobs2d_16k")
+    rl, rc, rk = oracle.dbscan_star(w.points, w.eps, w.min_pts)
+    lab, core, k = run_gpu(dev, w.points, w.eps, w.min_pts, algo, border="none")
+    assert k == rk and np.array_equal(core, rc) and np.array_equal(lab, rl)
+
+
+def test_automatic_choice(dev):
+    """FDB_ALGO_AUTO runs DenseBox, and FDbscan when the grid cannot be keyed;
+    labels exact either way."""
+    import paper_2103_05162_amd as fdb
+    h = fdb.default_handle(0)
+    w = workload("c3_dense3d_8m", 1 / 64)
+    assert_exact(dev, w.points, w.eps, w.min_pts, "auto")
+    assert not h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+    rng = np.random.default_rng(5)
+    sparse = rng.uniform(0, 1, size=(60000, 3)).astype(np.float32)
+    assert_exact(dev, sparse, 0.02, 5, "auto")
+    assert not h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+    # eps tiny against the extent: no 64-bit grid key, so FDbscan runs
+    wide = sparse.copy()
+    wide[0] = (1e7, 1e7, 1e7)
+    assert_exact(dev, wide, 1e-3, 3, "auto")
+    assert h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN

@@ -73,6 +73,24 @@ def test_two_lines_noise_and_border():
     assert counts.tolist() == [3, 4, 5, 4, 4, 3, 3, 3, 1, 2]
 
 
+def test_dbscan_star_drops_border_points():
+    # DBSCAN* (Section 2.1): same sets as test_two_lines_noise_and_border, but the
+    # border point (3,0) is noise, like (5,5); clusters and ids are unchanged.
+    A = [(0, 0), (0.5, 0), (1, 0), (1.5, 0), (2, 0)]
+    B = [(10, 0), (10.5, 0), (11, 0)]
+    pts = np.array(A + B + [(5, 5), (3, 0)], dtype=np.float32)
+    labels, core, k = oracle.dbscan_star(pts, 1.0, 3, "brute")
+    assert k == 2
+    assert labels.tolist() == [0] * 5 + [1] * 3 + [-1, -1]
+    # the bridging configuration: b, (5.75,0) and (0,0) are border points, all noise
+    B2 = [(3.75, 0), (4.25, 0), (4.75, 0), (5.25, 0), (5.75, 0)]
+    A2 = [(0, 0), (0.5, 0), (1, 0), (1.5, 0), (2, 0)]
+    pts = np.array(B2 + A2 + [(2.875, 0)], dtype=np.float32)
+    labels, core, k = oracle.dbscan_star(pts, 1.0, 4, "brute")
+    assert k == 2
+    assert labels.tolist() == [0, 0, 0, 0, -1, -1, 1, 1, 1, 1, -1]
+
+
 def test_bridging_border_point_does_not_merge_clusters():
     # eps=1, minPts=4 (Section 3.2's bridging hazard); all coordinates dyadic, so
     # every distance is exact. b=(2.875,0) is within eps of core (2,0) of cluster A
