@@ -530,10 +530,11 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
 
   if (densebox) {
     st.mark("cell_keys");
-    launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], s);
+    launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], gp.bits * dim,
+                    at<uint32_t>(ws, plan.hist), s);
     st.mark("sort");
     cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, gp.key64, gp.bits * dim, at<uint32_t>(ws, plan.hist),
-                     at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
+                     true, at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
     perm = vals[cur];
     st.mark("permute");
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
@@ -565,9 +566,11 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   } else {
     st.mark("morton");
     fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
-    launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], s);
+    const int mbits = dim == 3 ? 63 : 62;
+    launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], mbits,
+                  at<uint32_t>(ws, plan.hist), s);
     st.mark("sort");
-    cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, dim == 3 ? 63 : 62, at<uint32_t>(ws, plan.hist),
+    cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, mbits, at<uint32_t>(ws, plan.hist), true,
                      at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
     perm = vals[cur];
     st.mark("permute");
@@ -716,9 +719,9 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
              cl_flags, h->d_info, s);
   st.mark("keys");
   batch_keys(points, offsets, num_clouds, n, dim, cl_lo, cl_scale, bpd, shift, static_cast<uint64_t*>(keys[0]),
-             vals[0], s);
+             vals[0], shift + cb, at<uint32_t>(ws, plan.hist), s);
   st.mark("sort");
-  const int cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, shift + cb, at<uint32_t>(ws, plan.hist),
+  const int cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, true, shift + cb, at<uint32_t>(ws, plan.hist), true,
                              at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr),
                              at<uint64_t>(ws, plan.status), h->d_info, s);
   const uint32_t* perm = vals[cur];

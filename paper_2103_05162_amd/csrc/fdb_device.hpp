@@ -217,4 +217,53 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// ---- radix-sort digit histograms ---------------------------------------------
+// Lanes of the wavefront whose 8-bit digit d equals this lane's, among lanes
+// with `valid`.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t m = ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    bool bit = (d >> b) & 1u;
+    uint64_t bb = ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// Count the 8-bit digits of `key` (passes from the least significant) into the
+// workgroup's histograms s_h[p * 256 + digit]. A digit shared by every counted
+// lane (typical of a key's high digits) costs one LDS atomic; otherwise each
+// lane adds its own (same-address lanes serialise in LDS). Lanes outside the
+// wavefront's active set do not count.
+template <typename K>
+__device__ __forceinline__ void hist_add(K key, bool valid, int passes, uint32_t* s_h) {
+  const uint64_t vm = ballot(valid);
+  if (!vm) return;
+  const int first = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t d = static_cast<uint32_t>(key >> (8 * p)) & 0xffu;
+    const uint32_t d0 = static_cast<uint32_t>(__shfl(static_cast<int>(d), first));
+    if (!ballot(valid && d != d0)) {
+      if (lane_id() == first) atomicAdd(s_h + p * 256 + d0, static_cast<uint32_t>(__popcll(vm)));
+    } else if (valid) {
+      atomicAdd(s_h + p * 256 + d, 1u);
+    }
+  }
+}
+
+// Workgroup histogram lifecycle around hist_add: clear, then add to the global
+// counts (only non-zero bins). Every thread of the workgroup must call both.
+__device__ __forceinline__ void hist_clear(uint32_t* s_h, int passes) {
+  for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) s_h[i] = 0;
+  __syncthreads();
+}
+__device__ __forceinline__ void hist_flush(const uint32_t* s_h, int passes, uint32_t* hist) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) {
+    const uint32_t v = s_h[i];
+    if (v) atomicAdd(hist + i, v);
+  }
+}
+
 }  // namespace fdb

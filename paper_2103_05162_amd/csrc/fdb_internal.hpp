@@ -81,18 +81,22 @@ void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 
 // k_prep.hip
 void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint32_t* info, hipStream_t s);
+// The key kernels also count the digits of the `sort_bits`-bit keys for the
+// radix sort into hist (ceil(sort_bits / 8) x 256 words, cleared here).
 void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds, uint64_t* keys, uint32_t* vals,
-                   hipStream_t s);
+                   int sort_bits, uint32_t* hist, hipStream_t s);
 void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const float* inv_h3,
-                     const uint32_t* ncell3, int bits, bool key64, void* keys, uint32_t* vals, hipStream_t s);
+                     const uint32_t* ncell3, int bits, bool key64, void* keys, uint32_t* vals, int sort_bits,
+                     uint32_t* hist, hipStream_t s);
 void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,
                     hipStream_t s);
 
 // k_sort.hip: LSD radix sort of (key, index) pairs over the low `bits` bits.
-// Returns which of the two buffers holds the result (0 or 1).
+// hist_ready: hist already holds the digit counts of every pass (from the key
+// kernel). Returns which of the two buffers holds the result (0 or 1).
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
-               uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info,
-               hipStream_t s);
+               uint32_t* hist, bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
+               uint32_t* info, hipStream_t s);
 
 // k_tree.hip
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
@@ -185,7 +189,8 @@ void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n,
                 const int32_t* min_pts, int bpd, bool densebox, float4* cl_lo, float4* cl_scale, float* cl_eps2,
                 int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s);
 void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
-                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, hipStream_t s);
+                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, int sort_bits,
+                uint32_t* hist, hipStream_t s);
 void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,
                  int* root, int* end, uint32_t* info, hipStream_t s);
 void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minorig, const uint32_t* bits,

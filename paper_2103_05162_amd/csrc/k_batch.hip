@@ -132,7 +132,10 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_batch_keys(const float* __restrict__ pts, const int64_t* __restrict__ off,
                                                        int64_t n, const float4* __restrict__ cl_lo,
                                                        const float4* __restrict__ cl_scale, int bpd, int shift,
-                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                       int passes, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[8 * 256];
+  hist_clear(s_h, passes);
   const int c = blockIdx.x;
   int64_t b, e;
   cloud_range(off, c, n, b, e);
@@ -151,7 +154,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_keys(const float* __restrict__
       code = (spread2(q[0]) << 1) | spread2(q[1]);
     keys[i] = prefix | code;
     vals[i] = static_cast<uint32_t>(i);
+    hist_add(prefix | code, true, passes, s_h);
   }
+  hist_flush(s_h, passes, hist);
 }
 
 // Subtree of each cloud: its primitive range [a, b] and the node covering it.
@@ -252,13 +257,16 @@ void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n,
 }
 
 void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
-                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+                const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, int sort_bits,
+                uint32_t* hist, hipStream_t s) {
+  const int passes = (sort_bits + 7) / 8;
+  fill_u32(hist, 0, passes * 256, s);
   if (dim == 3)
     hipLaunchKernelGGL(k_batch_keys<3>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
-                       shift, keys, vals);
+                       shift, keys, vals, passes, hist);
   else
     hipLaunchKernelGGL(k_batch_keys<2>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
-                       shift, keys, vals);
+                       shift, keys, vals, passes, hist);
 }
 
 void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,

@@ -177,7 +177,10 @@ __device__ __forceinline__ uint32_t quantize(float v, float lo, float scale, uin
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_morton(const float* __restrict__ pts, int64_t n,
                                                    const uint32_t* __restrict__ bounds, uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals) {
+                                                   uint32_t* __restrict__ vals, int passes,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[8 * 256];
+  hist_clear(s_h, passes);
   constexpr uint32_t maxq = D == 3 ? 0x1fffffu : 0x7fffffffu;
   float lo[D], scale[D];
 #pragma unroll
@@ -198,7 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float* __restrict__ pts
     }
     keys[i] = code;
     vals[i] = static_cast<uint32_t>(i);
+    hist_add(code, true, passes, s_h);
   }
+  hist_flush(s_h, passes, hist);
 }
 
 // DenseBox grid (Section 4.2): cell c_k = floor((x_k - lo_k) / h), h = eps/sqrt(d)
@@ -209,7 +214,10 @@ template <int D, typename K>
 __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ pts, int64_t n,
                                                      const uint32_t* __restrict__ bounds, float ihx, float ihy,
                                                      float ihz, uint32_t ncx, uint32_t ncy, uint32_t ncz,
-                                                     K* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                     K* __restrict__ keys, uint32_t* __restrict__ vals, int passes,
+                                                     uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[8 * 256];
+  hist_clear(s_h, passes);
   const float ih[3] = {ihx, ihy, ihz};
   const uint32_t nc[3] = {ncx, ncy, ncz};
   float lo[D];
@@ -226,7 +234,9 @@ __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ p
       code = (spread2(c[0]) << 1) | spread2(c[1]);
     keys[i] = static_cast<K>(code);
     vals[i] = static_cast<uint32_t>(i);
+    hist_add(static_cast<K>(code), true, passes, s_h);
   }
+  hist_flush(s_h, passes, hist);
 }
 
 // Gather points into Morton order, structure-of-arrays.
@@ -277,32 +287,37 @@ void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint3
 }
 
 void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds, uint64_t* keys, uint32_t* vals,
-                   hipStream_t s) {
-  int g = grid_for(n, kBlock * 4);
+                   int sort_bits, uint32_t* hist, hipStream_t s) {
+  const int passes = (sort_bits + 7) / 8;
+  fill_u32(hist, 0, passes * 256, s);
+  int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
   if (dim == 3)
-    hipLaunchKernelGGL(k_morton<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals);
+    hipLaunchKernelGGL(k_morton<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals, passes, hist);
   else
-    hipLaunchKernelGGL(k_morton<2>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals);
+    hipLaunchKernelGGL(k_morton<2>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals, passes, hist);
 }
 
 void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const float* ih,
-                     const uint32_t* nc, int bits, bool key64, void* keys, uint32_t* vals, hipStream_t s) {
+                     const uint32_t* nc, int bits, bool key64, void* keys, uint32_t* vals, int sort_bits,
+                     uint32_t* hist, hipStream_t s) {
   (void)bits;
-  int g = grid_for(n, kBlock * 4);
+  const int passes = (sort_bits + 7) / 8;
+  fill_u32(hist, 0, passes * 256, s);
+  int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
   if (dim == 3) {
     if (key64)
       hipLaunchKernelGGL((k_gridkeys<3, uint64_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         ih[2], nc[0], nc[1], nc[2], static_cast<uint64_t*>(keys), vals);
+                         ih[2], nc[0], nc[1], nc[2], static_cast<uint64_t*>(keys), vals, passes, hist);
     else
       hipLaunchKernelGGL((k_gridkeys<3, uint32_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         ih[2], nc[0], nc[1], nc[2], static_cast<uint32_t*>(keys), vals);
+                         ih[2], nc[0], nc[1], nc[2], static_cast<uint32_t*>(keys), vals, passes, hist);
   } else {
     if (key64)
       hipLaunchKernelGGL((k_gridkeys<2, uint64_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         0.0f, nc[0], nc[1], 1u, static_cast<uint64_t*>(keys), vals);
+                         0.0f, nc[0], nc[1], 1u, static_cast<uint64_t*>(keys), vals, passes, hist);
     else
       hipLaunchKernelGGL((k_gridkeys<2, uint32_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         0.0f, nc[0], nc[1], 1u, static_cast<uint32_t*>(keys), vals);
+                         0.0f, nc[0], nc[1], 1u, static_cast<uint32_t*>(keys), vals, passes, hist);
   }
 }
 

@@ -34,44 +34,21 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift) {
   return static_cast<uint32_t>(key >> shift) & 0xffu;
 }
 
-// Lanes of the wavefront whose `d` equals this lane's, among lanes with `valid`.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
-  uint64_t m = ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    bool bit = (d >> b) & 1u;
-    uint64_t bb = ballot(bit);
-    m &= bit ? bb : ~bb;
-  }
-  return m;
-}
-
 // Histogram of every pass's digit over all keys.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, int64_t n, int passes,
                                                  uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_h[8][kRadix];
-  for (int i = threadIdx.x; i < 8 * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
-  __syncthreads();
+  __shared__ uint32_t s_h[8 * kRadix];
+  hist_clear(s_h, passes);
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   // every lane of a wavefront runs the same trip count so ballots see all lanes
   const int64_t base0 = blockIdx.x * int64_t(kBlock) + (threadIdx.x & ~63);
   for (int64_t base = base0; base < n; base += stride) {
     int64_t i = base + (threadIdx.x & 63);
     bool valid = i < n;
-    K key = valid ? keys[i] : K(0);
-    for (int p = 0; p < passes; ++p) {
-      uint32_t d = digit_of(key, 8 * p);
-      uint64_t m = match_digit(d, valid);
-      if (valid && lane_id() == __ffsll(static_cast<unsigned long long>(m)) - 1)
-        atomicAdd(&s_h[p][d], static_cast<uint32_t>(__popcll(m)));
-    }
+    hist_add(valid ? keys[i] : K(0), valid, passes, s_h);
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < passes * kRadix; i += kBlock) {
-    uint32_t v = (&s_h[0][0])[i];
-    if (v) atomicAdd(hist + i, v);
-  }
+  hist_flush(s_h, passes, hist);
 }
 
 // Exclusive scan of each pass's 256 digit counts -> global digit offsets.
@@ -225,16 +202,19 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K* __restrict__ kin, 
 
 template <typename K>
 int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, int bits, uint32_t* hist,
-                 uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info, hipStream_t s) {
+                 bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info,
+                 hipStream_t s) {
   const int passes = (bits + 7) / 8;
   if (n <= 1 || passes == 0) return 0;
   const int64_t tiles = ceil_div(n, kSortTile);
-  fill_u32(hist, 0, passes * kRadix, s);
   fill_u32(tilectr, 0, passes, s);
   fill_u32(reinterpret_cast<uint32_t*>(status), 0, tiles * kRadix * 2, s);
-  int hg = static_cast<int>(ceil_div(n, kBlock * 16));
-  if (hg > 2048) hg = 2048;
-  hipLaunchKernelGGL(k_hist<K>, dim3(hg), dim3(kBlock), 0, s, keys0, n, passes, hist);
+  if (!hist_ready) {
+    fill_u32(hist, 0, passes * kRadix, s);
+    int hg = static_cast<int>(ceil_div(n, kBlock * 16));
+    if (hg > 2048) hg = 2048;
+    hipLaunchKernelGGL(k_hist<K>, dim3(hg), dim3(kBlock), 0, s, keys0, n, passes, hist);
+  }
   hipLaunchKernelGGL(k_digit_offsets, dim3(passes), dim3(kRadix), 0, s, hist, digoff);
   K* kb[2] = {keys0, keys1};
   uint32_t* vb[2] = {vals0, vals1};
@@ -251,13 +231,13 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
 }  // namespace
 
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
-               uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status, uint32_t* info,
-               hipStream_t s) {
+               uint32_t* hist, bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
+               uint32_t* info, hipStream_t s) {
   if (key64)
     return radix_sort_t(static_cast<uint64_t*>(keys0), static_cast<uint64_t*>(keys1), vals0, vals1, n, bits, hist,
-                        digoff, tilectr, status, info, s);
+                        hist_ready, digoff, tilectr, status, info, s);
   return radix_sort_t(static_cast<uint32_t*>(keys0), static_cast<uint32_t*>(keys1), vals0, vals1, n, bits, hist,
-                      digoff, tilectr, status, info, s);
+                      hist_ready, digoff, tilectr, status, info, s);
 }
 
 }  // namespace fdb

@@ -796,55 +796,81 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   return -1;
 }
 
-// Core pass for points outside dense cells (one lane per point primitive).
+// Core pass for points outside dense cells. Each lane walks for kCoreQ
+// neighbouring point primitives (kCoreQ k + t for lane k of the index space).
+// Two walks per lane keep more node loads in flight, but a wavefront then waits
+// for the longest of 128 walks and the 8M-point set fills fewer wavefronts than
+// the chip has slots: measured slower (0.55 vs 0.47 ms), so one.
+constexpr int kCoreQ = 1;
+
 template <int D, bool B>
 __global__ void k_core_dbx(TravArgs a) {
   __shared__ int s_w[17];
-  extern __shared__ int s_rec[];  // kRecNb * blockDim.x
+  extern __shared__ int s_rec[];  // kCoreQ tables of kRecNb * blockDim.x
   const int m = tree_m(a.t);
   const int lane = lane_id();
-  const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
-  const bool mine = p >= 0 && p < m && a.prim_cnt[p] > 0;  // dense cells are core by construction
-  const int i = mine ? a.prim_start[p] : 0;
-  const Scope sc = scope_of<B>(a, m, i);
-  const Query q = load_point<D>(a.xs, a.n, i);
-  int cnt = 0;
-  NbRec rec;
-  rec_init(rec, s_rec);
-  Walk w;
-  walk_init<false>(w, m, sc, 0, mine);
-  bool active = mine && !walk_done(w);
-  while (ballot(active)) {
-    int pend = -1;
-    if (active) {
-      const int r = walk_step<D, false>(w, a.t, m, q, sc.eps2, 0, a.info);
-      if (r >= 0) {
-        const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) {
-          if (near<D>(a.xs, a.n, s, q, sc.eps2)) {
-            ++cnt;
-            if (s != i) rec_add(rec, s);
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, (m + kCoreQ - 1) / kCoreQ);
+  int p[kCoreQ], i[kCoreQ], cnt[kCoreQ];
+  bool mine[kCoreQ], active[kCoreQ];
+  Scope sc[kCoreQ];
+  Query q[kCoreQ];
+  NbRec rec[kCoreQ];
+  Walk w[kCoreQ];
+#pragma unroll
+  for (int t = 0; t < kCoreQ; ++t) {
+    p[t] = k >= 0 ? static_cast<int>(k * kCoreQ + t) : -1;
+    mine[t] = p[t] >= 0 && p[t] < m && a.prim_cnt[p[t]] > 0;  // dense cells are core by construction
+    i[t] = mine[t] ? a.prim_start[p[t]] : 0;
+    sc[t] = scope_of<B>(a, m, i[t]);
+    q[t] = load_point<D>(a.xs, a.n, i[t]);
+    cnt[t] = 0;
+    rec_init(rec[t], s_rec + t * kRecNb * blockDim.x);
+    walk_init<false>(w[t], m, sc[t], 0, mine[t]);
+    active[t] = mine[t] && !walk_done(w[t]);
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < kCoreQ; ++t) any |= active[t];
+    if (!ballot(any)) break;
+    int pend[kCoreQ];
+#pragma unroll
+    for (int t = 0; t < kCoreQ; ++t) {
+      pend[t] = -1;
+      if (active[t]) {
+        const int r = walk_step<D, false>(w[t], a.t, m, q[t], sc[t].eps2, 0, a.info);
+        if (r >= 0) {
+          const int c = a.prim_cnt[r], s = a.prim_start[r];
+          if (c > 0) {
+            if (near<D>(a.xs, a.n, s, q[t], sc[t].eps2)) {
+              ++cnt[t];
+              if (s != i[t]) rec_add(rec[t], s);
+            }
+          } else if (box_near<D>(a, r, q[t], sc[t].eps2)) {
+            pend[t] = r;
           }
-        } else if (box_near<D>(a, r, q, sc.eps2)) {
-          pend = r;
         }
       }
     }
-    for (uint64_t pm = ballot(pend >= 0); pm; pm &= pm - 1) {
-      const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
-      const int r = __shfl(pend, L);
-      const int want = __shfl(sc.min_pts - cnt, L);
-      const int s = a.prim_start[r];
-      const int found = cell_count_near<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q.x, L), __shfl(q.y, L),
-                                           __shfl(q.z, L), readlane_f(sc.eps2, L), want);
-      if (lane == L && found > 0) {
-        cnt += found;
-        rec_add(rec, cell_ref(s));  // a dense cell: all core, one cluster; its first point stands for it
+#pragma unroll
+    for (int t = 0; t < kCoreQ; ++t) {
+      for (uint64_t pm = ballot(pend[t] >= 0); pm; pm &= pm - 1) {
+        const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
+        const int r = __shfl(pend[t], L);
+        const int want = __shfl(sc[t].min_pts - cnt[t], L);
+        const int s = a.prim_start[r];
+        const int found = cell_count_near<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q[t].x, L), __shfl(q[t].y, L),
+                                             __shfl(q[t].z, L), readlane_f(sc[t].eps2, L), want);
+        if (lane == L && found > 0) {
+          cnt[t] += found;
+          rec_add(rec[t], cell_ref(s));  // a dense cell: all core, one cluster; its first point stands for it
+        }
       }
+      if (active[t] && (cnt[t] >= sc[t].min_pts || walk_done(w[t]))) active[t] = false;
     }
-    if (active && (cnt >= sc.min_pts || walk_done(w))) active = false;
   }
-  core_epilogue(a, mine, i, p, cnt, sc.min_pts, rec, s_w);
+#pragma unroll
+  for (int t = 0; t < kCoreQ; ++t) core_epilogue(a, mine[t], i[t], p[t], cnt[t], sc[t].min_pts, rec[t], s_w);
 }
 
 // Main phase, points outside dense cells: pairs with primitives above their own.
@@ -1128,8 +1154,10 @@ template <int D, bool B>
 void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
   const size_t lds = sizeof(int) * kRecNb * a.block;  // neighbour records
-  if (densebox) hipLaunchKernelGGL((k_core_dbx<D, B>), g, b, lds, s, a);
-  else hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, lds, s, a);
+  if (densebox)
+    hipLaunchKernelGGL((k_core_dbx<D, B>), grid_of(ceil_div(a.n, kCoreQ), a.block), b, kCoreQ * lds, s, a);
+  else
+    hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, lds, s, a);
 }
 
 // part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
