@@ -147,9 +147,9 @@ __device__ __forceinline__ void traverse(const TreeView& t, int m, const Scope& 
 // every lane, for each bucket (a subtree of at most leaf_size primitives, cut
 // to primitives above the mask) and each single leaf the walk reaches.
 template <int D, typename F>
-__device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Scope& sc, const float* lo,
+__device__ __forceinline__ bool traverse_box(const TreeView& t, int m, const Scope& sc, const float* lo,
                                              const float* hi, int mask, int leaf_size, uint32_t* info, F&& visit) {
-  if (m <= 0 || mask >= sc.end) return;
+  if (m <= 0 || mask >= sc.end) return false;
   uint32_t node = sc.start;
   int64_t steps = 0;
   const int64_t max_steps = 2 * int64_t(m) + 2;
@@ -157,21 +157,22 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
     node = __builtin_amdgcn_readfirstlane(node);
     if (++steps > max_steps) {
       atomicOr(info, kInternalBit);
-      return;
+      return false;
     }
     if (node & kLeaf) {
       int l = static_cast<int>(node & ~kLeaf);
       if (l >= m) {
         atomicOr(info, kInternalBit);
-        return;
+        return false;
       }
-      if (visit(l, l) || l >= sc.end) return;
+      if (visit(l, l)) return true;
+      if (l >= sc.end) return false;
       node = static_cast<uint32_t>(t.leaf_rope[l]);
       continue;
     }
     if (node >= static_cast<uint32_t>(m - 1)) {
       atomicOr(info, kInternalBit);
-      return;
+      return false;
     }
     const float4 na = t.node_a[kNodeStride * size_t(node)];
     const float4 nb = t.node_b[kNodeStride * size_t(node)];
@@ -180,18 +181,18 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
     const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
     const int first = o < k ? o : k, last = o > k ? o : k;
     if (boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) > sc.eps2) {
-      if (last >= sc.end) return;
+      if (last >= sc.end) return false;
       node = esc;
       continue;
     }
     if (first < 0 || last >= m || g < first || g >= last) {
       atomicOr(info, kInternalBit);
-      return;
+      return false;
     }
     if (last - first < leaf_size) {
       int s = first <= mask ? mask + 1 : first;
-      if (s <= last && visit(s, last)) return;
-      if (last >= sc.end) return;
+      if (s <= last && visit(s, last)) return true;
+      if (last >= sc.end) return false;
       node = esc;
       continue;
     }
@@ -199,6 +200,94 @@ __device__ __forceinline__ void traverse_box(const TreeView& t, int m, const Sco
       node = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
     else
       node = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+  }
+  return false;
+}
+
+// Wavefront-cooperative form of traverse_box: the wavefront expands up to 64
+// tree nodes per step (one per lane) from its own stack in LDS, newest first,
+// so a walk takes about as many steps as the tree is deep instead of one step
+// per node. It visits the same buckets and leaves as traverse_box (in another
+// order: callers only union, which does not depend on it). Children that do not
+// fit on the stack have their subtrees walked with traverse_box instead.
+constexpr int kWideStack = 512;  // entries per wavefront
+
+template <int D, typename F>
+__device__ __forceinline__ void traverse_box_wide(const TreeView& t, int m, const Scope& sc, const float* lo,
+                                                  const float* hi, int mask, int leaf_size, uint32_t* info,
+                                                  uint32_t* stack, F&& visit) {
+  if (m <= 0 || mask >= sc.end) return;
+  const int lane = lane_id();
+  if (lane == 0) stack[0] = sc.start;
+  int top = 1;
+  int64_t guard = 0;
+  const int64_t max_rounds = 2 * int64_t(m) + 2;
+  while (top > 0) {
+    if (++guard > max_rounds) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    const int take = top < 64 ? top : 64;
+    top -= take;
+    const uint32_t node = lane < take ? stack[top + lane] : kEnd;
+    int bs = -1, be = -1;
+    uint32_t c0 = kEnd, c1 = kEnd;
+    if (node != kEnd) {
+      if (node & kLeaf) {
+        const int l = static_cast<int>(node & ~kLeaf);
+        if (l >= m) atomicOr(info, kInternalBit);
+        else if (l > mask) bs = be = l;
+      } else if (node >= static_cast<uint32_t>(m - 1)) {
+        atomicOr(info, kInternalBit);
+      } else {
+        const float4 na = t.node_a[kNodeStride * size_t(node)];
+        const float4 nb = t.node_b[kNodeStride * size_t(node)];
+        const int k = static_cast<int>(node);
+        const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
+        const int first = o < k ? o : k, last = o > k ? o : k;
+        if (last > mask && boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) <= sc.eps2) {
+          if (first < 0 || last >= m || g < first || g >= last) {
+            atomicOr(info, kInternalBit);
+          } else if (last - first < leaf_size) {
+            bs = first <= mask ? mask + 1 : first;
+            be = last;
+          } else {
+            if (g > mask) c0 = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+            c1 = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+          }
+        }
+      }
+    }
+    for (uint64_t vm = ballot(bs >= 0); vm; vm &= vm - 1) {
+      const int L = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+      if (visit(__shfl(bs, L), __shfl(be, L))) return;
+    }
+    const uint64_t m0 = ballot(c0 != kEnd), m1 = ballot(c1 != kEnd);
+    const int n0 = __popcll(m0), n1 = __popcll(m1);
+    if (top + n0 + n1 <= kWideStack) {
+      const uint64_t lt = lanemask_lt();
+      if (c0 != kEnd) stack[top + __popcll(m0 & lt)] = c0;
+      if (c1 != kEnd) stack[top + n0 + __popcll(m1 & lt)] = c1;
+      top += n0 + n1;
+    } else {
+      // stack full: walk each child's subtree on its own
+      for (uint64_t cm = m0 | m1; cm; cm &= cm - 1) {
+        const int L = __ffsll(static_cast<unsigned long long>(cm)) - 1;
+        for (int side = 0; side < 2; ++side) {
+          const uint32_t c = static_cast<uint32_t>(__shfl(static_cast<int>(side ? c1 : c0), L));
+          if (c == kEnd) continue;
+          int end;
+          if (c & kLeaf) {
+            end = static_cast<int>(c & ~kLeaf);
+          } else {
+            const int oc = __float_as_int(t.node_a[kNodeStride * size_t(c)].w);
+            end = oc > static_cast<int>(c) ? oc : static_cast<int>(c);
+          }
+          const Scope sub{c, end, sc.eps2, sc.min_pts};
+          if (traverse_box<D>(t, m, sub, lo, hi, mask, leaf_size, info, visit)) return;
+        }
+      }
+    }
   }
 }
 
@@ -425,6 +514,7 @@ __global__ void k_main_fdb_first(TravArgs a) {
 // a candidate within eps of any query costs one union for the whole packet.
 template <int D, bool ALL_CORE, bool B, int Q>
 __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
+  __shared__ uint32_t s_stack[4 * kWideStack];  // packet walks (256-thread workgroups)
   const int lane = lane_id();
   const int64_t bbase = xcd_spread(blockIdx.x, 256 * Q, 0, a.n);
   if (bbase < 0) return;
@@ -525,7 +615,8 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   const bool common = !ballot(differ);
   const int p1 = static_cast<int>(base) + 64 * Q - 1;
 
-  traverse_box<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, [&](int s0, int e0) {
+  uint32_t* stack = s_stack + (threadIdx.x >> 6) * kWideStack;
+  traverse_box_wide<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, stack, [&](int s0, int e0) {
     const int cnt = e0 - s0 + 1;  // <= packet_leaf <= 64
     float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     int cc = 0, cl = 0;
@@ -809,6 +900,10 @@ __global__ void k_core_dbx(TravArgs a) {
   extern __shared__ int s_rec[];  // kCoreQ tables of kRecNb * blockDim.x
   const int m = tree_m(a.t);
   const int lane = lane_id();
+  // the grid is sized for n queries; a workgroup past the m primitives leaves
+  // at once (uniformly, before any barrier)
+  const int64_t k0 = xcd_spread(blockIdx.x, blockDim.x, 0, (m + kCoreQ - 1) / kCoreQ);
+  if (k0 < 0 || k0 * kCoreQ >= m) return;
   const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, (m + kCoreQ - 1) / kCoreQ);
   int p[kCoreQ], i[kCoreQ], cnt[kCoreQ];
   bool mine[kCoreQ], active[kCoreQ];
@@ -881,6 +976,8 @@ template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_points(TravArgs a) {
   const int m = tree_m(a.t);
   const int lane = lane_id();
+  const int64_t p0 = xcd_spread(blockIdx.x, blockDim.x, 0, m);
+  if (p0 < 0 || p0 >= m) return;  // the grid is sized for n; past the primitives
   const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
   const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
   const int i = pt ? a.prim_start[p] : 0;
@@ -947,7 +1044,9 @@ __global__ void k_main_dbx_points(TravArgs a) {
 constexpr int kCellsPerWaveMax = 65536;
 
 template <int D, bool ALL_CORE, bool FIRST, bool B>
-__global__ void k_main_dbx_cells_wave(TravArgs a) {
+__global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
+  __shared__ uint32_t s_stack[4 * kWideStack];  // 256-thread workgroups
+  uint32_t* stack = s_stack + (threadIdx.x >> 6) * kWideStack;
   const int nd = *a.d_ndense;
   if (nd > kCellsPerWaveMax) return;
   const int m = tree_m(a.t);
@@ -967,7 +1066,7 @@ __global__ void k_main_dbx_cells_wave(TravArgs a) {
     const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
     const float alo[3] = {alo4.x, alo4.y, alo4.z}, ahi[3] = {ahi4.x, ahi4.y, ahi4.z};
     int root = sa;
-    traverse_box<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, [&](int r0, int r1) {
+    traverse_box_wide<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, stack, [&](int r0, int r1) {
       for (int r = r0; r <= r1; ++r) {
         const int c = a.prim_cnt[r], s = a.prim_start[r];
         if (c > 0) {
