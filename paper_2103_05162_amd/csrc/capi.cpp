@@ -88,7 +88,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
     p.prim_key = take(N * 8);
     p.dense_list = take(N * 4);
   }
-  p.cl_lo = p.cl_scale = p.cl_eps2 = p.cl_minpts = p.cl_root = p.cl_end = p.cl_flags = 0;
+  p.cl_lo = p.cl_scale = p.cl_eps2 = p.cl_minpts = p.cl_root = p.cl_end = p.cl_flags = p.cl_ord = 0;
   if (num_clouds > 0) {
     const size_t B = static_cast<size_t>(num_clouds);
     p.cl_lo = take(B * 16);
@@ -98,6 +98,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
     p.cl_root = take(B * 4);
     p.cl_end = take(B * 4);
     p.cl_flags = take(B * 4);
+    p.cl_ord = take(B * 32);
   }
   p.bytes = off;
   return p;
@@ -715,8 +716,8 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   fill_u32(h->d_info, 0, 1, s);
   fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
   int* cl_flags = at<int>(ws, plan.cl_flags);
-  batch_prep(points, offsets, num_clouds, n, dim, eps, min_pts, bpd, densebox, cl_lo, cl_scale, cl_eps2, cl_minpts,
-             cl_flags, h->d_info, s);
+  batch_prep(points, offsets, num_clouds, n, dim, eps, min_pts, bpd, densebox, at<uint32_t>(ws, plan.cl_ord), cl_lo,
+             cl_scale, cl_eps2, cl_minpts, cl_flags, h->d_info, s);
   st.mark("keys");
   batch_keys(points, offsets, num_clouds, n, dim, cl_lo, cl_scale, bpd, shift, static_cast<uint64_t*>(keys[0]),
              vals[0], shift + cb, at<uint32_t>(ws, plan.hist), s);

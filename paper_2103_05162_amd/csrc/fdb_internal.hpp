@@ -37,7 +37,7 @@ struct Plan {
       prim_lo, prim_hi, prim_key, dense_list;
   // batches
   int num_clouds = 0;
-  size_t cl_lo, cl_scale, cl_eps2, cl_minpts, cl_root, cl_end, cl_flags;
+  size_t cl_lo, cl_scale, cl_eps2, cl_minpts, cl_root, cl_end, cl_flags, cl_ord;
   int64_t sort_tiles = 0, scan_blocks = 0;
 };
 
@@ -186,8 +186,8 @@ void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm,
 
 // k_batch.hip
 void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float* eps,
-                const int32_t* min_pts, int bpd, bool densebox, float4* cl_lo, float4* cl_scale, float* cl_eps2,
-                int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s);
+                const int32_t* min_pts, int bpd, bool densebox, uint32_t* cl_ord, float4* cl_lo, float4* cl_scale,
+                float* cl_eps2, int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s);
 void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
                 const float4* cl_scale, int bpd, int shift, uint64_t* keys, uint32_t* vals, int sort_bits,
                 uint32_t* hist, hipStream_t s);

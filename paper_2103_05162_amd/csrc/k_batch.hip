@@ -42,9 +42,6 @@ __device__ __forceinline__ uint32_t quantize(float v, float lo, float scale, uin
   return t >= fmax ? maxq : static_cast<uint32_t>(t);
 }
 
-// One workgroup per cloud: bounds, validity of its parameters, eps^2, and the
-// cloud's key scale (points normalised to its box, or DenseBox cells of side
-// eps/sqrt(d), slightly shrunk; the exactness guard covers any rounding).
 // Cloud c's range, clamped into [0, n] (offsets come from the caller's device
 // memory and cannot be checked on the host without waiting).
 __device__ __forceinline__ void cloud_range(const int64_t* off, int c, int64_t n, int64_t& b, int64_t& e) {
@@ -54,65 +51,134 @@ __device__ __forceinline__ void cloud_range(const int64_t* off, int c, int64_t n
   e = e < b ? b : (e > n ? n : e);
 }
 
+// Largest cloud c in [lo, hi] with off[c] <= i (binary search; with offsets out
+// of order the answer is still some cloud in [lo, hi]).
+__device__ __forceinline__ int cloud_at(const int64_t* __restrict__ off, int64_t i, int lo, int hi) {
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Points are processed in chunks of kChunk consecutive points per workgroup
+// (kItems per thread, striped); a chunk's clouds are [s_c[0], s_c[1]].
+constexpr int kItems = 16;
+constexpr int kChunk = kBlock * kItems;
+
+__device__ __forceinline__ void chunk_clouds(const int64_t* off, int num_clouds, int64_t base, int64_t n, int* s_c) {
+  if (threadIdx.x == 0) {
+    const int64_t last = (base + kChunk < n ? base + kChunk : n) - 1;
+    const int c0 = cloud_at(off, base, 0, num_clouds - 1);
+    s_c[0] = c0;
+    s_c[1] = cloud_at(off, last, c0, num_clouds - 1);
+  }
+  __syncthreads();
+}
+
+// Per-cloud bounds (order-preserving uints: cl_ord[8c + k] lo, [8c + 4 + k] hi,
+// pre-filled with 0xffffffff / 0) and non-finite flags, one chunk per
+// workgroup: a workgroup reduction for each cloud the chunk touches, then one
+// atomic per axis bound.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_cloud_prep(const float* __restrict__ pts, const int64_t* __restrict__ off,
-                                                       int num_clouds, int64_t n, const float* __restrict__ eps,
-                                                       const int32_t* __restrict__ mp, int bpd, int densebox,
-                                                       float4* __restrict__ cl_lo, float4* __restrict__ cl_scale,
-                                                       float* __restrict__ cl_eps2, int* __restrict__ cl_minpts,
-                                                       int* __restrict__ cl_flags, uint32_t* __restrict__ info) {
-  const int c = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_cloud_bounds(const float* __restrict__ pts, const int64_t* __restrict__ off,
+                                                         int num_clouds, int64_t n, uint32_t* __restrict__ cl_ord,
+                                                         int* __restrict__ cl_flags) {
+  __shared__ int s_c[2];
+  __shared__ float s_r[kBlock / 64][6];
+  __shared__ int s_bad[kBlock / 64];
+  const int64_t base = blockIdx.x * int64_t(kChunk);
+  chunk_clouds(off, num_clouds, base, n, s_c);
+  const int c0 = s_c[0], c1 = s_c[1];
+  int cl[kItems];
+  float v[kItems][3];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + k * kBlock + threadIdx.x;
+    cl[k] = i < n ? (c0 == c1 ? c0 : cloud_at(off, i, c0, c1)) : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[k][d] = (i < n && d < D) ? pts[i * D + d] : 0.0f;
+  }
+  const int w = threadIdx.x >> 6;
+  for (int c = c0; c <= c1; ++c) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k)
+      if (cl[k] == c)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          bad |= !isfinite(v[k][d]);
+          lo[d] = fminf(lo[d], v[k][d]);
+          hi[d] = fmaxf(hi[d], v[k][d]);
+        }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      for (int o = 32; o > 0; o >>= 1) {
+        lo[d] = fminf(lo[d], __shfl_xor(lo[d], o));
+        hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], o));
+      }
+    bad = ballot(bad != 0) ? 1 : 0;
+    if ((threadIdx.x & 63) == 0) {
+      for (int d = 0; d < 3; ++d) {
+        s_r[w][d] = lo[d];
+        s_r[w][3 + d] = hi[d];
+      }
+      s_bad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int b = 0;
+      for (int j = 0; j < kBlock / 64; ++j) {
+        b |= s_bad[j];
+        for (int d = 0; d < D; ++d) {
+          lo[d] = fminf(lo[d], s_r[j][d]);
+          hi[d] = fmaxf(hi[d], s_r[j][3 + d]);
+        }
+      }
+      for (int d = 0; d < D; ++d)
+        if (lo[d] <= hi[d]) {  // some finite value of this cloud in the chunk
+          atomicMin(cl_ord + 8 * c + d, f2ord(lo[d]));
+          atomicMax(cl_ord + 8 * c + 4 + d, f2ord(hi[d]));
+        }
+      if (b) atomicOr(cl_flags + c, kCloudNonfinite);
+    }
+    __syncthreads();
+  }
+}
+
+// Per-cloud validity, eps^2, minPts and key scale (points normalised to the
+// cloud's box, or DenseBox cells of side eps/sqrt(d), slightly shrunk; the
+// exactness guard covers any rounding). One thread per cloud.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cloud_params(const int64_t* __restrict__ off, int num_clouds, int64_t n,
+                                                         const float* __restrict__ eps, const int32_t* __restrict__ mp,
+                                                         int bpd, int densebox, const uint32_t* __restrict__ cl_ord,
+                                                         float4* __restrict__ cl_lo, float4* __restrict__ cl_scale,
+                                                         float* __restrict__ cl_eps2, int* __restrict__ cl_minpts,
+                                                         int* __restrict__ cl_flags, uint32_t* __restrict__ info) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= num_clouds) return;
   int64_t b, e;
   cloud_range(off, c, n, b, e);
-  __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  bool bad = false;
-  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      float v = pts[i * D + k];
-      bad |= !isfinite(v);
-      lo[k] = fminf(lo[k], v);
-      hi[k] = fmaxf(hi[k], v);
-    }
-  }
-  __shared__ float s_lo[kBlock / 64][3], s_hi[kBlock / 64][3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    for (int o = 32; o > 0; o >>= 1) {
-      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
-      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
-    }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < 3; ++k) {
-      s_lo[w][k] = lo[k];
-      s_hi[w][k] = hi[k];
-    }
-  if (bad) s_bad = 1;
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  int flags = s_bad ? kCloudNonfinite : 0;
+  int flags = cl_flags[c];
   if (off[c] != b || off[c + 1] != e || (c == 0 && b != 0) || (c == num_clouds - 1 && e != n)) flags |= kCloudBadRange;
-  for (int j = 1; j < kBlock / 64; ++j)
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = fminf(lo[k], s_lo[j][k]);
-      hi[k] = fmaxf(hi[k], s_hi[j][k]);
-    }
   const float ec = eps[c];
   const int mc = mp[c];
   if (!(ec > 0.0f) || !isfinite(ec) || mc < 1) flags |= kCloudBadParams;
   cl_flags[c] = flags;
   if (flags & kCloudNonfinite) atomicOr(info, FDB_INFO_NONFINITE);
   if (flags & (kCloudBadParams | kCloudBadRange)) atomicOr(info, FDB_INFO_BAD_PARAMS);
-  const float e2 = ec * ec;
-  cl_eps2[c] = e2;
+  cl_eps2[c] = ec * ec;
   cl_minpts[c] = mc;
   const uint32_t maxq = (1u << bpd) - 1u;
-  float sc[3] = {0.0f, 0.0f, 0.0f};
+  float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f}, sc[3] = {0.0f, 0.0f, 0.0f};
   for (int k = 0; k < D; ++k) {
+    lo[k] = ord2f(cl_ord[8 * c + k]);
+    hi[k] = ord2f(cl_ord[8 * c + 4 + k]);
     if (!(lo[k] <= hi[k])) lo[k] = hi[k] = 0.0f;  // empty cloud
     if (densebox) {
       const double side = static_cast<double>(ec) / sqrt(static_cast<double>(D)) * (1.0 - 1.0 / 1048576.0);
@@ -126,35 +192,51 @@ __global__ __launch_bounds__(kBlock) void k_cloud_prep(const float* __restrict__
   cl_scale[c] = make_float4(sc[0], sc[1], sc[2], 0.0f);
 }
 
-// Keys (cloud id << shift | Morton of the point's, or its cell's, coordinates)
-// and the identity permutation; one workgroup per cloud.
+// Lower-bound words of every cloud start at the largest order-preserving value.
+__global__ __launch_bounds__(kBlock) void k_ord_init(uint32_t* __restrict__ cl_ord, int num_clouds) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= num_clouds) return;
+  for (int k = 0; k < 4; ++k) cl_ord[8 * c + k] = 0xffffffffu;
+}
+
+// Keys (cloud id << shift | Morton of the point's, or its cell's, coordinates),
+// the identity permutation, and the radix sort's digit counts; one chunk of
+// consecutive points per workgroup.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_batch_keys(const float* __restrict__ pts, const int64_t* __restrict__ off,
-                                                       int64_t n, const float4* __restrict__ cl_lo,
+                                                       int num_clouds, int64_t n, const float4* __restrict__ cl_lo,
                                                        const float4* __restrict__ cl_scale, int bpd, int shift,
                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                        int passes, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_h[8 * 256];
+  __shared__ int s_c[2];
   hist_clear(s_h, passes);
-  const int c = blockIdx.x;
-  int64_t b, e;
-  cloud_range(off, c, n, b, e);
-  const float4 lo4 = cl_lo[c], sc4 = cl_scale[c];
-  const float lo[3] = {lo4.x, lo4.y, lo4.z}, sc[3] = {sc4.x, sc4.y, sc4.z};
+  const int64_t base = blockIdx.x * int64_t(kChunk);
+  chunk_clouds(off, num_clouds, base, n, s_c);
+  const int c0 = s_c[0], c1 = s_c[1];
   const uint32_t maxq = (1u << bpd) - 1u;
-  const uint64_t prefix = static_cast<uint64_t>(c) << shift;
-  for (int64_t i = b + threadIdx.x; i < e; i += kBlock) {
-    uint32_t q[D];
+#pragma unroll 4
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = base + k * kBlock + threadIdx.x;
+    const bool valid = i < n;
+    const int c = valid ? (c0 == c1 ? c0 : cloud_at(off, i, c0, c1)) : c0;
+    const float4 lo4 = cl_lo[c], sc4 = cl_scale[c];
+    const float lo[3] = {lo4.x, lo4.y, lo4.z}, sc[3] = {sc4.x, sc4.y, sc4.z};
+    uint64_t key = 0;
+    if (valid) {
+      uint32_t q[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) q[k] = quantize(pts[i * D + k], lo[k], sc[k], maxq);
-    uint64_t code;
-    if constexpr (D == 3)
-      code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    else
-      code = (spread2(q[0]) << 1) | spread2(q[1]);
-    keys[i] = prefix | code;
-    vals[i] = static_cast<uint32_t>(i);
-    hist_add(prefix | code, true, passes, s_h);
+      for (int d = 0; d < D; ++d) q[d] = quantize(pts[i * D + d], lo[d], sc[d], maxq);
+      uint64_t code;
+      if constexpr (D == 3)
+        code = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+      else
+        code = (spread2(q[0]) << 1) | spread2(q[1]);
+      key = (static_cast<uint64_t>(c) << shift) | code;
+      keys[i] = key;
+      vals[i] = static_cast<uint32_t>(i);
+    }
+    hist_add(key, valid, passes, s_h);
   }
   hist_flush(s_h, passes, hist);
 }
@@ -246,14 +328,25 @@ inline int grid_for(int64_t n) {
 }  // namespace
 
 void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float* eps,
-                const int32_t* min_pts, int bpd, bool densebox, float4* cl_lo, float4* cl_scale, float* cl_eps2,
-                int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s) {
-  if (dim == 3)
-    hipLaunchKernelGGL(k_cloud_prep<3>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, num_clouds, n, eps, min_pts,
-                       bpd, densebox ? 1 : 0, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
-  else
-    hipLaunchKernelGGL(k_cloud_prep<2>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, num_clouds, n, eps, min_pts,
-                       bpd, densebox ? 1 : 0, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
+                const int32_t* min_pts, int bpd, bool densebox, uint32_t* cl_ord, float4* cl_lo, float4* cl_scale,
+                float* cl_eps2, int* cl_minpts, int* cl_flags, uint32_t* info, hipStream_t s) {
+  fill_u32(cl_ord, 0u, 8 * int64_t(num_clouds), s);  // hi words 0; k_ord_init sets the lo words
+  hipLaunchKernelGGL(k_ord_init, dim3(static_cast<unsigned>(ceil_div(num_clouds, kBlock))), dim3(kBlock), 0, s,
+                     cl_ord, num_clouds);
+  fill_u32(reinterpret_cast<uint32_t*>(cl_flags), 0u, num_clouds, s);
+  const unsigned chunks = static_cast<unsigned>(ceil_div(n, kChunk));
+  const unsigned pg = static_cast<unsigned>(ceil_div(num_clouds, kBlock));
+  if (dim == 3) {
+    if (chunks) hipLaunchKernelGGL(k_cloud_bounds<3>, dim3(chunks), dim3(kBlock), 0, s, pts, off, num_clouds, n, cl_ord,
+                                   cl_flags);
+    hipLaunchKernelGGL(k_cloud_params<3>, dim3(pg), dim3(kBlock), 0, s, off, num_clouds, n, eps, min_pts, bpd,
+                       densebox ? 1 : 0, cl_ord, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
+  } else {
+    if (chunks) hipLaunchKernelGGL(k_cloud_bounds<2>, dim3(chunks), dim3(kBlock), 0, s, pts, off, num_clouds, n, cl_ord,
+                                   cl_flags);
+    hipLaunchKernelGGL(k_cloud_params<2>, dim3(pg), dim3(kBlock), 0, s, off, num_clouds, n, eps, min_pts, bpd,
+                       densebox ? 1 : 0, cl_ord, cl_lo, cl_scale, cl_eps2, cl_minpts, cl_flags, info);
+  }
 }
 
 void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float4* cl_lo,
@@ -261,12 +354,14 @@ void batch_keys(const float* pts, const int64_t* off, int num_clouds, int64_t n,
                 uint32_t* hist, hipStream_t s) {
   const int passes = (sort_bits + 7) / 8;
   fill_u32(hist, 0, passes * 256, s);
+  const unsigned chunks = static_cast<unsigned>(ceil_div(n, kChunk));
+  if (!chunks) return;
   if (dim == 3)
-    hipLaunchKernelGGL(k_batch_keys<3>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
-                       shift, keys, vals, passes, hist);
+    hipLaunchKernelGGL(k_batch_keys<3>, dim3(chunks), dim3(kBlock), 0, s, pts, off, num_clouds, n, cl_lo, cl_scale,
+                       bpd, shift, keys, vals, passes, hist);
   else
-    hipLaunchKernelGGL(k_batch_keys<2>, dim3(num_clouds), dim3(kBlock), 0, s, pts, off, n, cl_lo, cl_scale, bpd,
-                       shift, keys, vals, passes, hist);
+    hipLaunchKernelGGL(k_batch_keys<2>, dim3(chunks), dim3(kBlock), 0, s, pts, off, num_clouds, n, cl_lo, cl_scale,
+                       bpd, shift, keys, vals, passes, hist);
 }
 
 void batch_roots(const int64_t* off, int num_clouds, int64_t n, const int* pidx, const int* d_m, const int* other,

@@ -1034,8 +1034,8 @@ __global__ void k_main_dbx_points(TravArgs a) {
   }
 }
 
-// Main phase, dense cells, when there are few of them (at most
-// kCellsPerWaveMax): one wavefront per cell A walks the tree once with A's box,
+// Main phase, dense cells, when they are few (see cells_lane_mode):
+// one wavefront per cell A walks the tree once with A's box,
 // over primitives above A; a dense neighbour B joins A's set if some pair is
 // within eps, a core point if some point of A reaches it, and (first-claim
 // mode) a non-core point is claimed the same way. Many cells go to
@@ -1043,12 +1043,20 @@ __global__ void k_main_dbx_points(TravArgs a) {
 // leaves the other's case alone).
 constexpr int kCellsPerWaveMax = 65536;
 
+// More than 65,536 dense cells (8 per wavefront of the 8192 below) go to the
+// lane-per-cell kernel: measured faster there, for small cells (a batch of 4,096
+// clouds: 13 vs 62 ms) and for large ones (a batch of 50 clouds of up to 2M
+// points: 3 vs 8 ms); with fewer cells a wavefront per cell keeps more
+// wavefronts busy (8M-point set, 20k cells: 0.3 vs 0.96 ms). Both kernels read
+// the count.
+__device__ __forceinline__ bool cells_lane_mode(const TravArgs& a) { return *a.d_ndense > kCellsPerWaveMax; }
+
 template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
   __shared__ uint32_t s_stack[4 * kWideStack];  // 256-thread workgroups
   uint32_t* stack = s_stack + (threadIdx.x >> 6) * kWideStack;
   const int nd = *a.d_ndense;
-  if (nd > kCellsPerWaveMax) return;
+  if (cells_lane_mode(a)) return;
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int wave = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
@@ -1101,15 +1109,15 @@ __global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
   }
 }
 
-// Main phase, dense cells, when there are many (more than kCellsPerWaveMax,
-// e.g. a batch of many clouds): one lane per dense cell A, walking (in
+// Main phase, dense cells, when they are many (e.g. a batch of many clouds;
+// see cells_lane_mode): one lane per dense cell A, walking (in
 // lock-step with the other lanes of its wavefront) with A's box over the
 // primitives above A, with the same rules as above; each pair test runs on the
 // whole wavefront (64 points per ballot), one pending lane after another.
 template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_cells_lane(TravArgs a) {
   const int nd = *a.d_ndense;
-  if (nd <= kCellsPerWaveMax) return;
+  if (!cells_lane_mode(a)) return;
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nd);

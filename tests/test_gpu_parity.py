@@ -277,20 +277,31 @@ def test_unaligned_input_pointer(dev, algo):
     assert np.array_equal(lab.cpu().numpy(), ref[0]) and np.array_equal(core.cpu().numpy(), ref[1])
 
 
+_MANY_CELLS = {}
+
+
+def _many_cells_case():
+    if not _MANY_CELLS:
+        rng = np.random.default_rng(91)
+        k, per = 700_000, 6
+        centers = rng.uniform(0, 1, size=(k, 3))
+        pts = (np.repeat(centers, per, axis=0) + 1e-4 * rng.standard_normal((k * per, 3))).astype(np.float32)
+        pts = pts[rng.permutation(len(pts))]
+        eps, mp = 0.003, 4
+        _MANY_CELLS["case"] = (pts, eps, mp, oracle.dbscan(pts, eps, mp))
+    return _MANY_CELLS["case"]
+
+
 @pytest.mark.parametrize("border", ["canonical", "first"])
 def test_many_dense_cells(dev, border):
-    """More dense cells than the wavefront-per-cell kernel takes (65,536): 100k
-    tight clumps of 12 points, each spread over a few cells that must merge."""
-    rng = np.random.default_rng(91)
-    k, per = 100_000, 12
-    centers = rng.uniform(0, 1, size=(k, 3))
-    pts = (np.repeat(centers, per, axis=0) + 5e-4 * rng.standard_normal((k * per, 3))).astype(np.float32)
-    pts = pts[rng.permutation(len(pts))]
-    eps, mp = 0.003, 5
-    ref = oracle.dbscan(pts, eps, mp)
+    """More dense cells than the wavefront-per-cell kernel takes (65,536):
+    700k tight clumps of 6 points, some spread over cells that must merge."""
+    import paper_2103_05162_amd as fdb
+    pts, eps, mp, ref = _many_cells_case()
     _say(f"[gpu] many dense cells: n={len(pts)} K={ref[2]} ({border})")
     if border == "canonical":
         assert_exact(dev, pts, eps, mp, "densebox", ref=ref)
+        assert fdb.default_handle(0).last_counts()["dense_cells"] > 65536
         assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
     else:
         lab, core, kk = run_gpu(dev, pts, eps, mp, "densebox", border="first")
