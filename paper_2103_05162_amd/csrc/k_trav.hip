@@ -398,6 +398,19 @@ __device__ __forceinline__ void core_epilogue(const TravArgs& a, bool mine, int 
 // run) is noise: nothing to claim, no cluster to join.
 __device__ __forceinline__ bool is_lone(const TravArgs& a, int i) { return a.lone && a.lone[i]; }
 
+// An ancestor of x close to its root: labels followed (read only) for a few
+// hops, all lanes of a bucket at once. Equal to a query's root means the two
+// are already in one set (sets only grow); anything else only means "unknown".
+__device__ __forceinline__ int ancestor_of(const int* labels, int x) {
+  int p = labels[x];
+#pragma unroll 1
+  for (int h = 0; h < 16 && p != x; ++h) {
+    x = p;
+    p = labels[x];
+  }
+  return p;
+}
+
 __device__ __forceinline__ float readlane_f(float v, int k) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
@@ -626,7 +639,7 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
       cy = a.xs[a.n + j];
       cz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
       cc = (ALL_CORE || a.core[j]) ? 1 : 0;
-      cl = labels[j];
+      cl = ancestor_of(labels, j);
     }
     for (int k = 0; k < cnt; ++k) {
       const int j = s0 + k;
