@@ -146,10 +146,37 @@ __device__ __forceinline__ Box load_node(const float4* node_a, const float4* nod
   return b;
 }
 
+// The same accesses as 128-bit buffer instructions with the same cache policy
+// (sc1, as the agent-scope 64-bit accesses above): a node is 32 contiguous
+// bytes, so it takes two stores or loads instead of four. Buffer offsets are
+// 32-bit, so this serves node arrays below 2 GiB (kRefitBufMaxNodes).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kPolicySc1 = 16;                  // buffer cache-policy operand: sc1
+constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw-buffer descriptor word 3 on gfx9 parts
+constexpr int64_t kRefitBufMaxNodes = ((int64_t(1) << 31) - 1) / (16 * kNodeStride);
+
+__device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, int p, const Box& b, int o, int g) {
+  const u32x4 va = {__float_as_uint(b.lo[0]), __float_as_uint(b.lo[1]), __float_as_uint(b.lo[2]),
+                    static_cast<uint32_t>(o)};
+  const u32x4 vb = {__float_as_uint(b.hi[0]), __float_as_uint(b.hi[1]), __float_as_uint(b.hi[2]),
+                    static_cast<uint32_t>(g)};
+  __builtin_amdgcn_raw_buffer_store_b128(va, r, p * (16 * kNodeStride), 0, kPolicySc1);
+  __builtin_amdgcn_raw_buffer_store_b128(vb, r, p * (16 * kNodeStride) + 16, 0, kPolicySc1);
+}
+
+__device__ __forceinline__ Box load_node_buf(__amdgpu_buffer_rsrc_t r, int k) {
+  const u32x4 va = __builtin_amdgcn_raw_buffer_load_b128(r, k * (16 * kNodeStride), 0, kPolicySc1);
+  const u32x4 vb = __builtin_amdgcn_raw_buffer_load_b128(r, k * (16 * kNodeStride) + 16, 0, kPolicySc1);
+  Box b;
+  b.lo[0] = __uint_as_float(va.x); b.lo[1] = __uint_as_float(va.y); b.lo[2] = __uint_as_float(va.z);
+  b.hi[0] = __uint_as_float(vb.x); b.hi[1] = __uint_as_float(vb.y); b.hi[2] = __uint_as_float(vb.z);
+  return b;
+}
+
 // Bottom-up refit: each leaf walks towards the root; at every internal node the
 // second of the two arriving threads merges its box with the sibling's and
 // continues upwards, so every box is the exact min/max of its leaves.
-template <int D>
+template <int D, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
                                                   int64_t n,
                                                   LeafSrc ls, const int* __restrict__ other, const int* __restrict__ gamma,
@@ -158,6 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
   const int m = d_m ? *d_m : m_cap;
   int l = blockIdx.x * kBlock + threadIdx.x;
   if (m < 2 || l >= m) return;
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc(node_a, 0, BUF ? m_cap * (16 * kNodeStride) : 0, kBufferWord3);
   Box box = leaf_box<D>(l, xs, n, ls);
   int prev = l;
   bool prev_leaf = true;
@@ -179,15 +208,19 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
     const bool came_left = prev == g && prev_leaf == left_leaf;
     Box sib;
     if (came_left)
-      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls) : load_node(node_a, node_b, g + 1);
+      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls)
+                       : (BUF ? load_node_buf(rb, g + 1) : load_node(node_a, node_b, g + 1));
     else
-      sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : load_node(node_a, node_b, g);
+      sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : (BUF ? load_node_buf(rb, g) : load_node(node_a, node_b, g));
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       box.lo[k] = fminf(box.lo[k], sib.lo[k]);
       box.hi[k] = fmaxf(box.hi[k], sib.hi[k]);
     }
-    store_node(node_a, node_b, p, box, o, g);
+    if (BUF)
+      store_node_buf(rb, p, box, o, g);
+    else
+      store_node(node_a, node_b, p, box, o, g);
     prev = p;
     prev_leaf = false;
     p = parent[p];
@@ -207,12 +240,19 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
   }
   hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
   if (m_cap >= 2) {
-    if (dim == 3)
-      hipLaunchKernelGGL(k_refit<3>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other,
-                         gamma, parent, flags, node_a, node_b, info);
+    const bool buf = m_cap <= kRefitBufMaxNodes;
+    if (dim == 3 && buf)
+      hipLaunchKernelGGL((k_refit<3, true>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
+                         parent, flags, node_a, node_b, info);
+    else if (dim == 3)
+      hipLaunchKernelGGL((k_refit<3, false>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
+                         parent, flags, node_a, node_b, info);
+    else if (buf)
+      hipLaunchKernelGGL((k_refit<2, true>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
+                         parent, flags, node_a, node_b, info);
     else
-      hipLaunchKernelGGL(k_refit<2>, dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other,
-                         gamma, parent, flags, node_a, node_b, info);
+      hipLaunchKernelGGL((k_refit<2, false>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
+                         parent, flags, node_a, node_b, info);
   }
 }
 
