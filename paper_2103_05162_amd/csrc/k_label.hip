@@ -115,11 +115,17 @@ __global__ __launch_bounds__(kBlock) void k_cluster_ids(const int* __restrict__ 
     if (core[i] && labels[i] == i) cid[i] = leaders_before(bits, wpre, minorig[i], n, total);
 }
 
+// Output scatter from sorted order to input order. The destinations are
+// random, so every store costs a memory transaction of its own: with PACK the
+// core flag rides in bit 30 of the label (cluster ids stay below 2^30), one
+// random store per point, and k_split_core unpacks it in a coalesced pass.
+constexpr int kCoreBit = 1 << 30;
+
+template <bool PACK>
 __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ labels, const uint8_t* __restrict__ core,
                                                     const uint32_t* __restrict__ perm, const int* __restrict__ cid,
                                                     const int* __restrict__ border, int mode, int64_t n,
-                                                    int32_t* __restrict__ out, uint8_t* __restrict__ out_core,
-                                                    uint32_t* __restrict__ info) {
+                                                    int32_t* __restrict__ out, uint32_t* __restrict__ info) {
   // mode 0: non-core = noise; 1: non-core from the border pass; 2: first claim
   for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     const uint32_t o = perm[i];
@@ -133,8 +139,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ labe
     else if (mode == 1) v = border[i];
     else if (mode == 2) v = labels[i] != i ? cid[labels[i]] : -1;
     else v = -1;
-    out[o] = v;
-    if (out_core) out_core[o] = c ? 1 : 0;
+    out[o] = PACK && c && v >= 0 ? (v | kCoreBit) : v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_core(int32_t* __restrict__ out, uint8_t* __restrict__ out_core,
+                                                       int64_t n) {
+  for (int64_t j = blockIdx.x * int64_t(kBlock) + threadIdx.x; j < n; j += int64_t(gridDim.x) * kBlock) {
+    const int v = out[j];
+    const bool c = v >= 0 && (v & kCoreBit);
+    if (c) out[j] = v & ~kCoreBit;
+    out_core[j] = c ? 1 : 0;
   }
 }
 
@@ -296,8 +311,14 @@ void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm
                     bool first_border, bool have_border, int64_t n, int32_t* out_labels, uint8_t* out_core,
                     uint32_t* info, hipStream_t s) {
   int mode = have_border ? 1 : (first_border ? 2 : 0);
-  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, cid, border, mode, n,
-                     out_labels, out_core, info);
+  if (out_core) {
+    hipLaunchKernelGGL(k_scatter<true>, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, cid, border,
+                       mode, n, out_labels, info);
+    hipLaunchKernelGGL(k_split_core, dim3(grid_for(n)), dim3(kBlock), 0, s, out_labels, out_core, n);
+  } else {
+    hipLaunchKernelGGL(k_scatter<false>, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, cid, border,
+                       mode, n, out_labels, info);
+  }
 }
 
 }  // namespace fdb
