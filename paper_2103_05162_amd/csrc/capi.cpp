@@ -352,7 +352,7 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
   if (st == FDB_OK) {
     fill_u32(reinterpret_cast<uint32_t*>(xs), 0, 3 * M, s);
     fill_u32(h->d_info, 0, 1, s);
-    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
+    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
                h->d_info, s);
     TreeView t{na, nb, rope, lrope, m, nullptr, leaf_size};
     launch_debug_walk(t, m, mask, leaves, count, m, h->d_info, s);
@@ -552,8 +552,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   if (densebox) {
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
-               at<float4>(ws, plan.prim_hi), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
-               at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
     ta.t.m_cap = static_cast<int>(n);
@@ -578,8 +577,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
     launch_init_labels(lab, n, s);
     st.mark("lbvh");
-    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, nullptr, nullptr,
-               at<float4>(ws, plan.node_a),
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
                nullptr, h->d_info, s);
@@ -767,8 +765,7 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
                    core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2);
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
-               at<float4>(ws, plan.prim_hi), at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
-               at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
+               at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
     batch_roots(offsets, num_clouds, n, at<int>(ws, plan.cand), misc + kMiscNumPrims, at<int>(ws, plan.other),
@@ -783,8 +780,7 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   } else {
     launch_init_labels(lab, n, s);
     st.mark("lbvh");
-    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, nullptr, nullptr,
-               at<float4>(ws, plan.node_a),
+    build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
                nullptr, h->d_info, s);

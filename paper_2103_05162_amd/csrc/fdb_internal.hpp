@@ -99,9 +99,10 @@ int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64
                uint32_t* info, hipStream_t s);
 
 // k_tree.hip
+// prim_lo / prim_hi: DenseBox leaf records (null for FDbscan, whose leaves are
+// the sorted points); see TravArgs.
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
-                const float4* prim_lo, const float4* prim_hi, const int* prim_start, const int* prim_cnt,
-                float4* node_a, float4* node_b, int* rope,
+                const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
                 int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m, uint32_t* info,
                 hipStream_t s);
 
@@ -147,9 +148,14 @@ struct TravArgs {
   int* qborder_n;
   const int* cid;
   int* border;
-  // DenseBox primitives (null for FDbscan)
+  // DenseBox primitives (null for FDbscan). Primitive r covers sorted points
+  // [prim_start[r], prim_start[r] + |prim_cnt[r]|); prim_cnt > 0: a single
+  // point, < 0: a dense cell. prim_lo[r] is the leaf record a walk loads: a
+  // point's coordinates with its sorted index as int bits in w (>= 0), or a
+  // dense cell's low corner with w = -2 - its first point; prim_hi[r] is a
+  // dense cell's high corner.
   const int* prim_start;
-  const int* prim_cnt;  // > 0: a single point; < 0: -(count) points of a dense cell
+  const int* prim_cnt;
   const float4* prim_lo;
   const float4* prim_hi;
   const int* dense_list;  // dense-cell primitive indices

@@ -179,19 +179,21 @@ __global__ __launch_bounds__(kPushBlock) void k_prims(const K* __restrict__ keys
         labels[i] = s;
         core[i] = 1;
         if (opens_dense) {
+          const float4 cl = cell_lo[c];
           prim_start[p] = s;
           prim_cnt[p] = -(cell_start[c + 1] - s);
-          prim_lo[p] = cell_lo[c];
+          prim_lo[p] = make_float4(cl.x, cl.y, cl.z, __int_as_float(-2 - s));
           prim_hi[p] = cell_hi[c];
           prim_key[p] = keys[i];
           pd = p;
         }
       } else {
-        const int p = pidx[i];  // a point primitive: its box is the point (never stored)
+        const int p = pidx[i];  // a point primitive: its box is the point
         labels[i] = i;
         core[i] = 0;
         prim_start[p] = i;
         prim_cnt[p] = 1;
+        prim_lo[p] = make_float4(xs[i], xs[n + i], D == 3 ? xs[2 * n + i] : 0.0f, __int_as_float(i));
         prim_key[p] = keys[i];
       }
     }

@@ -718,10 +718,30 @@ __global__ void k_border_fdb(TravArgs a) {
 // wavefronts are full and in Morton order); a dense cell queries once, one
 // wavefront per cell, whose 64 lanes test the cell's points together.
 
+// A walk reads primitive r through its leaf record prim_lo[r] (see TravArgs):
+// one 16-byte load gives a point primitive's coordinates and sorted index, or a
+// dense cell's low corner and first point.
+__device__ __forceinline__ int rec_index(float4 lr) { return __float_as_int(lr.w); }
+
 template <int D>
-__device__ __forceinline__ bool box_near(const TravArgs& a, int p, const Query& q, float eps2) {
-  float4 lo = a.prim_lo[p], hi = a.prim_hi[p];
+__device__ __forceinline__ bool rec_point_near(float4 lr, const Query& q, float eps2) {
+  return dist2v<D>(lr.x, lr.y, lr.z, q.x, q.y, q.z) <= eps2;
+}
+
+template <int D>
+__device__ __forceinline__ bool cell_box_near(const TravArgs& a, int r, float4 lo, const Query& q, float eps2) {
+  const float4 hi = a.prim_hi[r];
   return box_dist2<D>(q.x, q.y, q.z, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= eps2;
+}
+
+// The query of point primitive p (its record), or an idle lane's (mine false).
+__device__ __forceinline__ void own_record(const TravArgs& a, int p, int m, bool& mine, int& i, Query& q) {
+  const float4 lr = p >= 0 && p < m ? a.prim_lo[p] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+  mine = rec_index(lr) >= 0;
+  i = mine ? rec_index(lr) : 0;
+  q.x = lr.x;
+  q.y = lr.y;
+  q.z = lr.z;
 }
 
 // Is some point of the cell [sa, sa+na) within eps of p? (whole wavefront)
@@ -927,10 +947,8 @@ __global__ void k_core_dbx(TravArgs a) {
 #pragma unroll
   for (int t = 0; t < kCoreQ; ++t) {
     p[t] = k >= 0 ? static_cast<int>(k * kCoreQ + t) : -1;
-    mine[t] = p[t] >= 0 && p[t] < m && a.prim_cnt[p[t]] > 0;  // dense cells are core by construction
-    i[t] = mine[t] ? a.prim_start[p[t]] : 0;
+    own_record(a, p[t], m, mine[t], i[t], q[t]);  // dense cells are core by construction
     sc[t] = scope_of<B>(a, m, i[t]);
-    q[t] = load_point<D>(a.xs, a.n, i[t]);
     cnt[t] = 0;
     rec_init(rec[t], s_rec + t * kRecNb * blockDim.x);
     walk_init<false>(w[t], m, sc[t], 0, mine[t]);
@@ -948,13 +966,14 @@ __global__ void k_core_dbx(TravArgs a) {
       if (active[t]) {
         const int r = walk_step<D, false>(w[t], a.t, m, q[t], sc[t].eps2, 0, a.info);
         if (r >= 0) {
-          const int c = a.prim_cnt[r], s = a.prim_start[r];
-          if (c > 0) {
-            if (near<D>(a.xs, a.n, s, q[t], sc[t].eps2)) {
+          const float4 lr = a.prim_lo[r];
+          const int s = rec_index(lr);
+          if (s >= 0) {
+            if (rec_point_near<D>(lr, q[t], sc[t].eps2)) {
               ++cnt[t];
               if (s != i[t]) rec_add(rec[t], s);
             }
-          } else if (box_near<D>(a, r, q[t], sc[t].eps2)) {
+          } else if (cell_box_near<D>(a, r, lr, q[t], sc[t].eps2)) {
             pend[t] = r;
           }
         }
@@ -992,12 +1011,13 @@ __global__ void k_main_dbx_points(TravArgs a) {
   const int64_t p0 = xcd_spread(blockIdx.x, blockDim.x, 0, m);
   if (p0 < 0 || p0 >= m) return;  // the grid is sized for n; past the primitives
   const int p = static_cast<int>(xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, m));
-  const bool pt = p >= 0 && p < m && a.prim_cnt[p] > 0;
-  const int i = pt ? a.prim_start[p] : 0;
+  bool pt;
+  int i;
+  Query q;
+  own_record(a, p, m, pt, i, q);
   const bool ci = pt && (ALL_CORE || a.core[i]);
   const bool mine = pt && (ci || (FIRST && !is_lone(a, i)));
   const Scope sc = scope_of<B>(a, m, i);
-  const Query q = load_point<D>(a.xs, a.n, i);
   int* labels = a.labels;
   // the core pass may already have joined i to dense cells it reaches
   int root = mine && ci ? uf_find(labels, i, a.info) : i;
@@ -1009,9 +1029,10 @@ __global__ void k_main_dbx_points(TravArgs a) {
     if (active) {
       const int r = walk_step<D, true>(w, a.t, m, q, sc.eps2, p, a.info);
       if (r >= 0) {
-        const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) {
-          if (near<D>(a.xs, a.n, s, q, sc.eps2)) {
+        const float4 lr = a.prim_lo[r];
+        const int s = rec_index(lr);
+        if (s >= 0) {
+          if (rec_point_near<D>(lr, q, sc.eps2)) {
             const bool cj = ALL_CORE || a.core[s];
             if (ci && cj) {
               if (!known_same_set(labels, s, root)) root = uf_union(labels, root, s, a.info);
@@ -1022,7 +1043,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
               active = false;  // i is a member now (by this or an earlier claim)
             }
           }
-        } else if (box_near<D>(a, r, q, sc.eps2) && !(ci && known_same_set(labels, s, root))) {
+        } else if (cell_box_near<D>(a, r, lr, q, sc.eps2) && !(ci && known_same_set(labels, ref_point(s), root))) {
           pend = r;
         }
       }
@@ -1089,10 +1110,10 @@ __global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
     int root = sa;
     traverse_box_wide<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, stack, [&](int r0, int r1) {
       for (int r = r0; r <= r1; ++r) {
-        const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) {
-          const int j = s;
-          const float px = a.xs[j], py = a.xs[a.n + j], pz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
+        const float4 lr = a.prim_lo[r];
+        if (rec_index(lr) >= 0) {
+          const int j = rec_index(lr);
+          const float px = lr.x, py = lr.y, pz = lr.z;
           if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) continue;
           const bool cj = ALL_CORE || a.core[j];
           if (cj) {
@@ -1108,10 +1129,11 @@ __global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
           }
           continue;
         }
-        const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
+        const int s = ref_point(rec_index(lr));
+        const float4 blo = lr, bhi = a.prim_hi[r];
         if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) continue;
         if (known_same_set(labels, s, root)) continue;
-        if (cells_touch<D>(a.xs, a.n, sa, na, s, -c, blo, bhi, eps2)) {
+        if (cells_touch<D>(a.xs, a.n, sa, na, s, -a.prim_cnt[r], blo, bhi, eps2)) {
           int nr = 0;
           if (lane == 0) nr = uf_union(labels, root, s, a.info);
           root = __shfl(nr, 0);
@@ -1156,9 +1178,10 @@ __global__ void k_main_dbx_cells_lane(TravArgs a) {
     if (active) {
       const int r = walk_step<D, true>(w, a.t, m, qa, sc.eps2, A, a.info);
       if (r >= 0) {
-        const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) {
-          const float px = a.xs[s], py = a.xs[a.n + s], pz = D == 3 ? a.xs[2 * a.n + s] : 0.0f;
+        const float4 lr = a.prim_lo[r];
+        const int s = ref_point(rec_index(lr));
+        if (rec_index(lr) >= 0) {
+          const float px = lr.x, py = lr.y, pz = lr.z;
           if (box_dist2<D>(px, py, pz, qa.lo[0], qa.lo[1], qa.lo[2], qa.hi[0], qa.hi[1], qa.hi[2]) <= sc.eps2) {
             if (ALL_CORE || a.core[s]) {
               if (!known_same_set(labels, s, root)) pend = r;
@@ -1167,7 +1190,7 @@ __global__ void k_main_dbx_cells_lane(TravArgs a) {
             }
           }
         } else {
-          const float4 blo = a.prim_lo[r], bhi = a.prim_hi[r];
+          const float4 blo = lr, bhi = a.prim_hi[r];
           if (boxbox_dist2<D>(qa.lo, qa.hi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) <= sc.eps2 &&
               !known_same_set(labels, s, root))
             pend = r;
@@ -1209,9 +1232,10 @@ __global__ void k_border_dbx(TravArgs a) {
   const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, nq);
   const bool mine = k >= 0 && k < nq;
   const int p = mine ? a.qborder[k] : 0;
-  const int i = mine ? a.prim_start[p] : 0;
+  const float4 own = mine ? a.prim_lo[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const int i = mine ? rec_index(own) : 0;
   const Scope sc = scope_of<B>(a, m, i);
-  const Query q = load_point<D>(a.xs, a.n, i);
+  const Query q{own.x, own.y, own.z};
   int best = 0x7fffffff;
   Walk w;
   walk_init<false>(w, m, sc, 0, mine);
@@ -1221,13 +1245,14 @@ __global__ void k_border_dbx(TravArgs a) {
     if (active) {
       const int r = walk_step<D, false>(w, a.t, m, q, sc.eps2, 0, a.info);
       if (r >= 0) {
-        const int c = a.prim_cnt[r], s = a.prim_start[r];
-        if (c > 0) {
-          if (a.core[s] && near<D>(a.xs, a.n, s, q, sc.eps2)) {
+        const float4 lr = a.prim_lo[r];
+        const int s = rec_index(lr);
+        if (s >= 0) {
+          if (rec_point_near<D>(lr, q, sc.eps2) && a.core[s]) {
             const int id = a.cid[a.labels[s]];
             best = id < best ? id : best;
           }
-        } else if (box_near<D>(a, r, q, sc.eps2) && a.cid[a.labels[s]] < best) {
+        } else if (cell_box_near<D>(a, r, lr, q, sc.eps2) && a.cid[a.labels[ref_point(s)]] < best) {
           pend = r;
         }
       }

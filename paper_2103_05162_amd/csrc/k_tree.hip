@@ -88,31 +88,31 @@ struct Box {
 
 // Leaves are points (FDbscan: leaf l is sorted point l), or DenseBox
 // primitives: a dense cell's stored box, or the single point it starts at.
+// DenseBox leaves: primitive l's record lo[l] holds a single point and its
+// sorted index (w >= 0), or a dense cell's low corner (w < 0; the high corner
+// is hi[l]).
 struct LeafSrc {
-  const float4* lo;   // null: leaves are the sorted points
+  const float4* lo;  // null: leaves are the sorted points
   const float4* hi;
-  const int* start;
-  const int* cnt;
 };
 
 template <int D>
 __device__ __forceinline__ Box leaf_box(int l, const float* __restrict__ xs, int64_t n, const LeafSrc& ls) {
   Box b;
-  int j = l;
   if (ls.lo) {
-    if (ls.cnt[l] < 0) {
-      float4 a = ls.lo[l], c = ls.hi[l];
-      b.lo[0] = a.x; b.lo[1] = a.y; b.lo[2] = a.z;
+    const float4 a = ls.lo[l];
+    b.lo[0] = a.x; b.lo[1] = a.y; b.lo[2] = a.z;
+    if (__float_as_int(a.w) < 0) {
+      const float4 c = ls.hi[l];
       b.hi[0] = c.x; b.hi[1] = c.y; b.hi[2] = c.z;
-      return b;
+    } else {
+      b.hi[0] = a.x; b.hi[1] = a.y; b.hi[2] = a.z;
     }
-    j = ls.start[l];
+    return b;
   }
-  {
-    b.lo[0] = b.hi[0] = xs[j];
-    b.lo[1] = b.hi[1] = xs[n + j];
-    b.lo[2] = b.hi[2] = D == 3 ? xs[2 * n + j] : 0.0f;
-  }
+  b.lo[0] = b.hi[0] = xs[l];
+  b.lo[1] = b.hi[1] = xs[n + l];
+  b.lo[2] = b.hi[2] = D == 3 ? xs[2 * n + l] : 0.0f;
   return b;
 }
 
@@ -259,10 +259,9 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
 }  // namespace
 
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
-                const float4* prim_hi, const int* prim_start, const int* prim_cnt, float4* node_a, float4* node_b,
-                int* rope, int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m,
-                uint32_t* info, hipStream_t s) {
-  const LeafSrc ls{prim_lo, prim_hi, prim_start, prim_cnt};
+                const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* parent,
+                int* flags, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s) {
+  const LeafSrc ls{prim_lo, prim_hi};
   if (key64)
     build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, parent,
             flags, other, gamma, info, s);
