@@ -26,6 +26,15 @@ def default_handle(device: int = 0) -> Handle:
     return h
 
 
+def _check_out(labels, is_core, n):
+    """Caller-supplied outputs: int32 labels and one byte (uint8 or bool) per core flag, n of each, contiguous."""
+    import torch
+    if labels.dtype != torch.int32 or labels.numel() < n or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 tensor of at least n elements")
+    if is_core.dtype not in (torch.uint8, torch.bool) or is_core.numel() < n or not is_core.is_contiguous():
+        raise ValueError("is_core must be a contiguous uint8 or bool tensor of at least n elements")
+
+
 def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str = "canonical",
            leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
            want_k: bool = True, workspace=None):
@@ -50,13 +59,14 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
         labels = torch.empty(n, dtype=torch.int32, device=pts.device)
     if is_core is None:
         is_core = torch.empty(n, dtype=torch.uint8, device=pts.device)
+    _check_out(labels, is_core, n)
     opt = make_options(algo, border, leaf_size, block_size)
     stream = torch.cuda.current_stream(pts.device).cuda_stream
     ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
         else (None, 0)
     k = h.dbscan_raw(pts.data_ptr() if n else 0, n, d, eps, min_pts, labels.data_ptr() if n else 0,
                      is_core.data_ptr() if n else 0, stream, opt, want_k, ws_ptr, ws_size)
-    return labels, is_core.bool(), k
+    return labels, is_core.view(torch.bool), k
 
 
 def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border: str = "canonical",
@@ -90,6 +100,7 @@ def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     if is_core is None:
         is_core = torch.empty(n, dtype=torch.uint8, device=dev)
+    _check_out(labels, is_core, n)
     if num_clusters is None:
         num_clusters = torch.empty(b, dtype=torch.int32, device=dev)
     opt = make_options(algo, border, leaf_size, block_size)
@@ -99,4 +110,4 @@ def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border:
     h.dbscan_batched_raw(pts.data_ptr() if n else 0, n, offs.data_ptr(), b, d, e.data_ptr(), mp.data_ptr(),
                          labels.data_ptr() if n else 0, is_core.data_ptr() if n else 0, num_clusters.data_ptr(),
                          stream, opt, ws_ptr, ws_size)
-    return labels, is_core.bool(), num_clusters
+    return labels, is_core.view(torch.bool), num_clusters

@@ -115,13 +115,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__
     const int c = cand[w];
     const int s = cell_start[c], e = cell_start[c + 1];
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int j = s + lane; j < e; j += 64) {
+    // four 64-point chunks per trip: their loads are in flight together
+    for (int j0 = s + lane; j0 < e; j0 += 4 * 64) {
+      float v[4][3];
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        float v = xs[k * n + j];
-        lo[k] = fminf(lo[k], v);
-        hi[k] = fmaxf(hi[k], v);
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u * 64;
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[u][k] = j < e ? xs[k * n + j] : NAN;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          lo[k] = fminf(lo[k], v[u][k]);  // fminf/fmaxf ignore the NaN fill
+          hi[k] = fmaxf(hi[k], v[u][k]);
+        }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)

@@ -837,7 +837,7 @@ struct Walk {
   uint32_t node;  // next node to examine, kEnd when finished
   int cur, end;   // pending bucket primitives [cur, end]; empty when cur > end
   int last;       // last primitive of the scope
-  int64_t steps;  // remaining step budget (see traverse())
+  uint32_t steps;  // remaining step budget (see traverse()); 2m + 2 <= 2^31
 };
 
 template <bool MASKED>
@@ -845,7 +845,7 @@ __device__ __forceinline__ void walk_init(Walk& w, int m, const Scope& sc, int m
   w.cur = 1;
   w.end = 0;
   w.last = sc.end;
-  w.steps = 2 * int64_t(m) + 2;
+  w.steps = 2u * static_cast<uint32_t>(m) + 2u;
   if (!on || m <= 0 || (MASKED && mask >= sc.end)) w.node = kEnd;
   else w.node = sc.start;
 }
@@ -872,7 +872,7 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   if (w.cur <= w.end) return w.cur++;
   const uint32_t node = w.node;
   if (node == kEnd) return -1;
-  if (--w.steps < 0) {
+  if (w.steps-- == 0) {
     atomicOr(info, kInternalBit);
     w.node = kEnd;
     return -1;
