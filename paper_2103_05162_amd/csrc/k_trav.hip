@@ -291,6 +291,97 @@ __device__ __forceinline__ void traverse_box_wide(const TreeView& t, int m, cons
   }
 }
 
+// traverse_box_wide delivering primitives rather than ranges: every bucket and
+// leaf that one step of the walk reaches is handed out a primitive per lane,
+// visit_lanes(r) being called on the whole wavefront with each lane's own
+// primitive (-1 for none), so the visitor loads all of them at once.
+template <int D, typename F>
+__device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m, const Scope& sc, const float* lo,
+                                                        const float* hi, int mask, int leaf_size, uint32_t* info,
+                                                        uint32_t* stack, F&& visit_lanes) {
+  if (m <= 0 || mask >= sc.end) return;
+  const int lane = lane_id();
+  // a range [s, e] of one lane (wave-uniform arguments), 64 primitives per call
+  auto range = [&](int s, int e) {
+    for (int b = s; b <= e; b += 64)
+      if (visit_lanes(b + lane <= e ? b + lane : -1)) return true;
+    return false;
+  };
+  if (lane == 0) stack[0] = sc.start;
+  int top = 1;
+  int64_t guard = 0;
+  const int64_t max_rounds = 2 * int64_t(m) + 2;
+  while (top > 0) {
+    if (++guard > max_rounds) {
+      atomicOr(info, kInternalBit);
+      return;
+    }
+    const int take = top < 64 ? top : 64;
+    top -= take;
+    const uint32_t node = lane < take ? stack[top + lane] : kEnd;
+    int bs = -1, be = -1;
+    uint32_t c0 = kEnd, c1 = kEnd;
+    if (node != kEnd) {
+      if (node & kLeaf) {
+        const int l = static_cast<int>(node & ~kLeaf);
+        if (l >= m) atomicOr(info, kInternalBit);
+        else if (l > mask) bs = be = l;
+      } else if (node >= static_cast<uint32_t>(m - 1)) {
+        atomicOr(info, kInternalBit);
+      } else {
+        const float4 na = t.node_a[kNodeStride * size_t(node)];
+        const float4 nb = t.node_b[kNodeStride * size_t(node)];
+        const int k = static_cast<int>(node);
+        const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
+        const int first = o < k ? o : k, last = o > k ? o : k;
+        if (last > mask && boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) <= sc.eps2) {
+          if (first < 0 || last >= m || g < first || g >= last) {
+            atomicOr(info, kInternalBit);
+          } else if (last - first < leaf_size) {
+            bs = first <= mask ? mask + 1 : first;
+            be = last;
+          } else {
+            if (g > mask) c0 = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
+            c1 = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
+          }
+        }
+      }
+    }
+    // this step's buckets, round t taking each lane's t-th primitive
+    int len = bs >= 0 ? be - bs + 1 : 0;
+    int rounds = len;
+    for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off));
+    for (int r = 0; r < rounds; ++r)
+      if (visit_lanes(r < len ? bs + r : -1)) return;
+    const uint64_t m0 = ballot(c0 != kEnd), m1 = ballot(c1 != kEnd);
+    const int n0 = __popcll(m0), n1 = __popcll(m1);
+    if (top + n0 + n1 <= kWideStack) {
+      const uint64_t lt = lanemask_lt();
+      if (c0 != kEnd) stack[top + __popcll(m0 & lt)] = c0;
+      if (c1 != kEnd) stack[top + n0 + __popcll(m1 & lt)] = c1;
+      top += n0 + n1;
+    } else {
+      // stack full: walk each child's subtree on its own
+      for (uint64_t cm = m0 | m1; cm; cm &= cm - 1) {
+        const int L = __ffsll(static_cast<unsigned long long>(cm)) - 1;
+        for (int side = 0; side < 2; ++side) {
+          const uint32_t c = static_cast<uint32_t>(__shfl(static_cast<int>(side ? c1 : c0), L));
+          if (c == kEnd) continue;
+          int end;
+          if (c & kLeaf) {
+            end = static_cast<int>(c & ~kLeaf);
+          } else {
+            const int oc = __float_as_int(t.node_a[kNodeStride * size_t(c)].w);
+            end = oc > static_cast<int>(c) ? oc : static_cast<int>(c);
+          }
+          const Scope sub{c, end, sc.eps2, sc.min_pts};
+          if (traverse_box<D>(t, m, sub, lo, hi, mask, leaf_size, info, range)) return;
+        }
+      }
+    }
+  }
+}
+
 // True only if `root` is an ancestor of x within a few plain-load hops (then x
 // already is in root's set: sets only grow). False means "unknown". When the
 // chain had intermediate links, x is re-pointed straight at root (an ancestor,
@@ -1004,8 +1095,18 @@ __global__ void k_core_dbx(TravArgs a) {
 // One lane per point primitive; lanes whose point is not a query stay idle.
 // (Compacting the few core queries into full wavefronts was slower: their
 // wavefront-wide cell scans then run on too few wavefronts to fill the chip.)
+// Canonical labels: when a wavefront's core queries lie in a box at most
+// kPointsPacketExt eps wide (and, in a batch, in one cloud), they walk as one
+// packet: one lane-parallel wide walk over the box reaches every primitive above
+// the smallest query within eps of any query; each candidate is broadcast and
+// every lane keeps the pairs above its own primitive, so the unions are those of
+// the per-lane walks. Queries around a dense clump otherwise each walk most of
+// the clump's subtree one node per step.
+constexpr float kPointsPacketExt = 8.0f;
+
 template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_points(TravArgs a) {
+  extern __shared__ uint32_t s_pstack[];  // kWideStack entries per wavefront
   const int m = tree_m(a.t);
   const int lane = lane_id();
   const int64_t p0 = xcd_spread(blockIdx.x, blockDim.x, 0, m);
@@ -1021,6 +1122,76 @@ __global__ void k_main_dbx_points(TravArgs a) {
   int* labels = a.labels;
   // the core pass may already have joined i to dense cells it reaches
   int root = mine && ci ? uf_find(labels, i, a.info) : i;
+  if (!FIRST) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (mine) {
+      lo[0] = hi[0] = q.x;
+      lo[1] = hi[1] = q.y;
+      lo[2] = hi[2] = q.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[d] = fminf(lo[d], __shfl_xor(lo[d], off));
+        hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], off));
+      }
+    const uint64_t mm = ballot(mine);
+    if (!mm) return;
+    const int fl = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+    const int i0 = __shfl(i, fl), p0 = __shfl(p, fl);  // primitives rise with the lanes
+    const Scope ps = scope_of<B>(a, m, i0);
+    const bool other_cloud = B && mine && cloud_of(a, i) != cloud_of(a, i0);
+    float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
+    if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
+    if (!ballot(other_cloud) && ext * ext <= kPointsPacketExt * kPointsPacketExt * ps.eps2) {
+      const float eps2 = ps.eps2;
+      uint32_t* stack = s_pstack + (threadIdx.x >> 6) * kWideStack;
+      traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, p0, a.t.leaf_size, a.info, stack, [&](int r) {
+        float4 lr = make_float4(0.0f, 0.0f, 0.0f, 0.0f), hr = lr;
+        bool hit = false;
+        int anc = -1;
+        if (r >= 0) {
+          lr = a.prim_lo[r];
+          const int v = rec_index(lr);
+          if (v >= 0) {
+            hit = (ALL_CORE || a.core[v]) &&
+                  box_dist2<D>(lr.x, lr.y, lr.z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]) <= eps2;
+          } else {
+            hr = a.prim_hi[r];
+            hit = boxbox_dist2<D>(lo, hi, lr.x, lr.y, lr.z, hr.x, hr.y, hr.z) <= eps2;
+          }
+          if (hit) anc = ancestor_of(labels, ref_point(v));
+        }
+        for (uint64_t vm = ballot(hit); vm; vm &= vm - 1) {
+          const int k = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+          const int rk = __builtin_amdgcn_readlane(r, k);
+          const int v = __builtin_amdgcn_readlane(rec_index(lr), k);
+          const int j = ref_point(v);
+          const int ak = __builtin_amdgcn_readlane(anc, k);
+          const float px = readlane_f(lr.x, k), py = readlane_f(lr.y, k), pz = readlane_f(lr.z, k);
+          if (v >= 0) {  // a core point
+            if (mine && rk > p && ak != root && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 &&
+                !known_same_set(labels, j, root))
+              root = uf_union(labels, root, j, a.info);
+            continue;
+          }
+          // a dense cell: one of its points within eps of the query suffices
+          const float ux = readlane_f(hr.x, k), uy = readlane_f(hr.y, k), uz = readlane_f(hr.z, k);
+          const bool nb = mine && rk > p && ak != root &&
+                          box_dist2<D>(q.x, q.y, q.z, px, py, pz, ux, uy, uz) <= eps2 &&
+                          !known_same_set(labels, j, root);
+          for (uint64_t lm = ballot(nb); lm; lm &= lm - 1) {
+            const int L = __ffsll(static_cast<unsigned long long>(lm)) - 1;
+            const bool reach = cell_reaches_point<D>(a.xs, a.n, j, -a.prim_cnt[rk], readlane_f(q.x, L),
+                                                     readlane_f(q.y, L), readlane_f(q.z, L), eps2);
+            if (lane == L && reach) root = uf_union(labels, root, j, a.info);
+          }
+        }
+        return false;
+      });
+      return;
+    }
+  }
   Walk w;
   walk_init<true>(w, m, sc, p, mine);
   bool active = mine && !walk_done(w);
@@ -1107,35 +1278,55 @@ __global__ __launch_bounds__(256) void k_main_dbx_cells_wave(TravArgs a) {
     const float eps2 = sc.eps2;
     const float4 alo4 = a.prim_lo[A], ahi4 = a.prim_hi[A];
     const float alo[3] = {alo4.x, alo4.y, alo4.z}, ahi[3] = {ahi4.x, ahi4.y, ahi4.z};
-    int root = sa;
-    traverse_box_wide<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, stack, [&](int r0, int r1) {
-      for (int r = r0; r <= r1; ++r) {
-        const float4 lr = a.prim_lo[r];
-        if (rec_index(lr) >= 0) {
-          const int j = rec_index(lr);
-          const float px = lr.x, py = lr.y, pz = lr.z;
-          if (box_dist2<D>(px, py, pz, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) > eps2) continue;
-          const bool cj = ALL_CORE || a.core[j];
-          if (cj) {
-            if (known_same_set(labels, j, root)) continue;
+    // the core pass may already have joined A to other sets
+    int root = uf_find(labels, sa, a.info);
+    traverse_box_wide_lanes<D>(a.t, m, sc, alo, ahi, A, a.t.leaf_size, a.info, stack, [&](int r) {
+      // every lane loads its primitive's record and what decides a skip (core
+      // flag, an ancestor near the root); candidates then go one after another
+      float4 lr = make_float4(0.0f, 0.0f, 0.0f, 0.0f), hr = lr;
+      bool hit = false, cj = false;
+      int anc = -1;
+      if (r >= 0) {
+        lr = a.prim_lo[r];
+        const int v = rec_index(lr);
+        if (v >= 0) {
+          hit = box_dist2<D>(lr.x, lr.y, lr.z, alo[0], alo[1], alo[2], ahi[0], ahi[1], ahi[2]) <= eps2;
+        } else {
+          hr = a.prim_hi[r];
+          hit = boxbox_dist2<D>(alo, ahi, lr.x, lr.y, lr.z, hr.x, hr.y, hr.z) <= eps2;
+        }
+        if (hit) {
+          const int j = ref_point(v);
+          cj = v < 0 || ALL_CORE || a.core[j];  // dense cells are core
+          anc = cj ? ancestor_of(labels, j) : labels[j];
+        }
+      }
+      for (uint64_t vm = ballot(hit && !(cj && anc == root)); vm; vm &= vm - 1) {
+        const int k = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+        const int v = __builtin_amdgcn_readlane(rec_index(lr), k);
+        const int j = ref_point(v);
+        const int ak = __builtin_amdgcn_readlane(anc, k);
+        const float px = readlane_f(lr.x, k), py = readlane_f(lr.y, k), pz = readlane_f(lr.z, k);
+        if (v >= 0) {
+          if (__builtin_amdgcn_readlane(static_cast<int>(cj), k)) {
+            if (ak == root || known_same_set(labels, j, root)) continue;
             if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2)) {
               int nr = 0;
               if (lane == 0) nr = uf_union(labels, root, j, a.info);
               root = __shfl(nr, 0);
             }
           } else if (FIRST) {
-            if (labels[j] != j) continue;
+            if (ak != j || labels[j] != j) continue;  // claimed already (claims are final)
             if (cell_reaches_point<D>(a.xs, a.n, sa, na, px, py, pz, eps2) && lane == 0) uf_claim(labels, j, sa);
           }
           continue;
         }
-        const int s = ref_point(rec_index(lr));
-        const float4 blo = lr, bhi = a.prim_hi[r];
-        if (boxbox_dist2<D>(alo, ahi, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) > eps2) continue;
-        if (known_same_set(labels, s, root)) continue;
-        if (cells_touch<D>(a.xs, a.n, sa, na, s, -a.prim_cnt[r], blo, bhi, eps2)) {
+        if (ak == root || known_same_set(labels, j, root)) continue;
+        const float4 blo = make_float4(px, py, pz, 0.0f);
+        const float4 bhi = make_float4(readlane_f(hr.x, k), readlane_f(hr.y, k), readlane_f(hr.z, k), 0.0f);
+        if (cells_touch<D>(a.xs, a.n, sa, na, j, -a.prim_cnt[__builtin_amdgcn_readlane(r, k)], blo, bhi, eps2)) {
           int nr = 0;
-          if (lane == 0) nr = uf_union(labels, root, s, a.info);
+          if (lane == 0) nr = uf_union(labels, root, j, a.info);
           root = __shfl(nr, 0);
         }
       }
@@ -1317,7 +1508,9 @@ void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
       if (max_cells > kCellsPerWaveMax)
         hipLaunchKernelGGL((k_main_dbx_cells_lane<D, ALL, FIRST, B>), grid_of(max_cells, a.block), b, 0, s, a);
     }
-    if (part != 1) hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST, B>), g, b, 0, s, a);
+    if (part != 1)
+      hipLaunchKernelGGL((k_main_dbx_points<D, ALL, FIRST, B>), g, b, sizeof(uint32_t) * kWideStack * (a.block / 64), s,
+                         a);
   } else if (FIRST) {
     hipLaunchKernelGGL((k_main_fdb_first<D, B>), g, b, 0, s, a);
   } else {
