@@ -31,7 +31,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.algo = algo;
   p.num_clouds = num_clouds;
   const size_t N = static_cast<size_t>(n > 0 ? n : 1);
-  p.sort_tiles = ceil_div(static_cast<int64_t>(N), kSortTile);
+  p.sort_tiles = ceil_div(static_cast<int64_t>(N), kSortTileMin);
   p.scan_blocks = ceil_div(static_cast<int64_t>(N), kScanTile);
   size_t off = 0;
   auto take = [&](size_t bytes) {

@@ -5,9 +5,10 @@
 //
 // Design (single-pass per digit, after Merrill & Adinets' "onesweep"): one
 // kernel builds the histograms of every pass at once; then each pass is a
-// single kernel in which a workgroup ranks a 4096-key tile with wavefront
-// ballots, learns its global offsets by a decoupled look-back over earlier
-// tiles, and scatters through LDS so that writes are contiguous per digit.
+// single kernel in which a workgroup ranks a tile (5120 32-bit or 6144 64-bit
+// keys) with wavefront ballots, learns its global offsets by a decoupled
+// look-back over earlier tiles (four status words per round trip), and
+// scatters through LDS so that writes are contiguous per digit.
 // Tiles are numbered in the order workgroups start (an atomic ticket), so a
 // tile only waits on tiles already running.
 #include "fdb_device.hpp"
@@ -90,8 +91,9 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K* __restrict__ kin, 
                                                      int shift, uint32_t epoch, const uint32_t* __restrict__ digoff,
                                                      uint32_t* __restrict__ tilectr, uint64_t* __restrict__ status,
                                                      uint32_t* __restrict__ info) {
-  constexpr int kItems = kSortItems;
-  constexpr int kTile = kSortTile;
+  constexpr int kItems = sort_items<K>();
+  constexpr int kTile = 256 * kItems;
+  static_assert(kTile >= kSortTileMin, "the workspace sizes the status words for kSortTileMin");
   constexpr int kWaveTile = 64 * kItems;
   __shared__ uint32_t s_tile;
   __shared__ uint32_t s_wcnt[kWaves][kRadix];  // per-wave digit counts, then per-wave prefixes
@@ -153,20 +155,30 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(const K* __restrict__ kin, 
     st_agent64(st, pack_status(epoch, kFlagAgg, total));
     int spins = 0;
     for (int64_t j = tile - 1; j >= 0;) {
-      uint64_t v = ld_agent64(status + j * kRadix + d);
-      if (static_cast<uint32_t>(v >> 34) != epoch) {
-        // earlier tiles are running and publish without waiting; the cap only
-        // turns a broken invariant into an error instead of a hang
+      // four predecessors per round trip
+      uint64_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = j - u >= 0 ? ld_agent64(status + (j - u) * kRadix + d) : 0;
+      bool done = false, wait = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (done || wait || j < 0) continue;
+        if (static_cast<uint32_t>(v[u] >> 34) != epoch) {
+          wait = true;
+          continue;
+        }
+        excl += static_cast<uint32_t>(v[u]);
+        if (((v[u] >> 32) & 3u) == kFlagIncl) done = true;
+        else --j;
+      }
+      if (done) break;
+      if (wait) {
         if (++spins > (1 << 24)) {
           atomicOr(info, kInternalBit);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += static_cast<uint32_t>(v);
-      if (((v >> 32) & 3u) == kFlagIncl) break;
-      --j;
     }
     st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
   }
@@ -206,7 +218,7 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
                  hipStream_t s) {
   const int passes = (bits + 7) / 8;
   if (n <= 1 || passes == 0) return 0;
-  const int64_t tiles = ceil_div(n, kSortTile);
+  const int64_t tiles = ceil_div(n, 256 * sort_items<K>());
   fill_u32(tilectr, 0, passes, s);
   fill_u32(reinterpret_cast<uint32_t*>(status), 0, tiles * kRadix * 2, s);
   if (!hist_ready) {
