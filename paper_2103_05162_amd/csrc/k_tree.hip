@@ -175,16 +175,27 @@ __device__ __forceinline__ Box load_node_buf(__amdgpu_buffer_rsrc_t r, int k) {
 
 // Bottom-up refit: each leaf walks towards the root; at every internal node the
 // second of the two arriving threads merges its box with the sibling's and
-// continues upwards, so every box is the exact min/max of its leaves.
+// continues upwards, so every box is the exact min/max of its leaves. A node
+// whose leaves all belong to this workgroup's 256 (its index then lies among
+// them too) is met in LDS: each arriver leaves its box in the slot of its side
+// and counts itself with a workgroup-scope atomic. Only nodes spanning
+// workgroups take the device-scope protocol, so most arrivals never leave the CU.
 template <int D, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
                                                   int64_t n,
                                                   LeafSrc ls, const int* __restrict__ other, const int* __restrict__ gamma,
                                                   const int* __restrict__ parent, int* __restrict__ flags,
                                                   float4* node_a, float4* node_b, uint32_t* __restrict__ info) {
+  __shared__ int s_arrive[kBlock];
+  __shared__ float s_side[2][6][kBlock];  // [child side][lo.xyz, hi.xyz][node - first leaf]
   const int m = d_m ? *d_m : m_cap;
-  int l = blockIdx.x * kBlock + threadIdx.x;
-  if (m < 2 || l >= m) return;
+  const int L0 = blockIdx.x * kBlock;
+  if (m < 2 || L0 >= m) return;  // whole workgroup
+  s_arrive[threadIdx.x] = 0;
+  __syncthreads();
+  const int L1 = min(L0 + kBlock, m) - 1;  // this workgroup's leaves are [L0, L1]
+  const int l = L0 + static_cast<int>(threadIdx.x);
+  if (l >= m) return;
   const __amdgpu_buffer_rsrc_t rb =
       __builtin_amdgcn_make_buffer_rsrc(node_a, 0, BUF ? m_cap * (16 * kNodeStride) : 0, kBufferWord3);
   Box box = leaf_box<D>(l, xs, n, ls);
@@ -196,8 +207,6 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
       atomicOr(info, kInternalBit);
       return;
     }
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's node stores have landed
-    if (atomicAdd(flags + p, 1) == 0) return;
     const int o = other[p], g = gamma[p];
     const int first = o < p ? o : p, last = o > p ? o : p;
     if (first < 0 || last >= m || g < first || g >= last) {
@@ -207,11 +216,28 @@ __global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restri
     const bool left_leaf = first == g, right_leaf = last == g + 1;
     const bool came_left = prev == g && prev_leaf == left_leaf;
     Box sib;
-    if (came_left)
-      sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls)
-                       : (BUF ? load_node_buf(rb, g + 1) : load_node(node_a, node_b, g + 1));
-    else
-      sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : (BUF ? load_node_buf(rb, g) : load_node(node_a, node_b, g));
+    if (first >= L0 && last <= L1) {
+      const int slot = p - L0, side = came_left ? 0 : 1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s_side[side][k][slot] = box.lo[k];
+        s_side[side][3 + k][slot] = box.hi[k];
+      }
+      if (__hip_atomic_fetch_add(&s_arrive[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) return;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sib.lo[k] = s_side[side ^ 1][k][slot];
+        sib.hi[k] = s_side[side ^ 1][3 + k][slot];
+      }
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's node stores have landed
+      if (atomicAdd(flags + p, 1) == 0) return;
+      if (came_left)
+        sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls)
+                         : (BUF ? load_node_buf(rb, g + 1) : load_node(node_a, node_b, g + 1));
+      else
+        sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : (BUF ? load_node_buf(rb, g) : load_node(node_a, node_b, g));
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       box.lo[k] = fminf(box.lo[k], sib.lo[k]);
