@@ -176,24 +176,26 @@ __device__ __forceinline__ Box load_node_buf(__amdgpu_buffer_rsrc_t r, int k) {
 // Bottom-up refit: each leaf walks towards the root; at every internal node the
 // second of the two arriving threads merges its box with the sibling's and
 // continues upwards, so every box is the exact min/max of its leaves. A node
-// whose leaves all belong to this workgroup's 256 (its index then lies among
+// whose leaves all belong to this workgroup's kRefitBlock (its index then lies among
 // them too) is met in LDS: each arriver leaves its box in the slot of its side
 // and counts itself with a workgroup-scope atomic. Only nodes spanning
 // workgroups take the device-scope protocol, so most arrivals never leave the CU.
+constexpr int kRefitBlock = 256;  // leaves per workgroup of the refit
+
 template <int D, bool BUF>
-__global__ __launch_bounds__(kBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
+__global__ __launch_bounds__(kRefitBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
                                                   int64_t n,
                                                   LeafSrc ls, const int* __restrict__ other, const int* __restrict__ gamma,
                                                   const int* __restrict__ parent, int* __restrict__ flags,
                                                   float4* node_a, float4* node_b, uint32_t* __restrict__ info) {
-  __shared__ int s_arrive[kBlock];
-  __shared__ float s_side[2][6][kBlock];  // [child side][lo.xyz, hi.xyz][node - first leaf]
+  __shared__ int s_arrive[kRefitBlock];
+  __shared__ float s_side[2][6][kRefitBlock];  // [child side][lo.xyz, hi.xyz][node - first leaf]
   const int m = d_m ? *d_m : m_cap;
-  const int L0 = blockIdx.x * kBlock;
+  const int L0 = blockIdx.x * kRefitBlock;
   if (m < 2 || L0 >= m) return;  // whole workgroup
   s_arrive[threadIdx.x] = 0;
   __syncthreads();
-  const int L1 = min(L0 + kBlock, m) - 1;  // this workgroup's leaves are [L0, L1]
+  const int L1 = min(L0 + kRefitBlock, m) - 1;  // this workgroup's leaves are [L0, L1]
   const int l = L0 + static_cast<int>(threadIdx.x);
   if (l >= m) return;
   const __amdgpu_buffer_rsrc_t rb =
@@ -267,18 +269,19 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
   hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
   if (m_cap >= 2) {
     const bool buf = m_cap <= kRefitBufMaxNodes;
+    const dim3 rg(static_cast<unsigned>(ceil_div(m_cap, kRefitBlock))), rb(kRefitBlock);
     if (dim == 3 && buf)
-      hipLaunchKernelGGL((k_refit<3, true>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
-                         parent, flags, node_a, node_b, info);
+      hipLaunchKernelGGL((k_refit<3, true>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
+                         node_a, node_b, info);
     else if (dim == 3)
-      hipLaunchKernelGGL((k_refit<3, false>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
-                         parent, flags, node_a, node_b, info);
+      hipLaunchKernelGGL((k_refit<3, false>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
+                         node_a, node_b, info);
     else if (buf)
-      hipLaunchKernelGGL((k_refit<2, true>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
-                         parent, flags, node_a, node_b, info);
+      hipLaunchKernelGGL((k_refit<2, true>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
+                         node_a, node_b, info);
     else
-      hipLaunchKernelGGL((k_refit<2, false>), dim3(g), dim3(kBlock), 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma,
-                         parent, flags, node_a, node_b, info);
+      hipLaunchKernelGGL((k_refit<2, false>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
+                         node_a, node_b, info);
   }
 }
 
