@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="HBM budget of the served batches")
     ap.add_argument("--pool-per-dim", type=int, default=32, help="resident clouds per dimension")
+    ap.add_argument("--ooc-budget-gib", type=float, default=6.0,
+                    help="device budget of the out-of-core batched leg (0 = skip it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (PMC calibration)")
     return ap.parse_args()
@@ -103,7 +105,7 @@ def time_algo(fdb, h, pts, eps, min_pts, algo, steps, warmup, leaf, block):
     return dict(ms=ms, k=k, stages=per_call, info=h.last_info(), sizes=h.last_counts())
 
 
-def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
+def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes, ooc_budget=0):
     """Batched clustering of many uneven 3D clouds (each with its own eps and minPts)
     in one call, against the same clouds clustered one call at a time."""
     import torch
@@ -138,6 +140,25 @@ def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     stages, calls = h.stage_times()
     h.set_timing(False)
+    ooc = None
+    if ooc_budget > 0:
+        # the same batch held in pinned host memory, clustered inside a device budget
+        # smaller than the batch needs (copies over PCIe included)
+        pts_h = pts.cpu().pin_memory()
+        lab_h = torch.empty(n, dtype=torch.int32).pin_memory()
+        core_h = torch.empty(n, dtype=torch.uint8).pin_memory()
+        k_h = np.empty(num_clouds, np.int32)
+        okw = dict(algo=algo, handle=h, labels=lab_h, is_core=core_h, num_clusters=k_h)
+        fdb.dbscan_batched_host(pts_h, offs, eps, mp, ooc_budget, **okw)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fdb.dbscan_batched_host(pts_h, offs, eps, mp, ooc_budget, **okw)
+        ooc_ms = (time.perf_counter() - t0) * 1e3 / steps
+        same = bool(torch.equal(lab_h, labels.cpu()) and torch.equal(core_h, core.cpu()) and
+                    np.array_equal(k_h, ncl.cpu().numpy()))
+        ooc = dict(ms=ooc_ms, budget=ooc_budget, identical=same,
+                   need=fdb.workspace_bytes_batched(n, num_clouds, 3, algo) + n * 17 + num_clouds * 20)
+        del pts_h, lab_h, core_h
     # one call per cloud, outputs written in place, one workspace sized for the largest cloud
     opt = fdb.make_options(algo)
     lws = torch.empty(fdb.workspace_bytes(int(sizes.max()), 3, algo), dtype=torch.uint8, device=dev)
@@ -153,7 +174,7 @@ def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
                          wp, wsz)
 
     if loop_passes <= 0:
-        return dict(ms=ms, loop_ms=None, n=n, identical=None, info=info,
+        return dict(ms=ms, loop_ms=None, n=n, identical=None, info=info, ooc=ooc,
                     stages={k2: v / max(calls, 1) for k2, v in stages.items()}, clusters=int(ncl.sum().item()))
     loop()
     torch.cuda.synchronize()
@@ -163,7 +184,7 @@ def time_batched(fdb, h, algo, steps, warmup, num_clouds, loop_passes):
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - t0) * 1e3 / loop_passes
     same = bool(torch.equal(labels, lab2) and torch.equal(core, core2))
-    return dict(ms=ms, loop_ms=loop_ms, n=n, identical=same, info=info,
+    return dict(ms=ms, loop_ms=loop_ms, n=n, identical=same, info=info, ooc=ooc,
                 stages={k2: v / max(calls, 1) for k2, v in stages.items()},
                 clusters=int(ncl.sum().item()))
 
@@ -413,7 +434,8 @@ def main():
         del pts
         torch.cuda.empty_cache()
         log(f"[bench] batched leg ({args.batched_algo})")
-        b = time_batched(fdb, h, args.batched_algo, args.steps, args.warmup, args.clouds, args.loop_passes)
+        b = time_batched(fdb, h, args.batched_algo, args.steps, args.warmup, args.clouds, args.loop_passes,
+                         int(args.ooc_budget_gib * (1 << 30)))
         log(f"[bench] batched: {b['ms']:.2f} ms per batch, loop {b['loop_ms']} ms, identical={b['identical']}")
         for st, v in sorted(b["stages"].items(), key=lambda kv: -kv[1]):
             log(f"    {st:12s} {v:9.3f} ms")
@@ -428,6 +450,17 @@ def main():
             "speedup_vs_loop": round(b["loop_ms"] / b["ms"], 3) if b["loop_ms"] else None,
             "identical_to_loop": b["identical"], "clusters": b["clusters"], "info": b["info"],
             "stages_ms": {k2: round(v, 4) for k2, v in b["stages"].items()}}
+        if b["ooc"]:
+            o = b["ooc"]
+            log(f"[bench] out-of-core: {o['ms']:.2f} ms per batch in {o['budget'] >> 20} MiB, identical={o['identical']}")
+            out["batched"]["out_of_core"] = {
+                "workload": "the same batch in pinned host memory, clustered in groups of whole clouds inside a "
+                            "device budget below what the batch needs (host-to-device and back included)",
+                "device_budget_gib": round(o["budget"] / (1 << 30), 3),
+                "device_bytes_in_core_gib": round(o["need"] / (1 << 30), 3),
+                "ms_per_batch": round(o["ms"], 3), "clouds_per_s": round(args.clouds / (o["ms"] / 1e3), 1),
+                "mpts_per_s": round(b["n"] / (o["ms"] / 1e3) / 1e6, 3),
+                "identical_to_in_core": o["identical"]}
     if args.served_algo != "none":
         log(f"[bench] served leg ({args.served_algo})")
         out["served"] = time_served(fdb, args.served_algo, args.requests, args.rate, args.budget_gib,

@@ -166,6 +166,38 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
                               const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
                               void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * Out-of-core batch (Section 6 names a batched mode for data and index that do
+ * not fit in GPU memory): the clouds stay in host memory and may add up to more
+ * than HBM holds. They are clustered in groups of consecutive whole clouds, each
+ * group one fdb_dbscan_batched call inside device_budget_bytes: two group slots,
+ * so the input copy of one group runs while the previous group is clustered (on
+ * a second stream), and results are copied back as groups finish. Every cloud's
+ * labels, is_core and K are those fdb_dbscan_batched gives (so those of
+ * fdb_dbscan for the cloud alone). Synchronous: returns when all results are in
+ * the caller's host buffers.
+ *   h_points         host float32, row-major [offsets[num_clouds]][dim]. Pinned
+ *                    (page-locked) buffers let copies overlap the clustering;
+ *                    pageable ones work, with the copies serialised.
+ *   h_offsets        host int64 [num_clouds+1]: offsets[0] = 0, nondecreasing
+ *                    (else FDB_ERR_INVALID); the total may exceed 2^30, each cloud
+ *                    stays below 2^30 points.
+ *   h_eps, h_min_pts host float32 / int32 [num_clouds], as in fdb_dbscan_batched
+ *                    (a cloud with bad values gets K = -1).
+ *   device_budget_bytes  device memory the call may allocate (two slots of half
+ *                    the budget each, freed before returning). A cloud whose
+ *                    batched workspace and buffers exceed half the budget gives
+ *                    FDB_ERR_NOMEM, before any work.
+ *   h_labels         host int32 [total] out; h_is_core host uint8 [total] or NULL;
+ *   h_num_clusters   host int32 [num_clouds] out (K, or -1 as in fdb_dbscan_batched).
+ * Returns FDB_ERR_INTERNAL if a kernel's consistency check failed in any group;
+ * afterwards fdb_last_info reports the bits of all groups together.
+ */
+fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const int64_t* h_offsets,
+                                   int32_t num_clouds, int32_t dim, const float* h_eps, const int32_t* h_min_pts,
+                                   const fdb_options* opt, size_t device_budget_bytes, int32_t* h_labels,
+                                   uint8_t* h_is_core, int32_t* h_num_clusters);
+
 /* Wait for the stream of the last fdb_dbscan call on h and return its FDB_INFO_* bits. */
 fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info);
 

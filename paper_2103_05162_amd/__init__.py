@@ -11,7 +11,7 @@ from ._lib import (FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS, FDB_INFO_DENSEBOX
                    FDB_INFO_NONFINITE, FdbError,
                    Handle, Server, load, make_options, status_string, workspace_bytes, workspace_bytes_batched)
 
-__all__ = ["dbscan", "dbscan_batched", "Handle", "Server", "FdbError", "workspace_bytes", "workspace_bytes_batched",
+__all__ = ["dbscan", "dbscan_batched", "dbscan_batched_host", "Handle", "Server", "FdbError", "workspace_bytes", "workspace_bytes_batched",
            "default_handle", "load", "make_options", "status_string", "FDB_INFO_DENSEBOX_FALLBACK",
            "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL", "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN"]
 
@@ -111,3 +111,49 @@ def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border:
                          labels.data_ptr() if n else 0, is_core.data_ptr() if n else 0, num_clusters.data_ptr(),
                          stream, opt, ws_ptr, ws_size)
     return labels, is_core.view(torch.bool), num_clusters
+
+
+def dbscan_batched_host(points, offsets, eps, min_pts, budget_bytes: int, algo: str = "densebox",
+                        border: str = "canonical", leaf_size: int = 0, block_size: int = 0, device: int = 0,
+                        handle: Handle | None = None, labels=None, is_core=None, num_clusters=None):
+    """Cluster a batch of clouds held in host memory, possibly more than fits on the
+    device, within budget_bytes of device memory (groups of whole clouds, input
+    copies overlapping the clustering of the previous group). Synchronous.
+
+    points: [N, d] float32 host array (numpy or CPU torch tensor; pinned memory
+    lets the copies overlap); offsets int64 [B+1]; eps float32 [B]; min_pts int32
+    [B]. Returns (labels int32 [N], is_core uint8 [N], num_clusters int32 [B]) as
+    numpy arrays (or the caller's own host buffers, filled), equal to what
+    dbscan_batched gives for the same clouds.
+    """
+    import numpy as np
+
+    def host(a, dtype):
+        if hasattr(a, "numpy"):  # torch tensor
+            if a.device.type != "cpu":
+                raise TypeError("dbscan_batched_host takes host (CPU) arrays")
+            a = a.numpy()
+        a = np.asarray(a)
+        if a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+            raise ValueError(f"expected a contiguous {np.dtype(dtype).name} array")
+        return a
+
+    pts = host(points, np.float32)
+    if pts.ndim != 2 or pts.shape[1] not in (2, 3):
+        raise ValueError("points must have shape [N, 2] or [N, 3]")
+    offs, e, mp = host(offsets, np.int64), host(eps, np.float32), host(min_pts, np.int32)
+    b = offs.shape[0] - 1
+    if b < 1 or e.shape[0] != b or mp.shape[0] != b or offs[-1] != pts.shape[0]:
+        raise ValueError("offsets must be [B+1] ending at N; eps and min_pts [B]")
+    n = pts.shape[0]
+    lab = np.empty(n, dtype=np.int32) if labels is None else host(labels, np.int32)
+    core = np.empty(n, dtype=np.uint8) if is_core is None else host(is_core, np.uint8)
+    k = np.empty(b, dtype=np.int32) if num_clusters is None else host(num_clusters, np.int32)
+    if lab.shape[0] < n or core.shape[0] < n or k.shape[0] < b:
+        raise ValueError("output buffers too small")
+    h = handle if handle is not None else default_handle(device)
+    opt = make_options(algo, border, leaf_size, block_size)
+    h.dbscan_batched_host_raw(pts.ctypes.data if n else 0, offs.ctypes.data, b, pts.shape[1], e.ctypes.data,
+                              mp.ctypes.data, int(budget_bytes), lab.ctypes.data if n else 0,
+                              core.ctypes.data if n else 0, k.ctypes.data, opt)
+    return lab, core, k

@@ -83,6 +83,9 @@ def load() -> ctypes.CDLL:
     lib.fdb_dbscan_batched.argtypes = [vp, vp, i64, vp, i32, i32, vp, vp, ctypes.POINTER(FdbOptions), vp, vp, vp, vp,
                                        sz, vp]
     lib.fdb_dbscan_batched.restype = ctypes.c_int
+    lib.fdb_dbscan_batched_host.argtypes = [vp, vp, vp, i32, i32, vp, vp, ctypes.POINTER(FdbOptions), sz, vp, vp,
+                                            vp]
+    lib.fdb_dbscan_batched_host.restype = ctypes.c_int
     lib.fdb_last_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.fdb_last_info.restype = ctypes.c_int
     lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
@@ -191,6 +194,18 @@ class Handle:
                                           vp(num_clusters_ptr) if num_clusters_ptr else None,
                                           vp(workspace_ptr) if workspace_ptr else None, int(workspace_size), vp(stream))
         _check(st, "fdb_dbscan_batched")
+
+    def dbscan_batched_host_raw(self, points_ptr: int, offsets_ptr: int, num_clouds: int, dim: int, eps_ptr: int,
+                                min_pts_ptr: int, budget_bytes: int, labels_ptr: int, core_ptr: int | None,
+                                num_clusters_ptr: int, options: FdbOptions | None = None) -> None:
+        """fdb_dbscan_batched_host on raw host pointers (synchronous)."""
+        vp = ctypes.c_void_p
+        st = self._lib.fdb_dbscan_batched_host(self.ptr, vp(points_ptr) if points_ptr else None, vp(offsets_ptr),
+                                               int(num_clouds), int(dim), vp(eps_ptr), vp(min_pts_ptr),
+                                               ctypes.byref(options) if options is not None else None,
+                                               int(budget_bytes), vp(labels_ptr) if labels_ptr else None,
+                                               vp(core_ptr) if core_ptr else None, vp(num_clusters_ptr))
+        _check(st, "fdb_dbscan_batched_host")
 
     def last_info(self) -> int:
         v = ctypes.c_uint32(0)

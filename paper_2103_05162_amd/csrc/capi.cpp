@@ -827,4 +827,194 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
 }
 
+
+// ---- out-of-core batches --------------------------------------------------------
+
+namespace {
+
+// Device bytes of one group slot: its batched workspace, points, offsets, eps,
+// minPts, K, labels and core flags.
+size_t ooc_slot_bytes(int64_t n, int32_t b, int dim, int algo) {
+  const fdb::Plan plan = fdb::make_plan(n, dim, algo, b);
+  return fdb::align_up(plan.bytes) + fdb::align_up(size_t(n) * dim * 4) + fdb::align_up(size_t(b + 1) * 8) +
+         3 * fdb::align_up(size_t(b) * 4) + fdb::align_up(size_t(n) * 4) + fdb::align_up(size_t(n));
+}
+
+struct OocSlot {
+  void* base = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  float* pts = nullptr;
+  int64_t* off = nullptr;
+  float* eps = nullptr;
+  int32_t* mp = nullptr;
+  int32_t* k = nullptr;
+  int32_t* lab = nullptr;
+  uint8_t* core = nullptr;
+  int64_t* h_off = nullptr;   // pinned: the group's offsets, rebased to its first point
+  uint32_t* h_info = nullptr; // pinned: the group's FDB_INFO_* bits
+  hipEvent_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+};
+
+}  // namespace
+
+fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const int64_t* h_offsets,
+                                   int32_t num_clouds, int32_t dim, const float* h_eps, const int32_t* h_min_pts,
+                                   const fdb_options* opt, size_t device_budget_bytes, int32_t* h_labels,
+                                   uint8_t* h_is_core, int32_t* h_num_clusters) {
+  using namespace fdb;
+  if (!h || !h_offsets || !h_eps || !h_min_pts || !h_num_clusters || (dim != 2 && dim != 3) || num_clouds < 1 ||
+      num_clouds > (1 << 24))
+    return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o) || h_offsets[0] != 0) return FDB_ERR_INVALID;
+  for (int32_t c = 0; c < num_clouds; ++c)
+    if (h_offsets[c + 1] < h_offsets[c]) return FDB_ERR_INVALID;
+  const int64_t n_total = h_offsets[num_clouds];
+  if (n_total > 0 && (!h_points || !h_labels)) return FDB_ERR_INVALID;
+
+  // Groups of consecutive whole clouds, each filling at most half the budget
+  // (two slots: one group is copied in while the other is clustered).
+  const size_t cap = (device_budget_bytes / 2) & ~size_t(255);
+  std::vector<int32_t> gbeg;
+  int64_t gn = 0, n_max = 0;
+  int32_t b_max = 0;
+  gbeg.push_back(0);
+  for (int32_t c = 0; c < num_clouds; ++c) {
+    const int64_t nc = h_offsets[c + 1] - h_offsets[c];
+    if (nc > kMaxPoints || ooc_slot_bytes(nc, 1, dim, o.algo) > cap) return FDB_ERR_NOMEM;  // a cloud alone
+    const int32_t b = c - gbeg.back();
+    if (b > 0 && (gn + nc > kMaxPoints || b + 1 > (1 << 24) || ooc_slot_bytes(gn + nc, b + 1, dim, o.algo) > cap)) {
+      n_max = std::max(n_max, gn);
+      b_max = std::max(b_max, b);
+      gbeg.push_back(c);
+      gn = 0;
+    }
+    gn += nc;
+  }
+  n_max = std::max(n_max, gn);
+  b_max = std::max(b_max, num_clouds - gbeg.back());
+  gbeg.push_back(num_clouds);
+  const size_t groups = gbeg.size() - 1;
+
+  DeviceGuard guard(h->device);
+  const size_t slot_bytes = ooc_slot_bytes(n_max, b_max, dim, o.algo);
+  const size_t ws_bytes = align_up(make_plan(n_max, dim, o.algo, b_max).bytes);
+  OocSlot slot[2];
+  hipStream_t sc = nullptr, sk = nullptr;  // clustering, copies
+  fdb_status st = FDB_OK;
+  uint32_t info = 0;
+  auto fail = [&](fdb_status e) {
+    if (st == FDB_OK) st = e;
+  };
+  if (hipStreamCreateWithFlags(&sc, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&sk, hipStreamNonBlocking) != hipSuccess)
+    fail(FDB_ERR_HIP);
+  for (int k = 0; k < 2 && st == FDB_OK; ++k) {
+    OocSlot& S = slot[k];
+    if (hipMalloc(&S.base, slot_bytes) != hipSuccess) {
+      S.base = nullptr;
+      fail(FDB_ERR_NOMEM);
+      break;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&S.h_off), size_t(b_max + 1) * 8 + 256, hipHostMallocDefault) !=
+        hipSuccess) {
+      S.h_off = nullptr;
+      fail(FDB_ERR_NOMEM);
+      break;
+    }
+    S.h_info = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(S.h_off) + align_up(size_t(b_max + 1) * 8));
+    *S.h_info = 0;
+    char* q = static_cast<char*>(S.base);
+    auto take = [&](size_t bytes) {
+      char* r = q;
+      q += align_up(bytes);
+      return r;
+    };
+    S.ws = take(ws_bytes);
+    S.ws_bytes = ws_bytes;
+    S.pts = reinterpret_cast<float*>(take(size_t(n_max) * dim * 4));
+    S.off = reinterpret_cast<int64_t*>(take(size_t(b_max + 1) * 8));
+    S.eps = reinterpret_cast<float*>(take(size_t(b_max) * 4));
+    S.mp = reinterpret_cast<int32_t*>(take(size_t(b_max) * 4));
+    S.k = reinterpret_cast<int32_t*>(take(size_t(b_max) * 4));
+    S.lab = reinterpret_cast<int32_t*>(take(size_t(n_max) * 4));
+    S.core = reinterpret_cast<uint8_t*>(take(size_t(n_max)));
+    if (hipEventCreateWithFlags(&S.h2d, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S.comp, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S.d2h, hipEventDisableTiming) != hipSuccess)
+      fail(FDB_ERR_HIP);
+  }
+
+  // Results of group g back to the caller (copy stream, after its clustering).
+  auto copy_out = [&](size_t g) {
+    OocSlot& S = slot[g & 1];
+    const int32_t c0 = gbeg[g], b = gbeg[g + 1] - c0;
+    const int64_t p0 = h_offsets[c0], n = h_offsets[gbeg[g + 1]] - p0;
+    if (hipStreamWaitEvent(sk, S.comp, 0) != hipSuccess) return fail(FDB_ERR_HIP);
+    if ((n > 0 && hipMemcpyAsync(h_labels + p0, S.lab, size_t(n) * 4, hipMemcpyDeviceToHost, sk) != hipSuccess) ||
+        (n > 0 && h_is_core &&
+         hipMemcpyAsync(h_is_core + p0, S.core, size_t(n), hipMemcpyDeviceToHost, sk) != hipSuccess) ||
+        hipMemcpyAsync(h_num_clusters + c0, S.k, size_t(b) * 4, hipMemcpyDeviceToHost, sk) != hipSuccess ||
+        hipEventRecord(S.d2h, sk) != hipSuccess)
+      fail(FDB_ERR_HIP);
+  };
+  for (size_t g = 0; g < groups && st == FDB_OK; ++g) {
+    OocSlot& S = slot[g & 1];
+    if (g >= 2) {  // the slot's previous group has left it
+      if (hipEventSynchronize(S.d2h) != hipSuccess) {
+        fail(FDB_ERR_HIP);
+        break;
+      }
+      info |= *S.h_info;
+    }
+    const int32_t c0 = gbeg[g], b = gbeg[g + 1] - c0;
+    const int64_t p0 = h_offsets[c0], n = h_offsets[gbeg[g + 1]] - p0;
+    for (int32_t c = 0; c <= b; ++c) S.h_off[c] = h_offsets[c0 + c] - p0;
+    if ((n > 0 && hipMemcpyAsync(S.pts, h_points + p0 * dim, size_t(n) * dim * 4, hipMemcpyHostToDevice, sk) !=
+                      hipSuccess) ||
+        hipMemcpyAsync(S.off, S.h_off, size_t(b + 1) * 8, hipMemcpyHostToDevice, sk) != hipSuccess ||
+        hipMemcpyAsync(S.eps, h_eps + c0, size_t(b) * 4, hipMemcpyHostToDevice, sk) != hipSuccess ||
+        hipMemcpyAsync(S.mp, h_min_pts + c0, size_t(b) * 4, hipMemcpyHostToDevice, sk) != hipSuccess ||
+        hipEventRecord(S.h2d, sk) != hipSuccess || hipStreamWaitEvent(sc, S.h2d, 0) != hipSuccess) {
+      fail(FDB_ERR_HIP);
+      break;
+    }
+    const fdb_status r = fdb_dbscan_batched(h, S.pts, n, S.off, b, dim, S.eps, S.mp, &o, S.lab,
+                                            h_is_core ? S.core : nullptr, S.k, S.ws, S.ws_bytes, sc);
+    if (r != FDB_OK) {
+      fail(r);
+      break;
+    }
+    if (hipMemcpyAsync(S.h_info, h->d_info, 4, hipMemcpyDeviceToHost, sc) != hipSuccess ||
+        hipEventRecord(S.comp, sc) != hipSuccess) {
+      fail(FDB_ERR_HIP);
+      break;
+    }
+    // queued behind this group's input copies, so they overlap the previous group's clustering
+    if (g >= 1) copy_out(g - 1);
+  }
+  if (st == FDB_OK && groups > 0) copy_out(groups - 1);
+  if (sc && hipStreamSynchronize(sc) != hipSuccess) fail(FDB_ERR_HIP);
+  if (sk && hipStreamSynchronize(sk) != hipSuccess) fail(FDB_ERR_HIP);
+  if (st == FDB_OK)
+    for (size_t g = groups >= 2 ? groups - 2 : 0; g < groups; ++g) info |= *slot[g & 1].h_info;
+  for (OocSlot& S : slot) {
+    if (S.h2d) (void)hipEventDestroy(S.h2d);
+    if (S.comp) (void)hipEventDestroy(S.comp);
+    if (S.d2h) (void)hipEventDestroy(S.d2h);
+    if (S.h_off) (void)hipHostFree(S.h_off);
+    if (S.base) (void)hipFree(S.base);
+  }
+  if (sc) (void)hipStreamDestroy(sc);
+  if (sk) (void)hipStreamDestroy(sk);
+  // fdb_last_info / fdb_last_counts now describe this call as a whole
+  h->last_stream = nullptr;
+  h->last_misc = nullptr;
+  h->host_info = info;
+  if (st == FDB_OK && (info & FDB_INFO_INTERNAL)) st = FDB_ERR_INTERNAL;
+  return st;
+}
+
 }  // extern "C"

@@ -1145,45 +1145,90 @@ __global__ void k_main_dbx_points(TravArgs a) {
     if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
     if (!ballot(other_cloud) && ext * ext <= kPointsPacketExt * kPointsPacketExt * ps.eps2) {
       const float eps2 = ps.eps2;
+      // Phase A: pairs of this wavefront's own queries (every core point primitive
+      // in its range is a query), each joined from its lower primitive.
+      for (uint64_t km = mm; km; km &= km - 1) {
+        const int kl = __ffsll(static_cast<unsigned long long>(km)) - 1;
+        const int jk = __shfl(i, kl);
+        const float px = readlane_f(q.x, kl), py = readlane_f(q.y, kl), pz = readlane_f(q.z, kl);
+        if (mine && lane < kl && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 && !known_same_set(labels, jk, root))
+          root = uf_union(labels, root, jk, a.info);
+      }
+      if (mine) root = uf_find(labels, root, a.info);
+      int r = __shfl(root, fl);
+      bool common = !ballot(mine && root != r);
+      const int plast = __shfl(p, 63);  // point primitives up to here are this wavefront's (phase A)
       uint32_t* stack = s_pstack + (threadIdx.x >> 6) * kWideStack;
-      traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, p0, a.t.leaf_size, a.info, stack, [&](int r) {
+      traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, p0, a.t.leaf_size, a.info, stack, [&](int rr) {
         float4 lr = make_float4(0.0f, 0.0f, 0.0f, 0.0f), hr = lr;
         bool hit = false;
         int anc = -1;
-        if (r >= 0) {
-          lr = a.prim_lo[r];
+        if (rr >= 0) {
+          lr = a.prim_lo[rr];
           const int v = rec_index(lr);
           if (v >= 0) {
-            hit = (ALL_CORE || a.core[v]) &&
+            hit = rr > plast && (ALL_CORE || a.core[v]) &&
                   box_dist2<D>(lr.x, lr.y, lr.z, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]) <= eps2;
           } else {
-            hr = a.prim_hi[r];
+            hr = a.prim_hi[rr];
             hit = boxbox_dist2<D>(lo, hi, lr.x, lr.y, lr.z, hr.x, hr.y, hr.z) <= eps2;
           }
           if (hit) anc = ancestor_of(labels, ref_point(v));
         }
-        for (uint64_t vm = ballot(hit); vm; vm &= vm - 1) {
+        const bool is_pt = rec_index(lr) >= 0;
+        if (common) {
+          // Points, all at once: every lane tests its own candidate against all
+          // queries (register broadcasts), then the lanes that reach one join
+          // the packet's set in parallel.
+          const bool cand = hit && is_pt && anc != r;
+          if (ballot(cand)) {
+            bool reach = false;
+            for (uint64_t qm = mm; qm; qm &= qm - 1) {
+              const int kl = __ffsll(static_cast<unsigned long long>(qm)) - 1;
+              reach |= cand && dist2v<D>(lr.x, lr.y, lr.z, readlane_f(q.x, kl), readlane_f(q.y, kl),
+                                         readlane_f(q.z, kl)) <= eps2;
+            }
+            if (ballot(reach)) {
+              if (reach && !known_same_set(labels, rec_index(lr), r)) uf_union(labels, r, rec_index(lr), a.info);
+              int nr = 0;
+              if (lane == fl) nr = uf_find(labels, r, a.info);
+              r = __shfl(nr, fl);
+              root = r;
+            }
+          }
+        }
+        // cells, and points when the queries are in several sets: one at a time
+        for (uint64_t vm = ballot(hit && !(common && (is_pt || anc == r))); vm; vm &= vm - 1) {
           const int k = __ffsll(static_cast<unsigned long long>(vm)) - 1;
-          const int rk = __builtin_amdgcn_readlane(r, k);
+          const int rk = __builtin_amdgcn_readlane(rr, k);
           const int v = __builtin_amdgcn_readlane(rec_index(lr), k);
           const int j = ref_point(v);
           const int ak = __builtin_amdgcn_readlane(anc, k);
           const float px = readlane_f(lr.x, k), py = readlane_f(lr.y, k), pz = readlane_f(lr.z, k);
-          if (v >= 0) {  // a core point
-            if (mine && rk > p && ak != root && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 &&
-                !known_same_set(labels, j, root))
+          if (common && ak == r) continue;  // joined by an earlier candidate of this walk
+          if (v >= 0) {  // a core point above every query of the wavefront (queries in several sets)
+            if (mine && ak != root && dist2v<D>(px, py, pz, q.x, q.y, q.z) <= eps2 && !known_same_set(labels, j, root))
               root = uf_union(labels, root, j, a.info);
             continue;
           }
-          // a dense cell: one of its points within eps of the query suffices
+          // a dense cell: one of its points within eps of a query suffices
           const float ux = readlane_f(hr.x, k), uy = readlane_f(hr.y, k), uz = readlane_f(hr.z, k);
-          const bool nb = mine && rk > p && ak != root &&
+          const bool nb = mine && rk > p && (common || ak != root) &&
                           box_dist2<D>(q.x, q.y, q.z, px, py, pz, ux, uy, uz) <= eps2 &&
-                          !known_same_set(labels, j, root);
+                          (common || !known_same_set(labels, j, root));
+          if (common && ballot(nb) && known_same_set(labels, j, r)) continue;
           for (uint64_t lm = ballot(nb); lm; lm &= lm - 1) {
             const int L = __ffsll(static_cast<unsigned long long>(lm)) - 1;
             const bool reach = cell_reaches_point<D>(a.xs, a.n, j, -a.prim_cnt[rk], readlane_f(q.x, L),
                                                      readlane_f(q.y, L), readlane_f(q.z, L), eps2);
+            if (common) {
+              if (!reach) continue;
+              int nr = 0;
+              if (lane == L) nr = uf_union(labels, r, j, a.info);
+              r = __shfl(nr, L);
+              root = r;
+              break;  // the whole packet is in one set with the cell now
+            }
             if (lane == L && reach) root = uf_union(labels, root, j, a.info);
           }
         }

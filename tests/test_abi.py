@@ -97,3 +97,18 @@ def test_batched_and_server_arguments_are_checked_before_any_gpu_call():
     assert lib.fdb_server_poll(None, 0, None) == _lib.FDB_ERR_INVALID
     assert lib.fdb_server_drain(None) == _lib.FDB_ERR_INVALID
     lib.fdb_server_destroy(None)
+
+
+def test_out_of_core_arguments_are_checked_before_any_gpu_call():
+    import numpy as np
+    from paper_2103_05162_amd import _lib
+    lib = _lib.load()
+    offs = np.array([0, 3, 5], np.int64)
+    eps = np.array([0.1, 0.1], np.float32)
+    mp = np.array([2, 2], np.int32)
+    pts = np.zeros((5, 3), np.float32)
+    lab = np.zeros(5, np.int32)
+    k = np.zeros(2, np.int32)
+    args = [pts.ctypes.data, offs.ctypes.data, 2, 3, eps.ctypes.data, mp.ctypes.data, None, 1 << 30,
+            lab.ctypes.data, None, k.ctypes.data]
+    assert lib.fdb_dbscan_batched_host(None, *args) == _lib.FDB_ERR_INVALID  # no handle
