@@ -318,7 +318,8 @@ def roofline(algo, stages, n, sizes, golden, traffic_db):
         out = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": dom, "ms": round(ms, 4), "alg_bytes": b}
     t = (traffic_db or {}).get(f"{algo}:{dom}")
-    out["traffic"] = t
+    out["traffic"] = t["bytes"] if t else None  # HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)
+    out["traffic_detail"] = t
     return out
 
 

@@ -345,3 +345,23 @@ def test_automatic_choice(dev):
     wide[0] = (1e7, 1e7, 1e7)
     assert_exact(dev, wide, 1e-3, 3, "auto")
     assert h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_isolated_points_and_pairs_at_eps(dev, d):
+    """Isolated points, and pairs at distances a hair inside or outside eps in
+    random directions: core, noise and border decisions must be the oracle's bit
+    for bit (DenseBox with minPts > 2: lone points, records and walks)."""
+    rng = np.random.default_rng(40 + d)
+    eps, n_single, n_pair = (0.03, 3000, 1500) if d == 3 else (0.02, 150, 100)
+    singles = rng.uniform(0, 1, size=(n_single, d))
+    a = rng.uniform(0.05, 0.95, size=(n_pair, d))
+    u = rng.standard_normal((n_pair, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    scale = eps * rng.choice([1 - 1e-6, 1 - 1e-7, 1.0, 1 + 1e-7, 1 + 1e-6, 0.5, 1.5], size=n_pair)
+    pts = np.concatenate([singles, a, a + u * scale[:, None]]).astype(np.float32)
+    rng.shuffle(pts)
+    for mp in (3, 4):
+        ref = assert_exact(dev, pts, eps, mp, "densebox")
+        assert (ref[0] == -1).sum() > len(pts) // 10  # plenty of noise
+        assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
