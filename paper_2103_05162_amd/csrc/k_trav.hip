@@ -347,12 +347,28 @@ __device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m
         }
       }
     }
-    // this step's buckets, round t taking each lane's t-th primitive
-    int len = bs >= 0 ? be - bs + 1 : 0;
-    int rounds = len;
-    for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, __shfl_xor(rounds, off));
-    for (int r = 0; r < rounds; ++r)
-      if (visit_lanes(r < len ? bs + r : -1)) return;
+    // this step's buckets laid end to end over the lanes: slot k of round q is
+    // primitive q*64 + lane of the concatenation, found by a binary search over the
+    // lanes' exclusive prefix sums (the last lane starting at or before it)
+    const int len = bs >= 0 ? be - bs + 1 : 0;
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int excl = incl - len;
+    const int total = __shfl(incl, 63);
+    for (int q = 0; q < total; q += 64) {  // every lane takes part in the shuffles
+      const int slot = q + lane;
+      const int sl = slot < total ? slot : total - 1;
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(excl, lo + step) <= sl) lo += step;
+      const int first = __shfl(bs, lo), ex = __shfl(excl, lo);
+      if (visit_lanes(slot < total ? first + (sl - ex) : -1)) return;
+    }
     const uint64_t m0 = ballot(c0 != kEnd), m1 = ballot(c1 != kEnd);
     const int n0 = __popcll(m0), n1 = __popcll(m1);
     if (top + n0 + n1 <= kWideStack) {
