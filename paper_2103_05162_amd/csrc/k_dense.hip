@@ -100,27 +100,33 @@ __global__ __launch_bounds__(kPushBlock) void k_cell_candidates(const int* __res
   }
 }
 
-// One wavefront per candidate cell: tight box by a wave reduction, then the guard.
-template <int D>
+// Tight box per candidate cell by a reduction over G lanes, then the guard. Two
+// launches share the candidate list: G = 64 (a wavefront per cell) takes the cells
+// of more than kSmallCell points, G = 8 (eight cells per wavefront) the others, so
+// a batch's many small cells do not each hold a whole wavefront.
+constexpr int kSmallCell = 64;
+
+template <int D, int G>
 __global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__ xs, int64_t n,
                                                        const int* __restrict__ cell_start, const int* __restrict__ cand,
                                                        const int* __restrict__ num_cand, float eps2_all,
                                                        CloudParams cp, uint8_t* __restrict__ dense,
                                                        float4* __restrict__ cell_lo, float4* __restrict__ cell_hi) {
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * kBlock) >> 6;
+  const int sub = threadIdx.x & (G - 1);
+  const int grp = (blockIdx.x * kBlock + threadIdx.x) / G;
+  const int ngrp = (gridDim.x * kBlock) / G;
   const int ncand = *num_cand;
-  for (int w = wave; w < ncand; w += nwaves) {
+  for (int w = grp; w < ncand; w += ngrp) {
     const int c = cand[w];
     const int s = cell_start[c], e = cell_start[c + 1];
+    if ((e - s > kSmallCell) != (G == 64)) continue;  // the other launch takes it
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    // four 64-point chunks per trip: their loads are in flight together
-    for (int j0 = s + lane; j0 < e; j0 += 4 * 64) {
+    // four G-point chunks per trip: their loads are in flight together
+    for (int j0 = s + sub; j0 < e; j0 += 4 * G) {
       float v[4][3];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int j = j0 + u * 64;
+        const int j = j0 + u * G;
 #pragma unroll
         for (int k = 0; k < D; ++k) v[u][k] = j < e ? xs[k * n + j] : NAN;
       }
@@ -134,11 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_boxes(const float* __restrict__
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
-      for (int off = 32; off > 0; off >>= 1) {
+      for (int off = G / 2; off > 0; off >>= 1) {  // within the group (its lanes run together)
         lo[k] = fminf(lo[k], __shfl_xor(lo[k], off));
         hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off));
       }
-    if (lane == 0) {
+    if (sub == 0) {
       if (D == 2) lo[2] = hi[2] = 0.0f;
       const float eps2 = cell_eps2(cp, s, eps2_all);
       bool ok = dist2v<D>(hi[0], hi[1], hi[2], lo[0], lo[1], lo[2]) <= eps2;
@@ -236,12 +242,17 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   hipLaunchKernelGGL(k_cell_candidates, dim3(gp), dim3(kPushBlock), 0, s, cell_start, d_cells, min_pts, cp, cand,
                      d_cand, dense);
   const int gb = 2048;  // 8192 wavefronts, grid-stride over candidate cells
-  if (dim == 3)
-    hipLaunchKernelGGL(k_cell_boxes<3>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+  if (dim == 3) {
+    hipLaunchKernelGGL((k_cell_boxes<3, 64>), dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
                        dense, cell_lo, cell_hi);
-  else
-    hipLaunchKernelGGL(k_cell_boxes<2>, dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+    hipLaunchKernelGGL((k_cell_boxes<3, 8>), dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
                        dense, cell_lo, cell_hi);
+  } else {
+    hipLaunchKernelGGL((k_cell_boxes<2, 64>), dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+                       dense, cell_lo, cell_hi);
+    hipLaunchKernelGGL((k_cell_boxes<2, 8>), dim3(gb), dim3(kBlock), 0, s, xs, n, cell_start, cand, d_cand, eps2, cp,
+                       dense, cell_lo, cell_hi);
+  }
   hipLaunchKernelGGL(k_prim_flags, dim3(g), dim3(kBlock), 0, s, cell_id, cell_start, dense, n, pflag);
   int* pidx = cand;  // candidates are no longer needed; reuse for primitive indices
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
