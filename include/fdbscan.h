@@ -179,14 +179,15 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
  *   h_points         host float32, row-major [offsets[num_clouds]][dim]. Pinned
  *                    (page-locked) buffers let copies overlap the clustering;
  *                    pageable ones work, with the copies serialised.
- *   h_offsets        host int64 [num_clouds+1]: offsets[0] = 0, nondecreasing
- *                    (else FDB_ERR_INVALID); the total may exceed 2^30, each cloud
- *                    stays below 2^30 points.
+ *   h_offsets        host int64 [num_clouds+1]: offsets[0] = 0, nondecreasing,
+ *                    each cloud below 2^30 points (else FDB_ERR_INVALID); the
+ *                    total may exceed 2^30.
  *   h_eps, h_min_pts host float32 / int32 [num_clouds], as in fdb_dbscan_batched
  *                    (a cloud with bad values gets K = -1).
- *   device_budget_bytes  device memory the call may allocate (two slots of half
- *                    the budget each, freed before returning). A cloud whose
- *                    batched workspace and buffers exceed half the budget gives
+ *   device_budget_bytes  device memory the call may allocate: two slots, each
+ *                    the largest group's workspace and buffers (at most half the
+ *                    budget), freed before returning. A cloud whose batched
+ *                    workspace and buffers exceed half the budget gives
  *                    FDB_ERR_NOMEM, before any work.
  *   h_labels         host int32 [total] out; h_is_core host uint8 [total] or NULL;
  *   h_num_clusters   host int32 [num_clouds] out (K, or -1 as in fdb_dbscan_batched).

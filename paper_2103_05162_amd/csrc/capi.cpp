@@ -878,29 +878,29 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
   // (two slots: one group is copied in while the other is clustered).
   const size_t cap = (device_budget_bytes / 2) & ~size_t(255);
   std::vector<int32_t> gbeg;
-  int64_t gn = 0, n_max = 0;
+  int64_t gn = 0;
   int32_t b_max = 0;
+  size_t slot_bytes = 0;  // the largest group's footprint; each group is carved from its slot on its own
   gbeg.push_back(0);
   for (int32_t c = 0; c < num_clouds; ++c) {
     const int64_t nc = h_offsets[c + 1] - h_offsets[c];
-    if (nc > kMaxPoints || ooc_slot_bytes(nc, 1, dim, o.algo) > cap) return FDB_ERR_NOMEM;  // a cloud alone
+    if (nc > kMaxPoints) return FDB_ERR_INVALID;
+    if (ooc_slot_bytes(nc, 1, dim, o.algo) > cap) return FDB_ERR_NOMEM;  // a cloud alone does not fit
     const int32_t b = c - gbeg.back();
-    if (b > 0 && (gn + nc > kMaxPoints || b + 1 > (1 << 24) || ooc_slot_bytes(gn + nc, b + 1, dim, o.algo) > cap)) {
-      n_max = std::max(n_max, gn);
+    if (b > 0 && (gn + nc > kMaxPoints || ooc_slot_bytes(gn + nc, b + 1, dim, o.algo) > cap)) {
+      slot_bytes = std::max(slot_bytes, ooc_slot_bytes(gn, b, dim, o.algo));
       b_max = std::max(b_max, b);
       gbeg.push_back(c);
       gn = 0;
     }
     gn += nc;
   }
-  n_max = std::max(n_max, gn);
+  slot_bytes = std::max(slot_bytes, ooc_slot_bytes(gn, num_clouds - gbeg.back(), dim, o.algo));
   b_max = std::max(b_max, num_clouds - gbeg.back());
   gbeg.push_back(num_clouds);
   const size_t groups = gbeg.size() - 1;
 
   DeviceGuard guard(h->device);
-  const size_t slot_bytes = ooc_slot_bytes(n_max, b_max, dim, o.algo);
-  const size_t ws_bytes = align_up(make_plan(n_max, dim, o.algo, b_max).bytes);
   OocSlot slot[2];
   hipStream_t sc = nullptr, sk = nullptr;  // clustering, copies
   fdb_status st = FDB_OK;
@@ -926,21 +926,6 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
     }
     S.h_info = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(S.h_off) + align_up(size_t(b_max + 1) * 8));
     *S.h_info = 0;
-    char* q = static_cast<char*>(S.base);
-    auto take = [&](size_t bytes) {
-      char* r = q;
-      q += align_up(bytes);
-      return r;
-    };
-    S.ws = take(ws_bytes);
-    S.ws_bytes = ws_bytes;
-    S.pts = reinterpret_cast<float*>(take(size_t(n_max) * dim * 4));
-    S.off = reinterpret_cast<int64_t*>(take(size_t(b_max + 1) * 8));
-    S.eps = reinterpret_cast<float*>(take(size_t(b_max) * 4));
-    S.mp = reinterpret_cast<int32_t*>(take(size_t(b_max) * 4));
-    S.k = reinterpret_cast<int32_t*>(take(size_t(b_max) * 4));
-    S.lab = reinterpret_cast<int32_t*>(take(size_t(n_max) * 4));
-    S.core = reinterpret_cast<uint8_t*>(take(size_t(n_max)));
     if (hipEventCreateWithFlags(&S.h2d, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&S.comp, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&S.d2h, hipEventDisableTiming) != hipSuccess)
@@ -971,6 +956,23 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
     }
     const int32_t c0 = gbeg[g], b = gbeg[g + 1] - c0;
     const int64_t p0 = h_offsets[c0], n = h_offsets[gbeg[g + 1]] - p0;
+    {  // this group's layout in its slot (at most ooc_slot_bytes(n, b) <= slot_bytes)
+      char* q = static_cast<char*>(S.base);
+      auto take = [&](size_t bytes) {
+        char* r = q;
+        q += align_up(bytes);
+        return r;
+      };
+      S.ws_bytes = align_up(make_plan(n, dim, o.algo, b).bytes);
+      S.ws = take(S.ws_bytes);
+      S.pts = reinterpret_cast<float*>(take(size_t(n) * dim * 4));
+      S.off = reinterpret_cast<int64_t*>(take(size_t(b + 1) * 8));
+      S.eps = reinterpret_cast<float*>(take(size_t(b) * 4));
+      S.mp = reinterpret_cast<int32_t*>(take(size_t(b) * 4));
+      S.k = reinterpret_cast<int32_t*>(take(size_t(b) * 4));
+      S.lab = reinterpret_cast<int32_t*>(take(size_t(n) * 4));
+      S.core = reinterpret_cast<uint8_t*>(take(size_t(n)));
+    }
     for (int32_t c = 0; c <= b; ++c) S.h_off[c] = h_offsets[c0 + c] - p0;
     if ((n > 0 && hipMemcpyAsync(S.pts, h_points + p0 * dim, size_t(n) * dim * 4, hipMemcpyHostToDevice, sk) !=
                       hipSuccess) ||

@@ -1154,7 +1154,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
     const uint64_t mm = ballot(mine);
     if (!mm) return;
     const int fl = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-    const int i0 = __shfl(i, fl), p0 = __shfl(p, fl);  // primitives rise with the lanes
+    const int i0 = __shfl(i, fl), pmin = __shfl(p, fl);  // primitives rise with the lanes
     const Scope ps = scope_of<B>(a, m, i0);
     const bool other_cloud = B && mine && cloud_of(a, i) != cloud_of(a, i0);
     float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
@@ -1175,7 +1175,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
       bool common = !ballot(mine && root != r);
       const int plast = __shfl(p, 63);  // point primitives up to here are this wavefront's (phase A)
       uint32_t* stack = s_pstack + (threadIdx.x >> 6) * kWideStack;
-      traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, p0, a.t.leaf_size, a.info, stack, [&](int rr) {
+      traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, pmin, a.t.leaf_size, a.info, stack, [&](int rr) {
         float4 lr = make_float4(0.0f, 0.0f, 0.0f, 0.0f), hr = lr;
         bool hit = false;
         int anc = -1;

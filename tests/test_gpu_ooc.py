@@ -116,3 +116,28 @@ def test_nonfinite_cloud_isolated_and_nomem(dev):
         with pytest.raises(fdb.FdbError) as e:
             fdb.dbscan_batched_host(allp, bad_offs, eps, mp, budget)
         assert e.value.status == 1
+
+
+def test_groups_of_mixed_shapes(dev):
+    """Many tiny clouds around two large ones in a budget that holds one large
+    cloud per slot: groups of very different point and cloud counts share the
+    slots (each group is laid out on its own), results equal the in-core batch."""
+    import paper_2103_05162_amd as fdb
+    for dim in (3, 2):
+        rng = np.random.default_rng(60 + dim)
+        sizes = [int(x) for x in rng.integers(5, 60, size=300)]
+        sizes[120] = sizes[240] = 40000
+        clouds = []
+        for n in sizes:
+            cen = rng.uniform(0, 1, size=(3, dim))
+            pts = cen[rng.integers(0, 3, size=n)] + 0.01 * rng.standard_normal((n, dim))
+            clouds.append(pts.astype(np.float32))
+        offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        allp = np.ascontiguousarray(np.concatenate(clouds))
+        eps = np.full(len(sizes), 0.01, np.float32)
+        mp = np.full(len(sizes), 4, np.int32)
+        budget = _budget_for(fdb, 40000, 1, dim, "densebox") + (1 << 20)
+        _say(f"[gpu] out-of-core mixed groups {dim}D: {len(sizes)} clouds, budget {budget >> 20} MiB")
+        ref_l, ref_c, ref_k = _in_core(dev, allp, offs, eps, mp, "densebox")
+        lab, core, k = fdb.dbscan_batched_host(allp, offs, eps, mp, budget)
+        assert np.array_equal(k, ref_k) and np.array_equal(lab, ref_l) and np.array_equal(core, ref_c)
