@@ -514,8 +514,8 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.xs = xs;
   ta.n = n;
   ta.eps2 = eps2;
-  ta.packet_ext_eps2 = 4.0f;  // packet when the queries' box is at most 2 eps wide
-  ta.packet_leaf = 32;
+  ta.packet_ext_eps2 = 9.0f;  // packet when the queries' box is at most 3 eps wide
+  ta.packet_leaf = 64;         // buckets of up to 64 candidates, one per lane (measured best)
   ta.min_pts = min_pts;
   ta.labels = lab;
   ta.core = core;
@@ -732,8 +732,8 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   ta.xs = xs;
   ta.n = n;
   ta.eps2 = 0.0f;
-  ta.packet_ext_eps2 = 4.0f;
-  ta.packet_leaf = 32;
+  ta.packet_ext_eps2 = 9.0f;
+  ta.packet_leaf = 64;
   ta.min_pts = 0;
   ta.labels = lab;
   ta.core = core;
