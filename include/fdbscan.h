@@ -85,8 +85,8 @@ typedef enum {
 typedef struct {
   int32_t algo;       /* fdb_algo */
   int32_t border;     /* fdb_border */
-  int32_t leaf_size;  /* traversal: subtrees of <= leaf_size primitives are scanned linearly; 0 = default */
-  int32_t block_size; /* threads per workgroup of the traversal kernels (64..1024, multiple of 64); 0 = default */
+  int32_t leaf_size;  /* traversal: subtrees of <= leaf_size primitives are scanned linearly; 0 = default (8) */
+  int32_t block_size; /* threads per workgroup of the traversal kernels (64..1024, multiple of 64); 0 = default (128) */
   uint32_t flags;     /* reserved, must be 0 */
 } fdb_options;        /* all-zero = FDbscan, canonical labels, defaults */
 
