@@ -1563,7 +1563,8 @@ void main_t(const TravArgs& a, bool densebox, int part, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
   if (densebox) {
     if (part != 2) {
-      hipLaunchKernelGGL((k_main_dbx_cells_wave<D, ALL, FIRST, B>), dim3(2048), dim3(256), 0, s, a);
+      // a batch's many cells usually go to the lane kernel, where this one exits at once
+      hipLaunchKernelGGL((k_main_dbx_cells_wave<D, ALL, FIRST, B>), dim3(B ? 2048 : 4096), dim3(256), 0, s, a);
       // dense cells hold >= minPts points each, so there are at most n / minPts
       const int64_t max_cells = a.min_pts > 1 ? a.n / a.min_pts + 1 : a.n;
       if (max_cells > kCellsPerWaveMax)
