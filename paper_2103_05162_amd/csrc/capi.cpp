@@ -595,6 +595,16 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.brec_cap = static_cast<int>(plan.brec_cap);
   if (!all_core) {
     fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
+    // isolated points first, when the lone-cell bitmap fits the (now free) pflag buffer
+    const int lone_shift = dim * (gp.bits - 1);
+    const int64_t lone_words = lone_shift <= 6 ? 1 : (int64_t(1) << (lone_shift - 6));
+    if (densebox && !gp.key64 && gp.bits >= 1 && 2 * lone_words <= n) {
+      st.mark("isolated");
+      ta.core_list = at<int>(ws, plan.cid);  // cid is free until the canonical ids
+      ta.core_qn = misc + kMiscCoreQ;
+      launch_lone_filter(ta, dim, at<uint32_t>(ws, plan.prim_key), gp.bits, gp.ncell, at<uint64_t>(ws, plan.pflag),
+                         lone_words, at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
+    }
     st.mark("core");
     launch_core(ta, dim, densebox, s);
   }

@@ -14,6 +14,8 @@
 // that subtree, eps^2 and minPts. A single cloud's scope is the whole tree; in
 // a batch the keys carry the cloud id above the Morton bits, so each cloud is
 // one subtree, and a query's scope is its cloud's (with its own eps, minPts).
+#include <algorithm>
+
 #include "fdb_device.hpp"
 #include "fdb_internal.hpp"
 
@@ -1027,6 +1029,262 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
   return -1;
 }
 
+// ---- isolated points (one cloud, DenseBox, 32-bit grid keys) --------------------
+// A lone cell is a 2^d block of grid cells, side 2 eps/sqrt(d) >= 1.15 eps. Two
+// points within eps (the fp32 predicate and the cell-index rounding included)
+// have grid coordinates at most 1.77 cells apart per axis, so lone-cell
+// coordinates at most 1 apart: every neighbour of a point lies in the 3^d lone
+// cells around its own. A lone cell's Morton code is the grid key without its
+// lowest d bits, so primitives, in key order, visit lone cells in code order.
+//
+// Occupancy is kept as one 64-bit word per brick of lone cells (4x4x4 in 3D, 8x8
+// in 2D). Bricks follow the Morton order, so a brick's index is the lone code
+// without its lowest 6 bits; inside a brick, local cell (x, y, z) is bit
+// x*16 + y*4 + z (3D) or x*8 + y (2D), which makes the part of a 3^d
+// neighbourhood inside one brick a product of per-axis bit ranges. A
+// neighbourhood touches at most 2^d bricks: at most 2^d loads per query.
+struct LoneGeom {
+  uint32_t nl[3];  // lone cells per axis
+};
+
+template <int D>
+__device__ __forceinline__ uint32_t lone_code(uint32_t key) {
+  return key >> D;
+}
+
+template <int D>
+constexpr int kBrickShift = D == 3 ? 2 : 3;  // local coordinate bits per axis
+
+template <int D>
+__device__ __forceinline__ int brick_bit(uint32_t code) {  // from the code's lowest 6 bits
+  if constexpr (D == 3) {
+    const uint32_t z = (code & 1u) | ((code >> 2) & 2u);
+    const uint32_t y = ((code >> 1) & 1u) | ((code >> 3) & 2u);
+    const uint32_t x = ((code >> 2) & 1u) | ((code >> 4) & 2u);
+    return static_cast<int>(x * 16 + y * 4 + z);
+  } else {
+    const uint32_t y = (code & 1u) | ((code >> 1) & 2u) | ((code >> 2) & 4u);
+    const uint32_t x = ((code >> 1) & 1u) | ((code >> 2) & 2u) | ((code >> 3) & 4u);
+    return static_cast<int>(x * 8 + y);
+  }
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int off) {
+  const uint32_t lo = static_cast<uint32_t>(__shfl_up(static_cast<int>(v), off));
+  const uint32_t hi = static_cast<uint32_t>(__shfl_up(static_cast<int>(v >> 32), off));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
+  const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off));
+  const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v >> 32), off));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// A brick word is written once, by the wavefront holding the brick's first
+// primitive: a segmented OR over the wavefront's 64 primitives, and for its last
+// brick the following primitives of the same brick, read 64 at a time.
+template <int D>
+__global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ pkey, const int* __restrict__ d_m,
+                                                   uint64_t* __restrict__ bits) {
+  const int m = *d_m;
+  const int lane = lane_id();
+  // a wavefront per 64 primitives, over a grid-stride loop (uniform per wavefront)
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t p0 = (blockIdx.x * int64_t(blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; p0 < m; p0 += waves * 64) {
+    const int64_t p = p0 + lane;
+    const bool valid = p < m;
+    const uint32_t code = valid ? lone_code<D>(pkey[p]) : 0xffffffffu;
+    const uint32_t word = code >> 6;  // invalid lanes: above every valid brick
+    const uint32_t prevw = static_cast<uint32_t>(__shfl_up(static_cast<int>(word), 1));
+    const uint32_t nextw = static_cast<uint32_t>(__shfl_down(static_cast<int>(word), 1));
+    const bool head = lane == 0 || word != prevw;
+    // segmented inclusive OR: the last lane of a run of equal bricks holds the run's bits
+    uint64_t v = valid ? (1ull << brick_bit<D>(code)) : 0ull;
+    bool f = head;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t u = shfl_up_u64(v, off);
+      const bool g = __shfl_up(static_cast<int>(f), off) != 0;
+      if (lane >= off && !f) {
+        v |= u;
+        f = g;
+      }
+    }
+    const uint32_t w0 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 0));
+    // the wavefront's first run may continue a brick begun by the previous
+    // wavefront, which then writes it
+    const bool continued = p0 > 0 && (lone_code<D>(pkey[p0 - 1]) >> 6) == w0;
+    const bool in_first_run = __popcll(ballot(head) & (lanemask_lt() | (1ull << lane))) == 1;
+    const uint32_t w63 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 63));
+    uint64_t extra = 0;
+    // lane 63 is valid and its run may go on past this wavefront; only the
+    // wavefront that writes that brick reads ahead
+    if (p0 + 64 < m && !(continued && w63 == w0)) {
+      for (int64_t b = p0 + 64; b < m; b += 64) {
+        const int64_t q = b + lane;
+        const uint32_t c2 = q < m ? lone_code<D>(pkey[q]) : 0xffffffffu;
+        const bool in = q < m && (c2 >> 6) == w63;
+        uint64_t x = in ? (1ull << brick_bit<D>(c2)) : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x |= shfl_xor_u64(x, off);
+        extra |= x;
+        if (!((ballot(in) >> 63) & 1)) break;  // codes are sorted: the run ended in this chunk
+      }
+    }
+    const bool tail = valid && (lane == 63 || nextw != word);
+    if (tail && !(continued && in_first_run)) bits[word] = v | (lane == 63 ? extra : 0ull);
+  }
+}
+
+__device__ __forceinline__ uint32_t compact_every(uint32_t x, int d) {  // inverse of the Morton spread
+  if (d == 3) {
+    x &= 0x09249249u;
+    x = (x | (x >> 2)) & 0x030c30c3u;
+    x = (x | (x >> 4)) & 0x0300f00fu;
+    x = (x | (x >> 8)) & 0xff0000ffu;
+    x = (x | (x >> 16)) & 0x000003ffu;
+  } else {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0f0f0f0fu;
+    x = (x | (x >> 4)) & 0x00ff00ffu;
+    x = (x | (x >> 8)) & 0x0000ffffu;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t spread_every(uint32_t x, int d) {  // Morton spread of one coordinate
+  if (d == 3) {
+    x &= 0x000003ffu;
+    x = (x | (x << 16)) & 0xff0000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+  } else {
+    x &= 0x0000ffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+  }
+  return x;
+}
+
+// Bits of a brick whose coordinate on axis a lies in [l, h] (local, l <= h).
+template <int D>
+__device__ __forceinline__ uint64_t axis_bits(int a, int l, int h) {
+  if constexpr (D == 3) {
+    if (a == 0) return (~0ull >> (48 - 16 * h)) & (~0ull << (16 * l));
+    if (a == 1) return uint64_t((0xffffu >> (12 - 4 * h)) & (0xffffu << (4 * l)) & 0xffffu) * 0x0001000100010001ull;
+    return uint64_t((0xfu >> (3 - h)) & (0xfu << l) & 0xfu) * 0x1111111111111111ull;
+  } else {
+    if (a == 0) return (~0ull >> (56 - 8 * h)) & (~0ull << (8 * l));
+    return uint64_t((0xffu >> (7 - h)) & (0xffu << l) & 0xffu) * 0x0101010101010101ull;
+  }
+}
+
+// Point primitive p (key order) is isolated if no other primitive shares its lone
+// cell (they would be next to it in key order) and the neighbouring lone cells are
+// all empty. Conservative: a false answer only means "walk it".
+template <int D>
+__device__ __forceinline__ bool isolated(const uint32_t* __restrict__ pkey, int m, int p, const LoneGeom& g,
+                                         const uint64_t* __restrict__ bits) {
+  const uint32_t lc = lone_code<D>(pkey[p]);
+  if ((p > 0 && lone_code<D>(pkey[p - 1]) == lc) || (p + 1 < m && lone_code<D>(pkey[p + 1]) == lc)) return false;
+  constexpr int S = kBrickShift<D>, W = 1 << S;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int c = static_cast<int>(compact_every(lc >> (D - 1 - a), D));
+    lo[a] = c > 0 ? c - 1 : 0;
+    hi[a] = static_cast<uint32_t>(c + 1) < g.nl[a] ? c + 1 : c;
+  }
+  const uint32_t own_brick = lc >> 6;
+  const int own_bit = brick_bit<D>(lc);
+  bool hit = false;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int k = 0; k < (D == 3 ? 2 : 1); ++k) {
+        const int br[3] = {(lo[0] >> S) + i, (lo[1] >> S) + j, (lo[2] >> S) + k};
+        bool use = br[0] <= (hi[0] >> S) && br[1] <= (hi[1] >> S);
+        if (D == 3) use = use && br[2] <= (hi[2] >> S);
+        if (!use) continue;
+        uint64_t mask = ~0ull;
+        uint32_t idx = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int base = br[a] << S;
+          const int l = (lo[a] > base ? lo[a] : base) - base;
+          const int h = (hi[a] < base + W - 1 ? hi[a] : base + W - 1) - base;
+          mask &= axis_bits<D>(a, l, h);
+          idx |= spread_every(static_cast<uint32_t>(br[a]), D) << (D - 1 - a);
+        }
+        if (idx == own_brick) mask &= ~(1ull << own_bit);
+        hit |= (bits[idx] & mask) != 0ull;
+      }
+  return !hit;
+}
+
+// A workgroup tests kLoneRounds x 256 consecutive primitives and lists the ones
+// left for the core pass with one atomic (a single counter taken by every
+// workgroup is the cost to keep low), in primitive order within the workgroup.
+constexpr int kLoneRounds = 8;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint32_t* __restrict__ pkey, LoneGeom g,
+                                                     const uint64_t* __restrict__ bits, int* __restrict__ list,
+                                                     int* __restrict__ list_n) {
+  __shared__ int s_cnt[kLoneRounds * 4 + 1];
+  const int m = tree_m(a.t);
+  const int64_t base = blockIdx.x * int64_t(kLoneRounds * 256);
+  if (base >= m) return;  // whole workgroup
+  const int w = threadIdx.x >> 6;
+  uint32_t keep = 0;  // bit r: primitive of round r is listed
+  for (int r = 0; r < kLoneRounds; ++r) {
+    const int64_t p = base + r * 256 + threadIdx.x;
+    bool query = false, lone = false;
+    int i = 0;
+    if (p < m) {
+      i = rec_index(a.prim_lo[p]);
+      if (i >= 0) {
+        query = true;
+        lone = isolated<D>(pkey, m, static_cast<int>(p), g, bits);
+      }
+    }
+    if (lone) {
+      a.core[i] = 0;
+      a.lone[i] = 1;
+      a.border[i] = -1;
+    }
+    const bool listed = query && !lone;
+    keep |= listed ? 1u << r : 0u;
+    const uint64_t bal = ballot(listed);
+    if (lane_id() == 0) s_cnt[r * 4 + w] = __popcll(bal);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int k = 0; k < kLoneRounds * 4; ++k) {
+      const int c = s_cnt[k];
+      s_cnt[k] = tot;
+      tot += c;
+    }
+    s_cnt[kLoneRounds * 4] = tot ? atomicAdd(list_n, tot) : 0;
+  }
+  __syncthreads();
+  const int start = s_cnt[kLoneRounds * 4];
+  for (int r = 0; r < kLoneRounds; ++r) {
+    const bool listed = (keep >> r) & 1u;
+    const uint64_t bal = ballot(listed);
+    if (listed)
+      list[start + s_cnt[r * 4 + w] + __popcll(bal & lanemask_lt())] = static_cast<int>(base + r * 256 + threadIdx.x);
+  }
+}
+
 // Core pass for points outside dense cells. Each lane walks for kCoreQ
 // neighbouring point primitives (kCoreQ k + t for lane k of the index space).
 // Two walks per lane keep more node loads in flight, but a wavefront then waits
@@ -1042,9 +1300,11 @@ __global__ void k_core_dbx(TravArgs a) {
   const int lane = lane_id();
   // the grid is sized for n queries; a workgroup past the m primitives leaves
   // at once (uniformly, before any barrier)
-  const int64_t k0 = xcd_spread(blockIdx.x, blockDim.x, 0, (m + kCoreQ - 1) / kCoreQ);
-  if (k0 < 0 || k0 * kCoreQ >= m) return;
-  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, (m + kCoreQ - 1) / kCoreQ);
+  static_assert(kCoreQ == 1, "a listed query is one primitive");
+  const int64_t total = a.core_list ? *a.core_qn : (m + kCoreQ - 1) / kCoreQ;
+  const int64_t k0 = xcd_spread(blockIdx.x, blockDim.x, 0, total);
+  if (k0 < 0 || k0 >= total) return;
+  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, total);
   int p[kCoreQ], i[kCoreQ], cnt[kCoreQ];
   bool mine[kCoreQ], active[kCoreQ];
   Scope sc[kCoreQ];
@@ -1053,7 +1313,7 @@ __global__ void k_core_dbx(TravArgs a) {
   Walk w[kCoreQ];
 #pragma unroll
   for (int t = 0; t < kCoreQ; ++t) {
-    p[t] = k >= 0 ? static_cast<int>(k * kCoreQ + t) : -1;
+    p[t] = k < 0 || k >= total ? -1 : (a.core_list ? a.core_list[k] : static_cast<int>(k * kCoreQ + t));
     own_record(a, p[t], m, mine[t], i[t], q[t]);  // dense cells are core by construction
     sc[t] = scope_of<B>(a, m, i[t]);
     cnt[t] = 0;
@@ -1547,6 +1807,19 @@ inline dim3 grid_of(int64_t n, int block) {
   return dim3(static_cast<unsigned>(kNumXcd * ceil_div(ceil_div(n, kNumXcd), block)));
 }
 
+template <int D>
+void lone_t(const TravArgs& a, const uint32_t* pkey, const LoneGeom& g, uint64_t* bits, int64_t words, int* list,
+            int* list_n, hipStream_t s) {
+  fill_u32(reinterpret_cast<uint32_t*>(bits), 0, 2 * words, s);
+  const int64_t gb = std::min<int64_t>(ceil_div(a.t.m_cap, 256), 4096);  // 4 wavefronts of 64 primitives
+  hipLaunchKernelGGL(k_lone_bits<D>, dim3(static_cast<unsigned>(gb > 0 ? gb : 1)), dim3(256), 0, s, pkey, a.t.d_m,
+                     bits);
+  fill_u32(reinterpret_cast<uint32_t*>(list_n), 0, 1, s);
+  const int64_t gf = ceil_div(a.t.m_cap, kLoneRounds * 256);
+  hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, g,
+                     bits, list, list_n);
+}
+
 template <int D, bool B>
 void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
@@ -1605,6 +1878,16 @@ void main_dispatch(const TravArgs& a, bool densebox, bool all_core, bool first_b
 }
 
 }  // namespace
+
+void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, int grid_bits, const uint32_t* ncell,
+                        uint64_t* bits, int64_t words, int* list, int* list_n, hipStream_t s) {
+  (void)grid_bits;
+  if (a.n <= 0) return;
+  LoneGeom g;
+  for (int k = 0; k < 3; ++k) g.nl[k] = k < dim ? (ncell[k] + 1) / 2 : 1;
+  if (dim == 3) lone_t<3>(a, prim_key, g, bits, words, list, list_n, s);
+  else lone_t<2>(a, prim_key, g, bits, words, list, list_n, s);
+}
 
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {
   if (a.n <= 0) return;

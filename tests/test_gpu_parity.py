@@ -351,7 +351,8 @@ def test_automatic_choice(dev):
 def test_isolated_points_and_pairs_at_eps(dev, d):
     """Isolated points, and pairs at distances a hair inside or outside eps in
     random directions: core, noise and border decisions must be the oracle's bit
-    for bit (DenseBox with minPts > 2: lone points, records and walks)."""
+    for bit (DenseBox: lone points, records and walks; with minPts 2 a pair is
+    core, so a point wrongly taken as isolated by the lone-cell test fails)."""
     rng = np.random.default_rng(40 + d)
     eps, n_single, n_pair = (0.03, 3000, 1500) if d == 3 else (0.02, 150, 100)
     singles = rng.uniform(0, 1, size=(n_single, d))
@@ -361,7 +362,7 @@ def test_isolated_points_and_pairs_at_eps(dev, d):
     scale = eps * rng.choice([1 - 1e-6, 1 - 1e-7, 1.0, 1 + 1e-7, 1 + 1e-6, 0.5, 1.5], size=n_pair)
     pts = np.concatenate([singles, a, a + u * scale[:, None]]).astype(np.float32)
     rng.shuffle(pts)
-    for mp in (3, 4):
+    for mp in (2, 3, 4):
         ref = assert_exact(dev, pts, eps, mp, "densebox")
         assert (ref[0] == -1).sum() > len(pts) // 10  # plenty of noise
         assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
