@@ -56,7 +56,8 @@ enum MiscSlot : int {
   kMiscNumDense = 4,     // DenseBox: dense cells
   kMiscBorderQ = 5,      // entries of the border query list (filled by the core pass)
   kMiscBorderRec = 6,    // border neighbour records asked for by the core pass
-  kMiscCoreQ = 7,        // DenseBox: point primitives left for the core pass by the isolated-point test
+  kMiscCoreQ = 8,        // DenseBox: point primitives left for the core pass by the isolated-point test,
+                         // one count per XCD segment (slots 8 .. 15)
   kMiscCount = 16
 };
 
@@ -153,8 +154,9 @@ struct TravArgs {
   int* qborder_n;
   const int* cid;
   int* border;
-  // DenseBox core pass over a list of point primitives (core_list[0..*core_qn)),
-  // or over every primitive when core_list is null
+  // DenseBox core pass over lists of point primitives, one per XCD segment
+  // (core_list[x * segment + 0 .. core_qn[x]), kNumXcd of them), or over every
+  // primitive when core_list is null
   const int* core_list;
   const int* core_qn;
   // DenseBox primitives (null for FDbscan). Primitive r covers sorted points
@@ -186,7 +188,7 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
 // a bitmap over "lone cells" (2^d blocks of grid cells) marks the cells holding a
 // primitive; a point primitive alone in its lone cell, whose 3^d - 1 neighbours
 // are empty, has no neighbour but itself and is finished here (core 0, lone,
-// border -1); the others are listed (list, *list_n) for the core pass. bits holds
+// border -1); the others are listed (list, list_n[kNumXcd]) for the core pass. bits holds
 // words = 2^(d (grid_bits - 1)) / 64 (at least 1) 64-bit words; ncell: grid cells per axis.
 void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, int grid_bits, const uint32_t* ncell,
                         uint64_t* bits, int64_t words, int* list, int* list_n, hipStream_t s);

@@ -1230,9 +1230,19 @@ __device__ __forceinline__ bool isolated(const uint32_t* __restrict__ pkey, int 
 }
 
 // A workgroup tests kLoneRounds x 256 consecutive primitives and lists the ones
-// left for the core pass with one atomic (a single counter taken by every
-// workgroup is the cost to keep low), in primitive order within the workgroup.
+// left for the core pass with one atomic (a counter taken by many workgroups is
+// the cost to keep low), in primitive order within the workgroup. The primitives
+// are cut into kNumXcd segments of lone_segment(m) (a multiple of a workgroup's
+// share); segment s has its own counter and lists into list[s * segment ...], which
+// never passes its own primitive range, so the list needs m entries. The core pass
+// gives segment s to the workgroups of XCD s: each XCD walks one contiguous range
+// of the curve, as it does without the test.
 constexpr int kLoneRounds = 8;
+
+__device__ __forceinline__ int64_t lone_segment(int m) {
+  const int64_t share = kLoneRounds * 256;
+  return ((m + kNumXcd - 1) / kNumXcd + share - 1) / share * share;
+}
 
 template <int D>
 __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint32_t* __restrict__ pkey, LoneGeom g,
@@ -1242,6 +1252,8 @@ __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint32_t*
   const int m = tree_m(a.t);
   const int64_t base = blockIdx.x * int64_t(kLoneRounds * 256);
   if (base >= m) return;  // whole workgroup
+  const int64_t segment = lone_segment(m);
+  const int seg = static_cast<int>(base / segment);  // a workgroup lies in one segment
   const int w = threadIdx.x >> 6;
   uint32_t keep = 0;  // bit r: primitive of round r is listed
   for (int r = 0; r < kLoneRounds; ++r) {
@@ -1273,10 +1285,10 @@ __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint32_t*
       s_cnt[k] = tot;
       tot += c;
     }
-    s_cnt[kLoneRounds * 4] = tot ? atomicAdd(list_n, tot) : 0;
+    s_cnt[kLoneRounds * 4] = tot ? atomicAdd(list_n + seg, tot) : 0;
   }
   __syncthreads();
-  const int start = s_cnt[kLoneRounds * 4];
+  const int64_t start = s_cnt[kLoneRounds * 4] + seg * segment;
   for (int r = 0; r < kLoneRounds; ++r) {
     const bool listed = (keep >> r) & 1u;
     const uint64_t bal = ballot(listed);
@@ -1301,10 +1313,14 @@ __global__ void k_core_dbx(TravArgs a) {
   // the grid is sized for n queries; a workgroup past the m primitives leaves
   // at once (uniformly, before any barrier)
   static_assert(kCoreQ == 1, "a listed query is one primitive");
-  const int64_t total = a.core_list ? *a.core_qn : (m + kCoreQ - 1) / kCoreQ;
-  const int64_t k0 = xcd_spread(blockIdx.x, blockDim.x, 0, total);
+  // listed queries: XCD x (workgroup index mod kNumXcd) takes segment x of the list
+  const int xcd = static_cast<int>(blockIdx.x % kNumXcd);
+  const int* qlist = a.core_list ? a.core_list + xcd * lone_segment(m) : nullptr;
+  const int64_t total = a.core_list ? a.core_qn[xcd] : (m + kCoreQ - 1) / kCoreQ;
+  const int64_t k0 = a.core_list ? int64_t(blockIdx.x / kNumXcd) * blockDim.x
+                                 : xcd_spread(blockIdx.x, blockDim.x, 0, total);
   if (k0 < 0 || k0 >= total) return;
-  const int64_t k = xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, total);
+  const int64_t k = a.core_list ? k0 + threadIdx.x : xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, total);
   int p[kCoreQ], i[kCoreQ], cnt[kCoreQ];
   bool mine[kCoreQ], active[kCoreQ];
   Scope sc[kCoreQ];
@@ -1313,7 +1329,7 @@ __global__ void k_core_dbx(TravArgs a) {
   Walk w[kCoreQ];
 #pragma unroll
   for (int t = 0; t < kCoreQ; ++t) {
-    p[t] = k < 0 || k >= total ? -1 : (a.core_list ? a.core_list[k] : static_cast<int>(k * kCoreQ + t));
+    p[t] = k < 0 || k >= total ? -1 : (qlist ? qlist[k] : static_cast<int>(k * kCoreQ + t));
     own_record(a, p[t], m, mine[t], i[t], q[t]);  // dense cells are core by construction
     sc[t] = scope_of<B>(a, m, i[t]);
     cnt[t] = 0;
@@ -1814,7 +1830,7 @@ void lone_t(const TravArgs& a, const uint32_t* pkey, const LoneGeom& g, uint64_t
   const int64_t gb = std::min<int64_t>(ceil_div(a.t.m_cap, 256), 4096);  // 4 wavefronts of 64 primitives
   hipLaunchKernelGGL(k_lone_bits<D>, dim3(static_cast<unsigned>(gb > 0 ? gb : 1)), dim3(256), 0, s, pkey, a.t.d_m,
                      bits);
-  fill_u32(reinterpret_cast<uint32_t*>(list_n), 0, 1, s);
+  fill_u32(reinterpret_cast<uint32_t*>(list_n), 0, kNumXcd, s);
   const int64_t gf = ceil_div(a.t.m_cap, kLoneRounds * 256);
   hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, g,
                      bits, list, list_n);
@@ -1824,10 +1840,17 @@ template <int D, bool B>
 void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
   const size_t lds = sizeof(int) * kRecNb * a.block;  // neighbour records
-  if (densebox)
+  if (densebox && a.core_list) {
+    // kNumXcd segments of at most lone_segment(m) <= this many listed queries
+    const int64_t share = kLoneRounds * 256;
+    const int64_t seg = ceil_div(ceil_div(a.t.m_cap, kNumXcd), share) * share;
+    const int64_t gl = kNumXcd * ceil_div(seg, a.block);
+    hipLaunchKernelGGL((k_core_dbx<D, B>), dim3(static_cast<unsigned>(gl)), b, kCoreQ * lds, s, a);
+  } else if (densebox) {
     hipLaunchKernelGGL((k_core_dbx<D, B>), grid_of(ceil_div(a.n, kCoreQ), a.block), b, kCoreQ * lds, s, a);
-  else
+  } else {
     hipLaunchKernelGGL((k_core_fdb<D, B>), g, b, lds, s, a);
+  }
 }
 
 // part: 0 = everything, 1 = dense-cell queries only, 2 = point queries only (DenseBox)
