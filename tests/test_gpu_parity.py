@@ -348,6 +348,34 @@ def test_automatic_choice(dev):
 
 
 @pytest.mark.parametrize("d", [2, 3])
+def test_isolated_point_test_edges(dev, d):
+    """The DenseBox isolated-point test on its edges: a blob of thousands of
+    point primitives (no dense cell at minPts 40) whose runs within one occupancy
+    word span many wavefronts; pairs just inside eps straddling word boundaries
+    on every axis at once; scattered points that are mostly alone; and a cloud
+    spanning under two grid cells (a one-word map)."""
+    rng = np.random.default_rng(70 + d)
+    eps = 0.03 if d == 3 else 0.02
+    h = eps / np.sqrt(d)              # grid cell side (the bounds below start at 0)
+    word = (8 if d == 3 else 16) * h   # side of the cells one occupancy word covers
+    blob = 0.5 + rng.uniform(0, 4 * eps, size=(5000 if d == 3 else 3000, d))
+    scattered = rng.uniform(0, 1, size=(2000 if d == 3 else 400, d))
+    u = np.ones(d) / np.sqrt(d)
+    k = rng.integers(1, int(0.9 / word), size=(300, 1))
+    a = k * word - 0.3 * eps * u + rng.uniform(-1e-3, 1e-3, size=(300, d)) * eps
+    b = a + eps * (1 - 1e-6) * u
+    corners = np.array([np.zeros(d), np.ones(d)])
+    pts = np.concatenate([blob, scattered, a, b, corners]).astype(np.float32)
+    rng.shuffle(pts)
+    for mp in (2, 40):
+        ref = assert_exact(dev, pts, eps, mp, "densebox")
+        assert (ref[0] == -1).sum() > 100 and ref[1].sum() > 1000
+    tiny = (rng.uniform(0, 1.5 * h, size=(40, d))).astype(np.float32)
+    ref = assert_exact(dev, tiny, eps, 2, "densebox")
+    assert ref[1].all() and ref[2] == 1
+
+
+@pytest.mark.parametrize("d", [2, 3])
 def test_isolated_points_and_pairs_at_eps(dev, d):
     """Isolated points, and pairs at distances a hair inside or outside eps in
     random directions: core, noise and border decisions must be the oracle's bit
