@@ -602,7 +602,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
       st.mark("isolated");
       ta.core_list = at<int>(ws, plan.cid);  // cid is free until the canonical ids
       ta.core_qn = misc + kMiscCoreQ;
-      launch_lone_filter(ta, dim, at<uint32_t>(ws, plan.prim_key), gp.bits, gp.ncell, at<uint64_t>(ws, plan.pflag),
+      launch_lone_filter(ta, dim, at<uint32_t>(ws, plan.prim_key), gp.ncell, at<uint64_t>(ws, plan.pflag),
                          lone_words, at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
     }
     st.mark("core");

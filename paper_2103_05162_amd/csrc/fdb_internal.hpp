@@ -137,7 +137,8 @@ struct TravArgs {
   int min_pts;
   int* labels;
   uint8_t* core;
-  uint8_t* lone;  // set by the core pass: 1 = not core and no neighbour but itself (noise); NULL if no core pass
+  uint8_t* lone;  // set by the core pass (or the isolated-point test before it): 1 = not core and no
+                  // neighbour but itself (noise); NULL if no core pass
   // Border work left by the core pass for non-core points with some neighbour
   // other than themselves. Up to kRecNb neighbouring primitives of such a point
   // (the point itself, or a dense cell's first point) are recorded, so the
@@ -189,9 +190,10 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
 // primitive; a point primitive alone in its lone cell, whose 3^d - 1 neighbours
 // are empty, has no neighbour but itself and is finished here (core 0, lone,
 // border -1); the others are listed (list, list_n[kNumXcd]) for the core pass. bits holds
-// words = 2^(d (grid_bits - 1)) / 64 (at least 1) 64-bit words; ncell: grid cells per axis.
-void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, int grid_bits, const uint32_t* ncell,
-                        uint64_t* bits, int64_t words, int* list, int* list_n, hipStream_t s);
+// words = 2^(d (b - 1)) / 64 (at least 1) 64-bit words for keys of b bits per axis;
+// ncell: grid cells per axis.
+void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, const uint32_t* ncell, uint64_t* bits,
+                        int64_t words, int* list, int* list_n, hipStream_t s);
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
                  hipStream_t s);
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);

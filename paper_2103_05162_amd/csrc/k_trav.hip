@@ -1084,9 +1084,11 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
 // A brick word is written once, by the wavefront holding the brick's first
 // primitive: a segmented OR over the wavefront's 64 primitives, and for its last
 // brick the following primitives of the same brick, read 64 at a time.
+// It also clears the list counters of k_lone_filter, which runs after it.
 template <int D>
 __global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ pkey, const int* __restrict__ d_m,
-                                                   uint64_t* __restrict__ bits) {
+                                                   uint64_t* __restrict__ bits, int* __restrict__ list_n) {
+  if (blockIdx.x == 0 && threadIdx.x < kNumXcd) list_n[threadIdx.x] = 0;
   const int m = *d_m;
   const int lane = lane_id();
   // a wavefront per 64 primitives, over a grid-stride loop (uniform per wavefront)
@@ -1829,8 +1831,7 @@ void lone_t(const TravArgs& a, const uint32_t* pkey, const LoneGeom& g, uint64_t
   fill_u32(reinterpret_cast<uint32_t*>(bits), 0, 2 * words, s);
   const int64_t gb = std::min<int64_t>(ceil_div(a.t.m_cap, 256), 4096);  // 4 wavefronts of 64 primitives
   hipLaunchKernelGGL(k_lone_bits<D>, dim3(static_cast<unsigned>(gb > 0 ? gb : 1)), dim3(256), 0, s, pkey, a.t.d_m,
-                     bits);
-  fill_u32(reinterpret_cast<uint32_t*>(list_n), 0, kNumXcd, s);
+                     bits, list_n);
   const int64_t gf = ceil_div(a.t.m_cap, kLoneRounds * 256);
   hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, g,
                      bits, list, list_n);
@@ -1902,9 +1903,8 @@ void main_dispatch(const TravArgs& a, bool densebox, bool all_core, bool first_b
 
 }  // namespace
 
-void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, int grid_bits, const uint32_t* ncell,
-                        uint64_t* bits, int64_t words, int* list, int* list_n, hipStream_t s) {
-  (void)grid_bits;
+void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, const uint32_t* ncell, uint64_t* bits,
+                        int64_t words, int* list, int* list_n, hipStream_t s) {
   if (a.n <= 0) return;
   LoneGeom g;
   for (int k = 0; k < 3; ++k) g.nl[k] = k < dim ? (ncell[k] + 1) / 2 : 1;
