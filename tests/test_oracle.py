@@ -211,6 +211,102 @@ def test_matches_sklearn_dbscan(dim, min_pts, seed):
     assert ((~core) & (labels >= 0)).sum() > 0
 
 
+# ---- the border checker must catch wrong border labels ---------------------------
+#
+# check_border is the only judge of first-claim outputs (Section 3.2: a border
+# point joins whichever cluster claims it first), so it is pinned here on labels
+# known to be wrong: each planted violation must be counted exactly once, and the
+# valid alternatives of the bridging case must pass.
+
+def _two_lines():
+    # the set of test_two_lines_noise_and_border: eps = 1, minPts = 3; points 0-4
+    # line A (core), 5-7 line B (core), 8 = (5,5) noise, 9 = (3,0) border of A only
+    A = [(0, 0), (0.5, 0), (1, 0), (1.5, 0), (2, 0)]
+    B = [(10, 0), (10.5, 0), (11, 0)]
+    return np.array(A + B + [(5, 5), (3, 0)], dtype=np.float32)
+
+
+@pytest.mark.parametrize("method", ["brute", "grid"])
+def test_check_border_counts_planted_violations(method):
+    pts = _two_lines()
+    labels, core, k = oracle.dbscan(pts, 1.0, 3, "brute")
+    assert labels.tolist() == [0] * 5 + [1] * 3 + [-1, 0]
+    assert oracle.check_border(pts, 1.0, core, labels, method) == 0
+    # a labelled non-core point whose label's cores are all beyond eps
+    # (B's nearest core (10,0) is 7 away from (3,0))
+    bad = labels.copy(); bad[9] = 1
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 1
+    # a noise label on a point with a core within eps ((2,0) at distance exactly 1)
+    bad = labels.copy(); bad[9] = -1
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 1
+    # a cluster label on a point with no core neighbour at all
+    bad = labels.copy(); bad[8] = 0
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 1
+    # an id that names no cluster
+    bad = labels.copy(); bad[9] = 7
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 1
+    # the three at once are three violations
+    bad = labels.copy(); bad[9] = 1; bad[8] = 0
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 2
+    bad[9] = -1
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 2
+    # core points' labels are not the checker's business (the partition test is)
+    bad = labels.copy(); bad[0] = 1
+    assert oracle.check_border(pts, 1.0, core, bad, method) == 0
+
+
+@pytest.mark.parametrize("method", ["brute", "grid"])
+def test_check_border_accepts_either_cluster_of_a_bridging_point(method):
+    # the bridging set of test_bridging_border_point_does_not_merge_clusters:
+    # b = (2.875, 0) is within eps of a core of each cluster, so both ids are valid
+    # and noise is not; (5.75, 0) reaches only B and (0, 0) only A.
+    B = [(3.75, 0), (4.25, 0), (4.75, 0), (5.25, 0), (5.75, 0)]
+    A = [(0, 0), (0.5, 0), (1, 0), (1.5, 0), (2, 0)]
+    pts = np.array(B + A + [(2.875, 0)], dtype=np.float32)
+    labels, core, k = oracle.dbscan(pts, 1.0, 4, "brute")
+    for b_label, expect in ((0, 0), (1, 0), (-1, 1), (2, 1)):
+        lab = labels.copy(); lab[10] = b_label
+        assert oracle.check_border(pts, 1.0, core, lab, method) == expect, b_label
+    lab = labels.copy(); lab[4] = 1   # (5.75, 0) moved to A: A's nearest core (2,0) is 3.75 away
+    assert oracle.check_border(pts, 1.0, core, lab, method) == 1
+    lab = labels.copy(); lab[5] = 0   # (0, 0) moved to B
+    assert oracle.check_border(pts, 1.0, core, lab, method) == 1
+
+
+@pytest.mark.parametrize("dim,min_pts,seed", [(2, 5, 1), (3, 4, 2)])
+def test_check_border_catches_one_moved_sklearn_border_point(dim, min_pts, seed):
+    """scikit-learn's own labels (an independent implementation) pass; moving one
+    border point into a cluster none of whose cores is within eps (decided in fp64
+    on an eps with no pair near the threshold) gives exactly one violation, and
+    turning one border point into noise gives exactly one."""
+    rng = np.random.default_rng(seed)
+    pts = _blobs(rng, 1500, dim, 6, 0.03)
+    eps = pick_safe_eps(pts, 0.03 if dim == 2 else 0.06)
+    sk = sklearn.cluster.DBSCAN(eps=eps, min_samples=min_pts, algorithm="brute").fit(pts.astype(np.float64))
+    core = np.zeros(len(pts), bool)
+    core[sk.core_sample_indices_] = True
+    lab = sk.labels_.astype(np.int32)
+    assert oracle.check_border(pts, eps, core, lab) == 0
+    p = pts.astype(np.float64)
+    border = np.flatnonzero(~core & (lab >= 0))
+    assert border.size > 0
+    i = int(border[0])
+    near = np.sqrt(((p - p[i]) ** 2).sum(1)) <= eps
+    reachable = set(lab[near & core].tolist())
+    far = [c for c in range(lab.max() + 1) if c not in reachable]
+    assert far
+    moved = lab.copy(); moved[i] = far[0]
+    assert oracle.check_border(pts, eps, core, moved) == 1
+    assert oracle.check_border(pts, eps, core, moved, "brute") == 1
+    dropped = lab.copy(); dropped[i] = -1
+    assert oracle.check_border(pts, eps, core, dropped) == 1
+    # a noise point given a cluster: noise has no core within eps, so any id is wrong
+    noise = np.flatnonzero(lab < 0)
+    assert noise.size > 0
+    given = lab.copy(); given[int(noise[0])] = 0
+    assert oracle.check_border(pts, eps, core, given) == 1
+
+
 # ---- brute vs grid enumeration ------------------------------------------------
 
 @pytest.mark.parametrize("dim,n,eps,min_pts,seed", [
