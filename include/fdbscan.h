@@ -29,7 +29,8 @@
  *     outputs and the workspace;
  *   - no call aborts, exits or throws; errors are returned as fdb_status and
  *     leave the outputs untouched when detected before any launch;
- *   - a handle is used by one host thread at a time.
+ *   - a handle is used by one host thread at a time; a call that finds another
+ *     thread inside a call on the same handle returns FDB_ERR_BUSY at once.
  */
 #ifndef FDBSCAN_H
 #define FDBSCAN_H
@@ -51,7 +52,8 @@ typedef enum {
   FDB_ERR_NOMEM = 2,     /* workspace too small, or the handle could not allocate one */
   FDB_ERR_HIP = 3,       /* a HIP runtime call failed */
   FDB_ERR_NONFINITE = 4, /* a coordinate is NaN or infinite (reported when the call waits) */
-  FDB_ERR_INTERNAL = 5   /* a kernel's own consistency check failed (reported when the call waits) */
+  FDB_ERR_INTERNAL = 5,  /* a kernel's own consistency check failed (reported when the call waits) */
+  FDB_ERR_BUSY = 6       /* another host thread is inside a call on the same handle */
 } fdb_status;
 
 typedef enum {
@@ -60,8 +62,7 @@ typedef enum {
   /* Choose per input (Sections 5-6 leave the choice to a rule of thumb). Measured
      here, DenseBox is never more than ~15% slower than FDbscan (sparse data with
      no dense cells) and up to 20x faster, and the share of points in dense cells
-     does not predict the rare cases FDbscan wins; so the choice is DenseBox,
-     and FDbscan when the grid cannot be keyed (FDB_INFO_AUTO_FDBSCAN then).
+     does not predict the rare cases FDbscan wins; so the choice is DenseBox.
      Batches (fdb_dbscan_batched) run DenseBox. */
   FDB_ALGO_AUTO = 2
 } fdb_algo;
@@ -82,23 +83,43 @@ typedef enum {
   FDB_BORDER_NONE = 2
 } fdb_border;
 
+/* Launch-shape parameters (leaf_size, block_size, tile) left at 0 take the
+   handle's tuned value for the call's shape when fdb_tune has stored one (see
+   fdb_tune), else the built-in default. None of them changes any label. */
 typedef struct {
   int32_t algo;       /* fdb_algo */
   int32_t border;     /* fdb_border */
-  int32_t leaf_size;  /* traversal: subtrees of <= leaf_size primitives are scanned linearly; 0 = default (8) */
-  int32_t block_size; /* threads per workgroup of the traversal kernels (64..1024, multiple of 64); 0 = default (128) */
-  uint32_t flags;     /* reserved, must be 0 */
-} fdb_options;        /* all-zero = FDbscan, canonical labels, defaults */
+  int32_t leaf_size;  /* traversal: subtrees of <= leaf_size primitives are scanned linearly (1..1024);
+                         0 = tuned or default (8) */
+  int32_t block_size; /* threads per workgroup of the traversal kernels (64..1024, multiple of 64);
+                         0 = tuned or default (128) */
+  int32_t tile;       /* traversal tile of the wavefront packet walks: candidates loaded per step, one
+                         per lane (8..64); 0 = tuned or default (64) */
+  uint32_t flags;     /* FDB_FLAG_* bits */
+} fdb_options;        /* all-zero = FDbscan, canonical labels, tuned or default launch shape */
+
+enum {
+  /* Record the call's whole launch sequence once as a HIP graph (per handle, keyed
+     by every argument but the stream) and replay it on later calls with the same
+     arguments: one graph launch instead of ~40 kernel launches. The graph holds
+     the buffers' addresses, so it is replayed only for exactly the same pointers,
+     sizes and parameters; anything else records a new one (the handle keeps the
+     16 most recent). Results are those of the plain call. */
+  FDB_FLAG_GRAPH = 1u
+};
 
 /* Information bits, read with fdb_last_info(). */
 enum {
-  FDB_INFO_DENSEBOX_FALLBACK = 1u, /* DenseBox asked for, but the grid could not be indexed in 64-bit
-                                      keys (eps tiny against the extent): FDbscan ran instead. */
+  FDB_INFO_DENSEBOX_FALLBACK = 1u, /* DenseBox (or the automatic choice): the eps/sqrt(d) grid needs more
+                                      cells per axis than 64-bit keys hold (eps tiny against the extent),
+                                      so the cells were widened to fit; density is still decided by the
+                                      exact guard, labels are exact, fewer cells come out dense. */
   FDB_INFO_NONFINITE = 2u,         /* a NaN or infinite coordinate was seen; labels are undefined */
   FDB_INFO_INTERNAL = 4u,          /* a kernel stopped a walk that broke its own bounds; labels undefined */
   FDB_INFO_BAD_PARAMS = 8u,        /* batch: some cloud's eps is not finite and > 0, or its minPts < 1;
                                       that cloud's labels are undefined */
-  FDB_INFO_AUTO_FDBSCAN = 16u       /* FDB_ALGO_AUTO could not key the grid and ran FDbscan */
+  FDB_INFO_AUTO_FDBSCAN = 16u      /* no longer raised: the automatic choice always runs DenseBox (a grid
+                                      too wide for 64-bit keys raises FDB_INFO_DENSEBOX_FALLBACK) */
 };
 
 /* Create a handle bound to HIP device `device`. *out receives the handle. */
@@ -128,8 +149,11 @@ fdb_status fdb_workspace_bytes(int64_t n, int32_t dim, const fdb_options* opt, s
  *   workspace  device buffer of >= fdb_workspace_bytes() bytes, or NULL: then the
  *              handle allocates (and keeps, growing it when needed) its own.
  *   stream     hipStream_t the work is ordered on.
- * DenseBox reads the scene bounds back to the host once (it sizes the grid from
- * them), so with algo = FDB_ALGO_DENSEBOX the call waits for the stream midway.
+ * With h_num_clusters = NULL nothing waits for the GPU, for either algorithm
+ * (DenseBox sizes its grid on the device), so the call can be recorded into a
+ * HIP graph by stream capture; errors found on the device are then read with
+ * fdb_last_status. The workspace is the caller's (or, when NULL, the handle's):
+ * too small a caller workspace gives FDB_ERR_NOMEM before any launch.
  */
 fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
                       const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
@@ -199,13 +223,21 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
                                    const fdb_options* opt, size_t device_budget_bytes, int32_t* h_labels,
                                    uint8_t* h_is_core, int32_t* h_num_clusters);
 
-/* Wait for the stream of the last fdb_dbscan call on h and return its FDB_INFO_* bits. */
+/* Device-side status of the last call on h: waits for `stream` (the stream that
+   call was ordered on, or one ordered after it) and returns its FDB_INFO_* bits in
+   *h_info. Returns FDB_ERR_NONFINITE or FDB_ERR_INTERNAL when those bits say the
+   labels are undefined, else FDB_OK (also FDB_ERR_HIP, FDB_ERR_INVALID). */
+fdb_status fdb_last_status(fdb_handle* h, hipStream_t stream, uint32_t* h_info);
+
+/* fdb_last_status on the stream of the last call, returning FDB_OK whatever the
+   bits say (kept for earlier callers). */
 fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info);
 
-/* Wait for the stream of the last fdb_dbscan call on h and report its sizes, for
-   cost models: h_counts[0] = K (clusters), [1] = non-empty grid cells, [2] = dense
-   cells, [3] = BVH primitives (dense cells + points outside them; n for FDbscan).
-   Entries 1-2 are 0 for FDbscan. The workspace of that call must still be alive. */
+/* Wait for the stream of the last fdb_dbscan (or fdb_dbscan_batched) call on h and
+   report its sizes, for cost models: h_counts[0] = K (clusters; a batch: summed over
+   its clouds), [1] = non-empty grid cells, [2] = dense cells, [3] = BVH primitives
+   (dense cells + points outside them; n for FDbscan). Entries 1-2 are 0 for FDbscan.
+   The workspace of that call must still be alive. */
 fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts);
 
 /* Per-stage GPU timing. With timing enabled, fdb_dbscan records a HIP event pair
@@ -300,6 +332,36 @@ fdb_status fdb_server_drain(fdb_server* s);
 fdb_status fdb_server_stats(fdb_server* s, int64_t first_ticket, fdb_serve_stats* h_out);
 /* Run every queued job, stop the worker and free the server's memory. */
 void fdb_server_destroy(fdb_server* s);
+
+/*
+ * Autotuner for the launch shape (leaf_size, block_size, tile of fdb_options;
+ * none of them changes any label). Times the call on the caller's own input:
+ * first the default shape, then coordinate descent over leaf_size in {4, 8, 16,
+ * 32}, block_size in {64, 128, 256} and tile in {32, 64}, each shape timed as the
+ * median of `reps` (1..100) runs after one warm-up, with HIP events on `stream`.
+ * The fastest shape is kept in the handle for the call's class - algorithm
+ * (the automatic choice counts as DenseBox), dim, floor(log2 n), minPts <= 2 or
+ * not, and for fdb_tune_batched a batch flag with n = n_total - so later calls of
+ * that class with 0 in those fields take it. If the environment variable
+ * FDB_TUNE_CACHE names a file, the result is appended to it as one text line,
+ * and fdb_create reads the file back (later lines win). Arguments are those of
+ * fdb_dbscan / fdb_dbscan_batched (the outputs receive the labels of the last
+ * run); *h_best receives the chosen options, h_ms[0] their time and h_ms[1] the
+ * default shape's time, in ms. Synchronous. FDB_ERR_INVALID also for n < 1.
+ */
+fdb_status fdb_tune(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                    const fdb_options* opt, int32_t reps, int32_t* labels, uint8_t* is_core, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream, fdb_options* h_best, double* h_ms);
+fdb_status fdb_tune_batched(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                            int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                            const fdb_options* opt, int32_t reps, int32_t* labels, uint8_t* is_core,
+                            int32_t* num_clusters, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                            fdb_options* h_best, double* h_ms);
+/* The options a call would run with: opt (NULL = all-zero) with the launch-shape
+   fields left at 0 filled from the handle's tuned table (num_clouds = 0 for
+   fdb_dbscan, else the batch's cloud count), then from the built-in defaults. */
+fdb_status fdb_tuned_options(fdb_handle* h, int64_t n, int32_t dim, int32_t min_pts, int32_t num_clouds,
+                             const fdb_options* opt, fdb_options* h_out);
 
 /* Static description of a status code. */
 const char* fdb_status_string(fdb_status s);

@@ -7,13 +7,14 @@ include/fdbscan.h); this package marshals torch tensors into that ABI.
 """
 from __future__ import annotations
 
-from ._lib import (FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS, FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL,
-                   FDB_INFO_NONFINITE, FdbError,
-                   Handle, Server, load, make_options, status_string, workspace_bytes, workspace_bytes_batched)
+from ._lib import (FDB_ERR_BUSY, FDB_FLAG_GRAPH, FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS,
+                   FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError, Handle, Server, load,
+                   make_options, options_dict, status_string, workspace_bytes, workspace_bytes_batched)
 
-__all__ = ["dbscan", "dbscan_batched", "dbscan_batched_host", "Handle", "Server", "FdbError", "workspace_bytes", "workspace_bytes_batched",
-           "default_handle", "load", "make_options", "status_string", "FDB_INFO_DENSEBOX_FALLBACK",
-           "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL", "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN"]
+__all__ = ["dbscan", "dbscan_batched", "dbscan_batched_host", "tune", "tune_batched", "Handle", "Server", "FdbError",
+           "workspace_bytes", "workspace_bytes_batched", "default_handle", "load", "make_options", "options_dict",
+           "status_string", "FDB_INFO_DENSEBOX_FALLBACK", "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL",
+           "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN", "FDB_FLAG_GRAPH", "FDB_ERR_BUSY"]
 
 _handles: dict[int, Handle] = {}
 
@@ -37,13 +38,15 @@ def _check_out(labels, is_core, n):
 
 def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str = "canonical",
            leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
-           want_k: bool = True, workspace=None):
+           want_k: bool = True, workspace=None, tile: int = 0, graph: bool = False):
     """Cluster points ([n, 2] or [n, 3] float32 torch tensor on a HIP device).
 
     Returns (labels int32 [n], is_core bool [n], K). labels are in input order:
     -1 noise, else a cluster id 0..K-1 (canonical order unless border="first";
     border="none" is DBSCAN*: every non-core point is noise).
     K is None when want_k is False (then the call does not wait for the GPU).
+    graph=True replays a recorded HIP graph of the launch sequence for repeated
+    calls with the same buffers and parameters.
     """
     import torch
 
@@ -60,7 +63,7 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     if is_core is None:
         is_core = torch.empty(n, dtype=torch.uint8, device=pts.device)
     _check_out(labels, is_core, n)
-    opt = make_options(algo, border, leaf_size, block_size)
+    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph)
     stream = torch.cuda.current_stream(pts.device).cuda_stream
     ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
         else (None, 0)
@@ -71,7 +74,7 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
 
 def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border: str = "canonical",
                    leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
-                   num_clusters=None, workspace=None):
+                   num_clusters=None, workspace=None, tile: int = 0, graph: bool = False):
     """Cluster a batch of clouds in one launch sequence.
 
     points: [N, d] float32 on a HIP device (clouds concatenated); offsets: int64
@@ -103,7 +106,7 @@ def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border:
     _check_out(labels, is_core, n)
     if num_clusters is None:
         num_clusters = torch.empty(b, dtype=torch.int32, device=dev)
-    opt = make_options(algo, border, leaf_size, block_size)
+    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph)
     stream = torch.cuda.current_stream(dev).cuda_stream
     ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
         else (None, 0)
@@ -157,3 +160,51 @@ def dbscan_batched_host(points, offsets, eps, min_pts, budget_bytes: int, algo: 
                               mp.ctypes.data, int(budget_bytes), lab.ctypes.data if n else 0,
                               core.ctypes.data if n else 0, k.ctypes.data, opt)
     return lab, core, k
+
+
+def tune(points, eps: float, min_pts: int, algo: str = "densebox", border: str = "canonical", reps: int = 3,
+         handle: Handle | None = None, workspace=None):
+    """fdb_tune on a torch tensor: times launch shapes on this input and keeps the
+    fastest in the handle (and in the FDB_TUNE_CACHE file, if set) for later calls
+    of the same class. Returns (options dict, best ms, default-shape ms)."""
+    import torch
+
+    pts = points.contiguous()
+    n, d = pts.shape
+    dev = pts.device.index if pts.device.index is not None else torch.cuda.current_device()
+    h = handle if handle is not None else default_handle(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=pts.device)
+    core = torch.empty(n, dtype=torch.uint8, device=pts.device)
+    stream = torch.cuda.current_stream(pts.device).cuda_stream
+    ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
+        else (None, 0)
+    best, ms, ms0 = h.tune_raw(pts.data_ptr(), n, d, eps, min_pts, labels.data_ptr(), core.data_ptr(), stream,
+                               make_options(algo, border), reps, ws_ptr, ws_size)
+    return options_dict(best), ms, ms0
+
+
+def tune_batched(points, offsets, eps, min_pts, algo: str = "densebox", border: str = "canonical", reps: int = 3,
+                 handle: Handle | None = None, workspace=None):
+    """fdb_tune_batched on torch tensors (as dbscan_batched). Returns (options dict,
+    best ms, default-shape ms)."""
+    import torch
+
+    pts = points.contiguous()
+    n, d = pts.shape
+    dev = pts.device
+    offs = offsets.to(device=dev, dtype=torch.int64).contiguous()
+    b = offs.numel() - 1
+    e = eps.to(device=dev, dtype=torch.float32).contiguous()
+    mp = min_pts.to(device=dev, dtype=torch.int32).contiguous()
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    h = handle if handle is not None else default_handle(idx)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    core = torch.empty(n, dtype=torch.uint8, device=dev)
+    ncl = torch.empty(b, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
+        else (None, 0)
+    best, ms, ms0 = h.tune_batched_raw(pts.data_ptr(), n, offs.data_ptr(), b, d, e.data_ptr(), mp.data_ptr(),
+                                       labels.data_ptr(), core.data_ptr(), ncl.data_ptr(), stream,
+                                       make_options(algo, border), reps, ws_ptr, ws_size)
+    return options_dict(best), ms, ms0

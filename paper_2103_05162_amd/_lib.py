@@ -12,11 +12,12 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdbscan.so")
 
-FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL = range(6)
+FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL, FDB_ERR_BUSY = range(7)
 FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX, FDB_ALGO_AUTO = 0, 1, 2
 FDB_BORDER_CANONICAL, FDB_BORDER_FIRST, FDB_BORDER_NONE = 0, 1, 2
 FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FDB_INFO_INTERNAL, FDB_INFO_BAD_PARAMS = 1, 2, 4, 8
 FDB_INFO_AUTO_FDBSCAN = 16
+FDB_FLAG_GRAPH = 1
 
 ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX, "auto": FDB_ALGO_AUTO}
 BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST, "none": FDB_BORDER_NONE}
@@ -24,7 +25,7 @@ BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST, "none":
 
 class FdbOptions(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("border", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("block_size", ctypes.c_int32), ("tile", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class FdbJob(ctypes.Structure):
@@ -88,6 +89,15 @@ def load() -> ctypes.CDLL:
     lib.fdb_dbscan_batched_host.restype = ctypes.c_int
     lib.fdb_last_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.fdb_last_info.restype = ctypes.c_int
+    lib.fdb_last_status.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_uint32)]
+    lib.fdb_last_status.restype = ctypes.c_int
+    po, pd = ctypes.POINTER(FdbOptions), ctypes.POINTER(ctypes.c_double)
+    lib.fdb_tune.argtypes = [vp, vp, i64, i32, ctypes.c_float, i32, po, i32, vp, vp, vp, sz, vp, po, pd]
+    lib.fdb_tune.restype = ctypes.c_int
+    lib.fdb_tune_batched.argtypes = [vp, vp, i64, vp, i32, i32, vp, vp, po, i32, vp, vp, vp, vp, sz, vp, po, pd]
+    lib.fdb_tune_batched.restype = ctypes.c_int
+    lib.fdb_tuned_options.argtypes = [vp, i64, i32, i32, i32, po, po]
+    lib.fdb_tuned_options.restype = ctypes.c_int
     lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fdb_last_counts.restype = ctypes.c_int
     pi32 = ctypes.POINTER(i32)
@@ -125,10 +135,15 @@ def _check(status: int, what: str) -> None:
         raise FdbError(status, what)
 
 
-def make_options(algo="fdbscan", border="canonical", leaf_size=0, block_size=0, flags=0) -> FdbOptions:
+def make_options(algo="fdbscan", border="canonical", leaf_size=0, block_size=0, flags=0, tile=0,
+                 graph=False) -> FdbOptions:
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     b = BORDERS[border] if isinstance(border, str) else int(border)
-    return FdbOptions(a, b, int(leaf_size), int(block_size), int(flags))
+    return FdbOptions(a, b, int(leaf_size), int(block_size), int(tile), int(flags) | (FDB_FLAG_GRAPH if graph else 0))
+
+
+def options_dict(o: FdbOptions) -> dict:
+    return {k: int(getattr(o, k)) for k, _ in FdbOptions._fields_}
 
 
 def workspace_bytes_batched(n_total: int, num_clouds: int, dim: int, algo="fdbscan") -> int:
@@ -211,6 +226,52 @@ class Handle:
         v = ctypes.c_uint32(0)
         _check(self._lib.fdb_last_info(self.ptr, ctypes.byref(v)), "fdb_last_info")
         return int(v.value)
+
+    def last_status(self, stream: int):
+        """(status, FDB_INFO_* bits) of the last call, waiting for `stream`."""
+        v = ctypes.c_uint32(0)
+        st = self._lib.fdb_last_status(self.ptr, ctypes.c_void_p(stream), ctypes.byref(v))
+        return int(st), int(v.value)
+
+    def tune_raw(self, points_ptr: int, n: int, dim: int, eps: float, min_pts: int, labels_ptr: int,
+                 core_ptr: int | None, stream: int, options: FdbOptions | None = None, reps: int = 3,
+                 workspace_ptr: int | None = None, workspace_size: int = 0):
+        """fdb_tune: returns (best options, best ms, default ms)."""
+        best = FdbOptions()
+        ms = (ctypes.c_double * 2)()
+        vp = ctypes.c_void_p
+        st = self._lib.fdb_tune(self.ptr, vp(points_ptr), int(n), int(dim), ctypes.c_float(eps), int(min_pts),
+                                ctypes.byref(options) if options is not None else None, int(reps), vp(labels_ptr),
+                                vp(core_ptr) if core_ptr else None, vp(workspace_ptr) if workspace_ptr else None,
+                                int(workspace_size), vp(stream), ctypes.byref(best), ms)
+        _check(st, "fdb_tune")
+        return best, float(ms[0]), float(ms[1])
+
+    def tune_batched_raw(self, points_ptr: int, n_total: int, offsets_ptr: int, num_clouds: int, dim: int,
+                         eps_ptr: int, min_pts_ptr: int, labels_ptr: int, core_ptr: int | None,
+                         num_clusters_ptr: int | None, stream: int, options: FdbOptions | None = None, reps: int = 3,
+                         workspace_ptr: int | None = None, workspace_size: int = 0):
+        """fdb_tune_batched: returns (best options, best ms, default ms)."""
+        best = FdbOptions()
+        ms = (ctypes.c_double * 2)()
+        vp = ctypes.c_void_p
+        st = self._lib.fdb_tune_batched(self.ptr, vp(points_ptr), int(n_total), vp(offsets_ptr), int(num_clouds),
+                                        int(dim), vp(eps_ptr), vp(min_pts_ptr),
+                                        ctypes.byref(options) if options is not None else None, int(reps),
+                                        vp(labels_ptr), vp(core_ptr) if core_ptr else None,
+                                        vp(num_clusters_ptr) if num_clusters_ptr else None,
+                                        vp(workspace_ptr) if workspace_ptr else None, int(workspace_size),
+                                        vp(stream), ctypes.byref(best), ms)
+        _check(st, "fdb_tune_batched")
+        return best, float(ms[0]), float(ms[1])
+
+    def tuned_options(self, n: int, dim: int, min_pts: int, num_clouds: int = 0,
+                      options: FdbOptions | None = None) -> FdbOptions:
+        out = FdbOptions()
+        _check(self._lib.fdb_tuned_options(self.ptr, int(n), int(dim), int(min_pts), int(num_clouds),
+                                           ctypes.byref(options) if options is not None else None,
+                                           ctypes.byref(out)), "fdb_tuned_options")
+        return out
 
     def last_counts(self) -> dict:
         """Sizes of the last call: clusters, grid cells, dense cells, BVH primitives."""

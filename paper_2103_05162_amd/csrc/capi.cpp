@@ -11,7 +11,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -41,6 +44,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   };
   p.bounds = take(8 * sizeof(uint32_t));
   p.misc = take(kMiscCount * sizeof(int));
+  p.gplan = take(sizeof(GridPlan));
   p.keys0 = take(N * 8);
   p.keys1 = take(N * 8);
   p.vals0 = take(N * 4);
@@ -109,6 +113,20 @@ struct StageRec {
   hipEvent_t a, b;
 };
 
+// A recorded launch sequence: the call's arguments (every pointer, size and
+// parameter but the stream) and the executable graph replaying it.
+struct GraphRec {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec;
+};
+
+// One autotuner result: the launch shape measured fastest for calls of this class.
+struct TuneEntry {
+  int32_t batched, algo, dim, nlog2, mpclass;  // the class
+  int32_t leaf_size, block_size, tile;         // its shape
+  double best_ms, default_ms, dense_share;     // what the tuner measured
+};
+
 }  // namespace fdb
 
 struct fdb_handle {
@@ -128,6 +146,10 @@ struct fdb_handle {
   std::vector<std::string> names;      // accumulated stage names (static strings)
   std::vector<double> ms;
   std::vector<hipEvent_t> event_pool;
+  std::atomic<int> busy{0};             // a host thread is inside a call (FDB_ERR_BUSY for another)
+  hipStream_t cap_stream = nullptr;     // stream that graph recordings are captured on
+  std::vector<fdb::GraphRec> graphs;    // recorded launch sequences, most recent last
+  std::vector<fdb::TuneEntry> tune;     // launch shapes chosen by fdb_tune (and the tune cache file)
 };
 
 namespace {
@@ -158,14 +180,16 @@ hipEvent_t take_event(fdb_handle* h) {
 }
 
 // Marks the start of a named stage; the previous stage (if any) ends there.
+// Off while a launch sequence is recorded into a graph.
 struct Stager {
   fdb_handle* h;
   hipStream_t s;
+  bool on;
   const char* cur = nullptr;
   hipEvent_t cur_a = nullptr;
-  Stager(fdb_handle* hh, hipStream_t ss) : h(hh), s(ss) {}
+  Stager(fdb_handle* hh, hipStream_t ss, bool enable) : h(hh), s(ss), on(enable) {}
   void mark(const char* name) {
-    if (!h->timing) return;
+    if (!on) return;
     hipEvent_t e = take_event(h);
     if (!e) return;
     (void)hipEventRecord(e, s);
@@ -180,7 +204,7 @@ struct Stager {
     cur_a = e;
   }
   void finish() {
-    if (!h->timing || !cur) return;
+    if (!on || !cur) return;
     hipEvent_t e2 = take_event(h);
     if (e2) {
       (void)hipEventRecord(e2, s);
@@ -214,12 +238,187 @@ bool valid_options(const fdb_options& o) {
   if (o.border != FDB_BORDER_CANONICAL && o.border != FDB_BORDER_FIRST && o.border != FDB_BORDER_NONE) return false;
   if (o.leaf_size < 0 || o.leaf_size > 1024) return false;
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64 != 0)) return false;
-  if (o.flags != 0) return false;
+  if (o.tile != 0 && (o.tile < 8 || o.tile > 64)) return false;
+  if (o.flags & ~uint32_t(FDB_FLAG_GRAPH)) return false;
   return true;
 }
 
 constexpr int kDefaultLeaf = 8;     // measured against 2, 4, 6 and 16 (8M set and the 4096-cloud batch)
 constexpr int kDefaultBlock = 128;  // measured against 64, 256 and 512
+constexpr int kDefaultTile = 64;    // packet bucket: a candidate per lane (measured against 32)
+constexpr size_t kMaxGraphs = 16;
+
+// One host thread per handle: a second one gets FDB_ERR_BUSY instead of racing.
+struct CallGuard {
+  fdb_handle* h;
+  bool ok;
+  explicit CallGuard(fdb_handle* hh) : h(hh) {
+    int expected = 0;
+    ok = h->busy.compare_exchange_strong(expected, 1);
+  }
+  ~CallGuard() {
+    if (ok) h->busy.store(0);
+  }
+};
+
+struct SingleArgs {
+  const float* points;
+  int64_t n;
+  int32_t dim;
+  float eps;
+  int32_t min_pts;
+  int32_t* labels;
+  uint8_t* is_core;
+};
+
+struct BatchArgs {
+  const float* points;
+  int64_t n_total;
+  const int64_t* offsets;
+  int32_t num_clouds;
+  int32_t dim;
+  const float* eps;
+  const int32_t* min_pts;
+  int32_t* labels;
+  uint8_t* is_core;
+  int32_t* num_clusters;
+};
+
+using CallKey = std::vector<uint64_t>;
+
+uint64_t ptr_word(const void* p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); }
+
+uint64_t float_word(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+void options_words(CallKey& k, const fdb_options& o) {
+  k.push_back(uint64_t(uint32_t(o.algo)) | uint64_t(uint32_t(o.border)) << 32);
+  k.push_back(uint64_t(uint32_t(o.leaf_size)) | uint64_t(uint32_t(o.block_size)) << 32);
+  k.push_back(uint64_t(uint32_t(o.tile)) | uint64_t(o.flags) << 32);
+}
+
+CallKey single_key(const SingleArgs& a, const fdb_options& o, const void* ws, size_t ws_bytes) {
+  CallKey k{1, ptr_word(a.points), uint64_t(a.n), uint64_t(uint32_t(a.dim)), float_word(a.eps),
+            uint64_t(uint32_t(a.min_pts)), ptr_word(a.labels), ptr_word(a.is_core), ptr_word(ws), ws_bytes};
+  options_words(k, o);
+  return k;
+}
+
+CallKey batch_key(const BatchArgs& a, const fdb_options& o, const void* ws, size_t ws_bytes) {
+  CallKey k{2, ptr_word(a.points), uint64_t(a.n_total), ptr_word(a.offsets), uint64_t(uint32_t(a.num_clouds)),
+            uint64_t(uint32_t(a.dim)), ptr_word(a.eps), ptr_word(a.min_pts), ptr_word(a.labels), ptr_word(a.is_core),
+            ptr_word(a.num_clusters), ptr_word(ws), ws_bytes};
+  options_words(k, o);
+  return k;
+}
+
+void drop_graphs(fdb_handle* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
+// Replays the graph recorded for `key` on `stream`, recording it first (by stream
+// capture of launch(cs) on the handle's capture stream) if there is none.
+template <typename F>
+fdb_status run_graph(fdb_handle* h, const CallKey& key, hipStream_t stream, F&& launch) {
+  size_t k = 0;
+  while (k < h->graphs.size() && h->graphs[k].key != key) ++k;
+  if (k == h->graphs.size()) {
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      h->cap_stream = nullptr;
+      return FDB_ERR_HIP;
+    }
+    hipStream_t cs = h->cap_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return FDB_ERR_HIP;
+    const fdb_status st = launch(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (st != FDB_OK || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return st != FDB_OK ? st : FDB_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess || !exec) return FDB_ERR_HIP;
+    if (h->graphs.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(h->graphs.front().exec);
+      h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back({key, exec});
+    k = h->graphs.size() - 1;
+  }
+  return hipGraphLaunch(h->graphs[k].exec, stream) == hipSuccess ? FDB_OK : FDB_ERR_HIP;
+}
+
+// The caller's workspace (checked against the plan), or the handle's own, grown
+// when needed (which drops the graphs recorded over the old one).
+fdb_status take_workspace(fdb_handle* h, const fdb::Plan& plan, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream, void** out) {
+  if (workspace) {
+    if (workspace_bytes < plan.bytes) return FDB_ERR_NOMEM;
+    *out = workspace;
+    return FDB_OK;
+  }
+  if (h->ws_bytes < plan.bytes) {
+    if (h->ws) {
+      if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
+      if (h->cap_stream && hipStreamSynchronize(h->cap_stream) != hipSuccess) return FDB_ERR_HIP;
+      if (hipDeviceSynchronize() != hipSuccess) return FDB_ERR_HIP;  // graphs replayed on other streams
+      drop_graphs(h);
+      (void)hipFree(h->ws);
+      h->ws = nullptr;
+      h->ws_bytes = 0;
+    }
+    if (hipMalloc(&h->ws, plan.bytes) != hipSuccess) return FDB_ERR_NOMEM;
+    h->ws_bytes = plan.bytes;
+  }
+  *out = h->ws;
+  return FDB_OK;
+}
+
+int nlog2_of(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+int mpclass_of(int32_t min_pts) { return min_pts <= 2 ? 0 : 1; }
+
+const fdb::TuneEntry* find_tune(const fdb_handle* h, int batched, int algo, int dim, int64_t n, int mpclass) {
+  const int nl = nlog2_of(n);
+  for (const auto& e : h->tune)
+    if (e.batched == batched && e.algo == algo && e.dim == dim && e.nlog2 == nl && e.mpclass == mpclass) return &e;
+  return nullptr;
+}
+
+// Launch-shape fields left at 0 take the tuned value for the call's class.
+void resolve_shape(const fdb_handle* h, fdb_options& o, int64_t n, int dim, int num_clouds, int32_t min_pts = 3) {
+  if (o.leaf_size && o.block_size && o.tile) return;
+  const int algo = o.algo == FDB_ALGO_FDBSCAN ? FDB_ALGO_FDBSCAN : FDB_ALGO_DENSEBOX;
+  const fdb::TuneEntry* e = find_tune(h, num_clouds > 0, algo, dim, n, num_clouds > 0 ? 1 : mpclass_of(min_pts));
+  if (!e) return;
+  if (!o.leaf_size) o.leaf_size = e->leaf_size;
+  if (!o.block_size) o.block_size = e->block_size;
+  if (!o.tile) o.tile = e->tile;
+}
+
+fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_options& o, const fdb::Plan& plan, void* ws,
+                         hipStream_t stream, bool timing);
+fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_options& o, const fdb::Plan& plan, void* ws,
+                          hipStream_t stream, bool timing);
+fdb_status dbscan_batched_entry(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                                int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                                const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream);
+void load_tune_file(fdb_handle* h);
+fdb_status dbscan_entry(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                        const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 template <typename T>
 T* at(void* base, size_t off) {
@@ -238,6 +437,7 @@ const char* fdb_status_string(fdb_status s) {
     case FDB_ERR_HIP: return "HIP runtime error";
     case FDB_ERR_NONFINITE: return "non-finite coordinate";
     case FDB_ERR_INTERNAL: return "internal consistency check failed";
+    case FDB_ERR_BUSY: return "another thread is inside a call on this handle";
   }
   return "unknown status";
 }
@@ -261,6 +461,7 @@ fdb_status fdb_create(fdb_handle** out, int device) {
     delete h;
     return FDB_ERR_NOMEM;
   }
+  load_tune_file(h);
   *out = h;
   return FDB_OK;
 }
@@ -274,6 +475,8 @@ void fdb_destroy(fdb_handle* h) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : h->event_pool) (void)hipEventDestroy(e);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_info) (void)hipFree(h->d_info);
   if (h->h_pinned) (void)hipHostFree(h->h_pinned);
@@ -289,14 +492,22 @@ fdb_status fdb_workspace_bytes(int64_t n, int32_t dim, const fdb_options* opt, s
   return FDB_OK;
 }
 
-fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info) {
+fdb_status fdb_last_status(fdb_handle* h, hipStream_t stream, uint32_t* h_info) {
   if (!h || !h_info) return FDB_ERR_INVALID;
   DeviceGuard g(h->device);
-  if (hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, h->last_stream) != hipSuccess)
+  if (hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, stream) != hipSuccess)
     return FDB_ERR_HIP;
-  if (hipStreamSynchronize(h->last_stream) != hipSuccess) return FDB_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
   *h_info = h->h_pinned[8] | h->host_info;
+  if (*h_info & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
+  if (*h_info & FDB_INFO_INTERNAL) return FDB_ERR_INTERNAL;
   return FDB_OK;
+}
+
+fdb_status fdb_last_info(fdb_handle* h, uint32_t* h_info) {
+  if (!h || !h_info) return FDB_ERR_INVALID;
+  const fdb_status st = fdb_last_status(h, h->last_stream, h_info);
+  return st == FDB_ERR_NONFINITE || st == FDB_ERR_INTERNAL ? FDB_OK : st;
 }
 
 fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts) {
@@ -405,8 +616,21 @@ fdb_status fdb_stage_times(fdb_handle* h, int32_t max, const char** h_names, dou
 fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
                       const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
                       void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  using namespace fdb;
   if (!h) return FDB_ERR_INVALID;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
+  return dbscan_entry(h, points, n, dim, eps, min_pts, opt, labels, is_core, h_num_clusters, workspace,
+                      workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+fdb_status dbscan_entry(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                        const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace fdb;
   fdb_options o{};
   if (opt) o = *opt;
   if (!valid_options(o)) return FDB_ERR_INVALID;
@@ -421,33 +645,58 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
     if (h_num_clusters) *h_num_clusters = 0;
     return FDB_OK;
   }
+  resolve_shape(h, o, n, dim, 0, min_pts);
+  const Plan plan = make_plan(n, dim, o.algo);
+  void* ws = nullptr;
+  const fdb_status wst = take_workspace(h, plan, workspace, workspace_bytes, stream, &ws);
+  if (wst != FDB_OK) return wst;
+  const SingleArgs args{points, n, dim, eps, min_pts, labels, is_core};
+  fdb_status st;
+  if (o.flags & FDB_FLAG_GRAPH) {
+    const CallKey key = single_key(args, o, ws, plan.bytes);
+    st = run_graph(h, key, stream, [&](hipStream_t cs) { return dbscan_launch(h, args, o, plan, ws, cs, false); });
+    h->last_misc = at<int>(ws, plan.misc);
+    h->last_densebox = o.algo != FDB_ALGO_FDBSCAN;
+    h->last_n = n;
+  } else {
+    st = dbscan_launch(h, args, o, plan, ws, stream, h->timing);
+  }
+  if (st != FDB_OK) return st;
+  if (h_num_clusters) {
+    if (hipMemcpyAsync(h->h_pinned, at<int>(ws, plan.misc) + kMiscNumClusters, 4, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return FDB_ERR_HIP;
+    *h_num_clusters = static_cast<int32_t>(h->h_pinned[0]);
+    if (h->h_pinned[8] & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
+    if (h->h_pinned[8] & FDB_INFO_INTERNAL) return FDB_ERR_INTERNAL;
+  }
+  return FDB_OK;
+}
+
+// The launch sequence of one clustering call: stream-ordered launches only (no
+// allocation, no host wait), so a stream capture can record it.
+fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_options& o, const fdb::Plan& plan, void* ws,
+                         hipStream_t stream, bool timing) {
+  using namespace fdb;
+  const float* points = args.points;
+  const int64_t n = args.n;
+  const int dim = args.dim;
+  const float eps = args.eps;
+  const int min_pts = args.min_pts;
+  int32_t* labels = args.labels;
+  uint8_t* is_core = args.is_core;
   const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
   const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
-  bool densebox = o.algo != FDB_ALGO_FDBSCAN;
-  const bool auto_algo = o.algo == FDB_ALGO_AUTO;
+  const int tile = o.tile > 0 ? o.tile : kDefaultTile;
+  const bool densebox = o.algo != FDB_ALGO_FDBSCAN;  // the automatic choice is DenseBox
   const bool first_border = o.border == FDB_BORDER_FIRST;
-  const Plan plan = make_plan(n, dim, o.algo);
-  void* ws = workspace;
-  if (ws) {
-    if (workspace_bytes < plan.bytes) return FDB_ERR_NOMEM;
-  } else {
-    if (h->ws_bytes < plan.bytes) {
-      if (h->ws) {
-        if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
-        (void)hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_bytes = 0;
-      }
-      if (hipMalloc(&h->ws, plan.bytes) != hipSuccess) return FDB_ERR_NOMEM;
-      h->ws_bytes = plan.bytes;
-    }
-    ws = h->ws;
-  }
   (void)hipGetLastError();
   const float eps2 = eps * eps;
   hipStream_t s = stream;
-  Stager st(h, s);
-  if (h->timing) ++h->timed_calls;
+  Stager st(h, s, timing);
+  if (timing) ++h->timed_calls;
 
   uint32_t* bounds = at<uint32_t>(ws, plan.bounds);
   int* misc = at<int>(ws, plan.misc);
@@ -466,47 +715,9 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   fill_u32(bounds + 4, 0u, 4, s);
   launch_bounds(points, n, dim, bounds, h->d_info, s);
 
-  GridParams gp{};
-  if (densebox) {
-    // The grid is sized on the host from the bounds: one read-back.
-    if (hipMemcpyAsync(h->h_pinned, bounds, 8 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return FDB_ERR_HIP;
-    if (h->h_pinned[8] & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
-    auto dec = [](uint32_t u) {
-      uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
-      float f;
-      std::memcpy(&f, &b, 4);
-      return f;
-    };
-    // cell side h = eps/sqrt(d), shrunk by 2^-20 so rounding in the cell index
-    // rarely pushes a cell's extent past h (the guard catches the rest)
-    const double side = static_cast<double>(eps) / std::sqrt(static_cast<double>(dim)) * (1.0 - 1.0 / 1048576.0);
-    int bits = 0;
-    bool ok = side > 0.0 && std::isfinite(side);
-    for (int k = 0; k < dim && ok; ++k) {
-      double ext = static_cast<double>(dec(h->h_pinned[4 + k])) - static_cast<double>(dec(h->h_pinned[k]));
-      double cells = std::floor(ext / side) + 1.0;
-      if (!(cells < 2147483648.0)) {
-        ok = false;
-        break;
-      }
-      gp.ncell[k] = static_cast<uint32_t>(cells);
-      gp.inv_h[k] = static_cast<float>(1.0 / side);
-      int b = 0;
-      while ((uint64_t(1) << b) < gp.ncell[k]) ++b;
-      bits = b > bits ? b : bits;
-    }
-    const int maxbits = dim == 3 ? 21 : 32;
-    if (!ok || bits > maxbits) {
-      densebox = false;
-      h->host_info |= auto_algo ? FDB_INFO_AUTO_FDBSCAN : FDB_INFO_DENSEBOX_FALLBACK;
-    } else {
-      gp.bits = bits;
-      gp.key64 = bits * dim > 32;
-    }
-  }
+  // DenseBox sizes its grid on the device (k_grid_plan): nothing waits for the GPU
+  GridPlan* gplan = at<GridPlan>(ws, plan.gplan);
+  if (densebox) launch_grid_plan(bounds, dim, eps, n, gplan, h->d_info, s);
 
   int cur = 0;
   const uint32_t* perm = nullptr;
@@ -515,7 +726,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.n = n;
   ta.eps2 = eps2;
   ta.packet_ext_eps2 = 9.0f;  // packet when the queries' box is at most 3 eps wide
-  ta.packet_leaf = 64;         // buckets of up to 64 candidates, one per lane (measured best)
+  ta.packet_leaf = tile;       // buckets of up to `tile` candidates, one per lane
   ta.min_pts = min_pts;
   ta.labels = lab;
   ta.core = core;
@@ -531,27 +742,28 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
 
   if (densebox) {
     st.mark("cell_keys");
-    launch_gridkeys(points, n, dim, bounds, gp.inv_h, gp.ncell, gp.bits, gp.key64, keys[0], vals[0], gp.bits * dim,
-                    at<uint32_t>(ws, plan.hist), s);
+    launch_gridkeys(points, n, dim, bounds, gplan, keys[0], keys[1], vals[0], vals[1], at<uint32_t>(ws, plan.hist), s);
     st.mark("sort");
-    cur = radix_sort(keys[0], keys[1], vals[0], vals[1], n, gp.key64, gp.bits * dim, at<uint32_t>(ws, plan.hist),
-                     true, at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status), h->d_info, s);
+    radix_sort_planned(keys[0], keys[1], vals[0], vals[1], n, gplan, at<uint32_t>(ws, plan.hist),
+                       at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status),
+                       h->d_info, s);
+    cur = 1;  // the planned sort ends in buffer 1
     perm = vals[cur];
     st.mark("permute");
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
     st.mark("dense_cells");
     fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
-    densebox_cells(keys[cur], gp.key64, n, dim, xs, eps2, min_pts, at<int>(ws, plan.cell_id),
+    densebox_cells(keys[cur], false, &gplan->key64, n, dim, xs, eps2, min_pts, at<int>(ws, plan.cell_id),
                    at<int>(ws, plan.cell_start), at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense),
                    at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
-                   at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key),
+                   at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<uint64_t>(ws, plan.prim_key),
                    at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
   }
   h->last_densebox = densebox;
   if (densebox) {
     st.mark("lbvh");
-    build_lbvh(at<void>(ws, plan.prim_key), gp.key64, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
+    build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
@@ -595,15 +807,16 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   ta.brec_cap = static_cast<int>(plan.brec_cap);
   if (!all_core) {
     fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
-    // isolated points first, when the lone-cell bitmap fits the (now free) pflag buffer
-    const int lone_shift = dim * (gp.bits - 1);
-    const int64_t lone_words = lone_shift <= 6 ? 1 : (int64_t(1) << (lone_shift - 6));
-    if (densebox && !gp.key64 && gp.bits >= 1 && 2 * lone_words <= n) {
+    // isolated points first, when the plan says the lone-cell bitmap fits the (now
+    // free) pflag buffer; otherwise these kernels leave at once and the core pass
+    // walks every primitive
+    if (densebox) {
       st.mark("isolated");
       ta.core_list = at<int>(ws, plan.cid);  // cid is free until the canonical ids
       ta.core_qn = misc + kMiscCoreQ;
-      launch_lone_filter(ta, dim, at<uint32_t>(ws, plan.prim_key), gp.ncell, at<uint64_t>(ws, plan.pflag),
-                         lone_words, at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
+      ta.lone_on = &gplan->lone_on;
+      launch_lone_filter(ta, dim, at<uint64_t>(ws, plan.prim_key), gplan, at<uint64_t>(ws, plan.pflag),
+                         at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
     }
     st.mark("core");
     launch_core(ta, dim, densebox, s);
@@ -632,18 +845,12 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
   launch_scatter(lab, core, perm, at<int>(ws, plan.cid), at<int>(ws, plan.border), first_border && !all_core,
                  have_border, n, labels, is_core, h->d_info, s);
   st.finish();
-  if (hipGetLastError() != hipSuccess) return FDB_ERR_HIP;
-  if (h_num_clusters) {
-    if (hipMemcpyAsync(h->h_pinned, misc + kMiscNumClusters, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(h->h_pinned + 8, h->d_info, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return FDB_ERR_HIP;
-    *h_num_clusters = static_cast<int32_t>(h->h_pinned[0]);
-    if (h->h_pinned[8] & FDB_INFO_NONFINITE) return FDB_ERR_NONFINITE;
-    if (h->h_pinned[8] & FDB_INFO_INTERNAL) return FDB_ERR_INTERNAL;
-  }
-  return FDB_OK;
+  return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
 }
+
+}  // namespace
+
+extern "C" {
 
 fdb_status fdb_workspace_bytes_batched(int64_t n_total, int32_t num_clouds, int32_t dim, const fdb_options* opt,
                                        size_t* h_out) {
@@ -661,8 +868,22 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
                               int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
                               const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
                               void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  using namespace fdb;
   if (!h) return FDB_ERR_INVALID;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
+  return dbscan_batched_entry(h, points, n_total, offsets, num_clouds, dim, eps, min_pts, opt, labels, is_core,
+                              num_clusters, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+fdb_status dbscan_batched_entry(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                                int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                                const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* num_clusters,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  using namespace fdb;
   fdb_options o{};
   if (opt) o = *opt;
   if (!valid_options(o) || (dim != 2 && dim != 3) || n_total < 0 || n_total > kMaxPoints || num_clouds < 1 ||
@@ -673,41 +894,60 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   h->last_stream = stream;
   h->host_info = 0;
   h->last_misc = nullptr;
-  hipStream_t s = stream;
   if (n_total == 0) {
-    if (num_clusters) fill_u32(reinterpret_cast<uint32_t*>(num_clusters), 0, num_clouds, s);
+    if (num_clusters) fill_u32(reinterpret_cast<uint32_t*>(num_clusters), 0, num_clouds, stream);
     return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
   }
+  resolve_shape(h, o, n_total, dim, num_clouds);
+  const Plan plan = make_plan(n_total, dim, o.algo, num_clouds);
+  void* ws = nullptr;
+  const fdb_status wst = take_workspace(h, plan, workspace, workspace_bytes, stream, &ws);
+  if (wst != FDB_OK) return wst;
+  const BatchArgs args{points, n_total, offsets, num_clouds, dim, eps, min_pts, labels, is_core, num_clusters};
+  if (o.flags & FDB_FLAG_GRAPH) {
+    const CallKey key = batch_key(args, o, ws, plan.bytes);
+    const fdb_status st =
+        run_graph(h, key, stream, [&](hipStream_t cs) { return batched_launch(h, args, o, plan, ws, cs, false); });
+    h->last_misc = at<int>(ws, plan.misc);
+    h->last_densebox = o.algo != FDB_ALGO_FDBSCAN;
+    h->last_n = n_total;
+    return st;
+  }
+  return batched_launch(h, args, o, plan, ws, stream, h->timing);
+}
+
+// The launch sequence of one batched call (stream-ordered launches only).
+fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_options& o, const fdb::Plan& plan, void* ws,
+                          hipStream_t stream, bool timing) {
+  using namespace fdb;
+  const float* points = args.points;
+  const int64_t n_total = args.n_total;
+  const int64_t* offsets = args.offsets;
+  const int32_t num_clouds = args.num_clouds;
+  const int dim = args.dim;
+  const float* eps = args.eps;
+  const int32_t* min_pts = args.min_pts;
+  int32_t* labels = args.labels;
+  uint8_t* is_core = args.is_core;
+  int32_t* num_clusters = args.num_clusters;
+  hipStream_t s = stream;
   const int leaf = o.leaf_size > 0 ? o.leaf_size : kDefaultLeaf;
   const int block = o.block_size > 0 ? o.block_size : kDefaultBlock;
+  const int tile = o.tile > 0 ? o.tile : kDefaultTile;
   const bool densebox = o.algo != FDB_ALGO_FDBSCAN;  // the automatic choice runs DenseBox for a batch
   const bool first_border = o.border == FDB_BORDER_FIRST;
-  const Plan plan = make_plan(n_total, dim, o.algo, num_clouds);
-  void* ws = workspace;
-  if (ws) {
-    if (workspace_bytes < plan.bytes) return FDB_ERR_NOMEM;
-  } else {
-    if (h->ws_bytes < plan.bytes) {
-      if (h->ws) {
-        if (hipStreamSynchronize(stream) != hipSuccess) return FDB_ERR_HIP;
-        (void)hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_bytes = 0;
-      }
-      if (hipMalloc(&h->ws, plan.bytes) != hipSuccess) return FDB_ERR_NOMEM;
-      h->ws_bytes = plan.bytes;
-    }
-    ws = h->ws;
-  }
   (void)hipGetLastError();
-  Stager st(h, s);
-  if (h->timing) ++h->timed_calls;
+  Stager st(h, s, timing);
+  if (timing) ++h->timed_calls;
   const int64_t n = n_total;
   int cb = 1;
   while ((int64_t(1) << cb) < num_clouds) ++cb;
   const int bpd = std::min(dim == 3 ? 21 : 31, (64 - cb) / dim);  // key bits per axis below the cloud id
   const int shift = dim * bpd;
   int* misc = at<int>(ws, plan.misc);
+  h->last_misc = misc;  // fdb_last_counts reports the batch as a whole
+  h->last_densebox = densebox;
+  h->last_n = n;
   void* keys[2] = {at<void>(ws, plan.keys0), at<void>(ws, plan.keys1)};
   uint32_t* vals[2] = {at<uint32_t>(ws, plan.vals0), at<uint32_t>(ws, plan.vals1)};
   float* xs = at<float>(ws, plan.xs);
@@ -743,7 +983,7 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   ta.n = n;
   ta.eps2 = 0.0f;
   ta.packet_ext_eps2 = 9.0f;
-  ta.packet_leaf = 64;
+  ta.packet_leaf = tile;
   ta.min_pts = 0;
   ta.labels = lab;
   ta.core = core;
@@ -767,11 +1007,11 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
 
   if (densebox) {
     st.mark("dense_cells");
-    densebox_cells(keys[cur], true, n, dim, xs, 0.0f, 0, at<int>(ws, plan.cell_id), at<int>(ws, plan.cell_start),
+    densebox_cells(keys[cur], true, nullptr, n, dim, xs, 0.0f, 0, at<int>(ws, plan.cell_id), at<int>(ws, plan.cell_start),
                    at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense), at<float4>(ws, plan.cell_lo),
                    at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt), at<float4>(ws, plan.prim_lo),
-                   at<float4>(ws, plan.prim_hi), at<void>(ws, plan.prim_key), at<int>(ws, plan.dense_list), lab,
+                   at<float4>(ws, plan.prim_hi), at<uint64_t>(ws, plan.prim_key), at<int>(ws, plan.dense_list), lab,
                    core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2);
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
@@ -837,6 +1077,10 @@ fdb_status fdb_dbscan_batched(fdb_handle* h, const float* points, int64_t n_tota
   return hipGetLastError() == hipSuccess ? FDB_OK : FDB_ERR_HIP;
 }
 
+}  // namespace
+
+extern "C" {
+
 
 // ---- out-of-core batches --------------------------------------------------------
 
@@ -876,6 +1120,8 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
   if (!h || !h_offsets || !h_eps || !h_min_pts || !h_num_clusters || (dim != 2 && dim != 3) || num_clouds < 1 ||
       num_clouds > (1 << 24))
     return FDB_ERR_INVALID;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
   fdb_options o{};
   if (opt) o = *opt;
   if (!valid_options(o) || h_offsets[0] != 0) return FDB_ERR_INVALID;
@@ -993,8 +1239,8 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
       fail(FDB_ERR_HIP);
       break;
     }
-    const fdb_status r = fdb_dbscan_batched(h, S.pts, n, S.off, b, dim, S.eps, S.mp, &o, S.lab,
-                                            h_is_core ? S.core : nullptr, S.k, S.ws, S.ws_bytes, sc);
+    const fdb_status r = dbscan_batched_entry(h, S.pts, n, S.off, b, dim, S.eps, S.mp, &o, S.lab,
+                                              h_is_core ? S.core : nullptr, S.k, S.ws, S.ws_bytes, sc);
     if (r != FDB_OK) {
       fail(r);
       break;
@@ -1027,6 +1273,210 @@ fdb_status fdb_dbscan_batched_host(fdb_handle* h, const float* h_points, const i
   h->host_info = info;
   if (st == FDB_OK && (info & FDB_INFO_INTERNAL)) st = FDB_ERR_INTERNAL;
   return st;
+}
+
+// ---- autotuner ------------------------------------------------------------------
+//
+// The launch shape (leaf size, workgroup size, traversal tile) changes no label,
+// only time. fdb_tune times candidate shapes on the caller's own input by
+// coordinate descent (each axis over its candidates, the others held at the best
+// so far), keeps the fastest for the call's class and appends it to the file
+// named by FDB_TUNE_CACHE, which fdb_create reads back.
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kTuneLeaf[] = {4, 8, 16, 32};
+constexpr int kTuneBlock[] = {64, 128, 256};
+constexpr int kTuneTile[] = {32, 64};
+
+void store_tune(fdb_handle* h, const fdb::TuneEntry& e) {
+  for (auto& x : h->tune)
+    if (x.batched == e.batched && x.algo == e.algo && x.dim == e.dim && x.nlog2 == e.nlog2 &&
+        x.mpclass == e.mpclass) {
+      x = e;
+      return;
+    }
+  h->tune.push_back(e);
+}
+
+void append_tune_file(const fdb::TuneEntry& e) {
+  const char* path = std::getenv("FDB_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "fdbtune1 %d %d %d %d %d %d %d %d %.6f %.6f %.6f\n", e.batched, e.algo, e.dim, e.nlog2, e.mpclass,
+               e.leaf_size, e.block_size, e.tile, e.best_ms, e.default_ms, e.dense_share);
+  std::fclose(f);
+}
+
+// Later lines override earlier ones for the same class; malformed lines are skipped.
+void load_tune_file(fdb_handle* h) {
+  const char* path = std::getenv("FDB_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    fdb::TuneEntry e{};
+    if (std::sscanf(line, "fdbtune1 %d %d %d %d %d %d %d %d %lf %lf %lf", &e.batched, &e.algo, &e.dim, &e.nlog2,
+                    &e.mpclass, &e.leaf_size, &e.block_size, &e.tile, &e.best_ms, &e.default_ms,
+                    &e.dense_share) != 11)
+      continue;
+    fdb_options o{};
+    o.leaf_size = e.leaf_size;
+    o.block_size = e.block_size;
+    o.tile = e.tile;
+    if (!valid_options(o) || e.leaf_size < 1 || (e.dim != 2 && e.dim != 3)) continue;
+    store_tune(h, e);
+  }
+  std::fclose(f);
+}
+
+// Median time (ms) of `reps` runs of call(o) on `stream`, timed with HIP events.
+template <typename F>
+fdb_status time_shape(hipStream_t stream, int reps, const fdb_options& o, F&& call, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return FDB_ERR_HIP;
+  }
+  fdb_status st = call(o);  // warm-up (and the first graph recording, if asked for)
+  std::vector<double> t;
+  for (int r = 0; r < reps && st == FDB_OK; ++r) {
+    float x = 0.0f;
+    if (hipEventRecord(a, stream) != hipSuccess) st = FDB_ERR_HIP;
+    if (st == FDB_OK) st = call(o);
+    if (st == FDB_OK && (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                         hipEventElapsedTime(&x, a, b) != hipSuccess))
+      st = FDB_ERR_HIP;
+    t.push_back(x);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != FDB_OK) return st;
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return FDB_OK;
+}
+
+template <typename F>
+fdb_status tune_search(fdb_handle* h, hipStream_t stream, int reps, const fdb_options& base, F&& call,
+                       fdb_options* best, double* best_ms, double* default_ms) {
+  fdb_options cur = base;
+  cur.leaf_size = kDefaultLeaf;
+  cur.block_size = kDefaultBlock;
+  cur.tile = kDefaultTile;
+  double cur_ms = 0.0;
+  fdb_status st = time_shape(stream, reps, cur, call, &cur_ms);
+  if (st != FDB_OK) return st;
+  *default_ms = cur_ms;
+  auto axis = [&](int32_t fdb_options::*field, const int* cand, int count) -> fdb_status {
+    for (int k = 0; k < count; ++k) {
+      if (cur.*field == cand[k]) continue;
+      fdb_options o = cur;
+      o.*field = cand[k];
+      double ms = 0.0;
+      const fdb_status r = time_shape(stream, reps, o, call, &ms);
+      if (r != FDB_OK) return r;
+      if (ms < cur_ms) {
+        cur = o;
+        cur_ms = ms;
+      }
+    }
+    return FDB_OK;
+  };
+  if ((st = axis(&fdb_options::leaf_size, kTuneLeaf, 4)) != FDB_OK) return st;
+  if ((st = axis(&fdb_options::block_size, kTuneBlock, 3)) != FDB_OK) return st;
+  if ((st = axis(&fdb_options::tile, kTuneTile, 2)) != FDB_OK) return st;
+  *best = cur;
+  *best_ms = cur_ms;
+  (void)h;
+  return FDB_OK;
+}
+
+double dense_share_of(fdb_handle* h, int64_t n) {
+  int64_t c[4];
+  if (n <= 0 || fdb_last_counts(h, c) != FDB_OK || c[2] <= 0) return 0.0;
+  return static_cast<double>(n - (c[3] - c[2])) / static_cast<double>(n);
+}
+
+}  // namespace
+
+extern "C" {
+
+fdb_status fdb_tune(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                    const fdb_options* opt, int32_t reps, int32_t* labels, uint8_t* is_core, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream, fdb_options* h_best, double* h_ms) {
+  if (!h || !h_best || !h_ms || reps < 1 || reps > 100 || n < 1) return FDB_ERR_INVALID;
+  fdb_options base{};
+  if (opt) base = *opt;
+  if (!valid_options(base)) return FDB_ERR_INVALID;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
+  DeviceGuard guard(h->device);
+  auto call = [&](const fdb_options& o) {
+    return dbscan_entry(h, points, n, dim, eps, min_pts, &o, labels, is_core, nullptr, workspace, workspace_bytes,
+                        stream);
+  };
+  fdb_options best{};
+  double best_ms = 0.0, def_ms = 0.0;
+  const fdb_status st = tune_search(h, stream, reps, base, call, &best, &best_ms, &def_ms);
+  if (st != FDB_OK) return st;
+  fdb::TuneEntry e{0, base.algo == FDB_ALGO_FDBSCAN ? FDB_ALGO_FDBSCAN : FDB_ALGO_DENSEBOX, dim, nlog2_of(n),
+                   mpclass_of(min_pts), best.leaf_size, best.block_size, best.tile, best_ms, def_ms,
+                   dense_share_of(h, n)};
+  store_tune(h, e);
+  append_tune_file(e);
+  *h_best = best;
+  h_ms[0] = best_ms;
+  h_ms[1] = def_ms;
+  return FDB_OK;
+}
+
+fdb_status fdb_tune_batched(fdb_handle* h, const float* points, int64_t n_total, const int64_t* offsets,
+                            int32_t num_clouds, int32_t dim, const float* eps, const int32_t* min_pts,
+                            const fdb_options* opt, int32_t reps, int32_t* labels, uint8_t* is_core,
+                            int32_t* num_clusters, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                            fdb_options* h_best, double* h_ms) {
+  if (!h || !h_best || !h_ms || reps < 1 || reps > 100 || n_total < 1) return FDB_ERR_INVALID;
+  fdb_options base{};
+  if (opt) base = *opt;
+  if (!valid_options(base)) return FDB_ERR_INVALID;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
+  DeviceGuard guard(h->device);
+  auto call = [&](const fdb_options& o) {
+    return dbscan_batched_entry(h, points, n_total, offsets, num_clouds, dim, eps, min_pts, &o, labels, is_core,
+                                num_clusters, workspace, workspace_bytes, stream);
+  };
+  fdb_options best{};
+  double best_ms = 0.0, def_ms = 0.0;
+  const fdb_status st = tune_search(h, stream, reps, base, call, &best, &best_ms, &def_ms);
+  if (st != FDB_OK) return st;
+  fdb::TuneEntry e{1, base.algo == FDB_ALGO_FDBSCAN ? FDB_ALGO_FDBSCAN : FDB_ALGO_DENSEBOX, dim, nlog2_of(n_total), 1,
+                   best.leaf_size, best.block_size, best.tile, best_ms, def_ms, dense_share_of(h, n_total)};
+  store_tune(h, e);
+  append_tune_file(e);
+  *h_best = best;
+  h_ms[0] = best_ms;
+  h_ms[1] = def_ms;
+  return FDB_OK;
+}
+
+fdb_status fdb_tuned_options(fdb_handle* h, int64_t n, int32_t dim, int32_t min_pts, int32_t num_clouds,
+                             const fdb_options* opt, fdb_options* h_out) {
+  if (!h || !h_out || n < 0 || (dim != 2 && dim != 3) || num_clouds < 0) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o)) return FDB_ERR_INVALID;
+  resolve_shape(h, o, n, dim, num_clouds, min_pts);
+  if (!o.leaf_size) o.leaf_size = kDefaultLeaf;
+  if (!o.block_size) o.block_size = kDefaultBlock;
+  if (!o.tile) o.tile = kDefaultTile;
+  *h_out = o;
+  return FDB_OK;
 }
 
 }  // extern "C"

@@ -30,7 +30,7 @@ struct Plan {
   int algo = 0;
   size_t bytes = 0;
   // common
-  size_t bounds, misc, keys0, keys1, vals0, vals1, hist, digoff, tilectr, status;
+  size_t bounds, misc, gplan, keys0, keys1, vals0, vals1, hist, digoff, tilectr, status;
   size_t xs;                       // dim * n floats, sorted SoA
   size_t node_a, node_b, rope, leaf_rope, parent, flags, other, gamma;
   size_t labels, core, lone, qborder, brec_i, brec_nb;
@@ -59,6 +59,25 @@ enum MiscSlot : int {
   kMiscCoreQ = 8,        // DenseBox: point primitives left for the core pass by the isolated-point test,
                          // one count per XCD segment (slots 8 .. 15)
   kMiscCount = 16
+};
+
+// DenseBox grid of one cloud (Section 4.2: cells of side eps/sqrt(d)), sized on
+// the device from the scene bounds by k_grid_plan, so no value goes back to the
+// host mid-call. The key, sort, dense-cell and isolated-point kernels read it.
+// When the eps/sqrt(d) grid needs more cells per axis than a 64-bit key holds
+// (21 bits per axis in 3D, 31 in 2D), the cells are widened to fit (coarse = 1,
+// FDB_INFO_DENSEBOX_FALLBACK): density is still decided by the exact guard, so
+// labels stay exact; only fewer cells come out dense.
+struct GridPlan {
+  float inv_h[4];      // 1 / cell side, per axis
+  uint32_t ncell[4];   // cells per axis (>= 1)
+  int32_t bits;        // key bits per axis
+  int32_t key64;       // 1: d * bits > 32, keys are stored as 64-bit words, else 32-bit
+  int32_t passes;      // 8-bit radix passes over the d * bits key bits
+  int32_t start;       // key buffer (0/1) the key kernel fills: the sort then ends in buffer 1
+  int32_t lone_on;     // the isolated-point test runs (32-bit keys, bitmap fits its buffer)
+  int32_t coarse;      // cells widened to fit 64-bit keys
+  int64_t lone_words;  // 64-bit occupancy words of the isolated-point test
 };
 
 // Node records are interleaved: node k's two halves sit at node_a[kNodeStride * k]
@@ -91,9 +110,14 @@ void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint3
 // radix sort into hist (ceil(sort_bits / 8) x 256 words, cleared here).
 void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds, uint64_t* keys, uint32_t* vals,
                    int sort_bits, uint32_t* hist, hipStream_t s);
-void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const float* inv_h3,
-                     const uint32_t* ncell3, int bits, bool key64, void* keys, uint32_t* vals, int sort_bits,
-                     uint32_t* hist, hipStream_t s);
+// DenseBox of one cloud: k_grid_plan writes *plan from the bounds (after
+// launch_bounds; eps is the caller's), then the cell keys go to key buffer
+// plan->start as 32- or 64-bit words with the identity permutation, and their
+// digits are counted for the sort (hist: 8 x 256 words, cleared here).
+void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, GridPlan* plan, uint32_t* info,
+                      hipStream_t s);
+void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const GridPlan* plan,
+                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s);
 void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,
                     hipStream_t s);
 
@@ -103,6 +127,13 @@ void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, 
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
                uint32_t* hist, bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
                uint32_t* info, hipStream_t s);
+// The same with key width and pass count taken from a GridPlan on the device:
+// passes for both widths are launched and those the plan does not call for exit
+// at once. The keys start in buffer plan->start and end in buffer 1; hist holds
+// every pass's digit counts (from the key kernel).
+void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, const GridPlan* plan,
+                        const uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
+                        uint32_t* info, hipStream_t s);
 
 // k_tree.hip
 // prim_lo / prim_hi: DenseBox leaf records (null for FDbscan, whose leaves are
@@ -113,16 +144,13 @@ void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, i
                 hipStream_t s);
 
 // k_dense.hip
-struct GridParams {
-  float inv_h[3];
-  uint32_t ncell[3];
-  int bits;
-  bool key64;
-};
-void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2,
-                    int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo,
-                    float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
-                    float4* prim_hi, void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
+// sorted_keys are 64-bit words when key64 (or, with d_key64 set, when *d_key64 on
+// the device says so), else 32-bit; prim_key receives each primitive's key as a
+// 64-bit word.
+void densebox_cells(const void* sorted_keys, bool key64, const int* d_key64, int64_t n, int dim, const float* xs,
+                    float eps2, int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense,
+                    float4* cell_lo, float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
+                    float4* prim_hi, uint64_t* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
                     int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift = 0,
                     const int* cl_minpts = nullptr, const float* cl_eps2 = nullptr);
 
@@ -160,6 +188,7 @@ struct TravArgs {
   // primitive when core_list is null
   const int* core_list;
   const int* core_qn;
+  const int* lone_on;  // device flag: core_list is in use (null = whenever core_list is set)
   // DenseBox primitives (null for FDbscan). Primitive r covers sorted points
   // [prim_start[r], prim_start[r] + |prim_cnt[r]|); prim_cnt > 0: a single
   // point, < 0: a dense cell. prim_lo[r] is the leaf record a walk loads: a
@@ -189,11 +218,11 @@ void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
 // a bitmap over "lone cells" (2^d blocks of grid cells) marks the cells holding a
 // primitive; a point primitive alone in its lone cell, whose 3^d - 1 neighbours
 // are empty, has no neighbour but itself and is finished here (core 0, lone,
-// border -1); the others are listed (list, list_n[kNumXcd]) for the core pass. bits holds
-// words = 2^(d (b - 1)) / 64 (at least 1) 64-bit words for keys of b bits per axis;
-// ncell: grid cells per axis.
-void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, const uint32_t* ncell, uint64_t* bits,
-                        int64_t words, int* list, int* list_n, hipStream_t s);
+// border -1); the others are listed (list, list_n[kNumXcd]) for the core pass.
+// Runs only where plan->lone_on: bits then holds plan->lone_words =
+// 2^(d (b - 1)) / 64 (at least 1) 64-bit words for keys of b bits per axis.
+void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint64_t* bits,
+                        int* list, int* list_n, hipStream_t s);
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
                  hipStream_t s);
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);

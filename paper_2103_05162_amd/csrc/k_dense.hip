@@ -21,10 +21,22 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <typename K>
-__global__ __launch_bounds__(kBlock) void k_cell_heads(const K* __restrict__ keys, int64_t n, int* __restrict__ head) {
+// Sorted keys as 32- or 64-bit words: the width is fixed by the caller (key64) or,
+// for a DenseBox grid sized on the device, read from the plan's flag (d_key64).
+struct KeyIn {
+  const void* p;
+  const int* d_key64;
+  int key64;
+  __device__ __forceinline__ bool wide() const { return d_key64 ? *d_key64 != 0 : key64 != 0; }
+};
+__device__ __forceinline__ uint64_t key_at(const KeyIn& k, bool wide, int64_t i) {
+  return wide ? static_cast<const uint64_t*>(k.p)[i] : static_cast<const uint32_t*>(k.p)[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_heads(KeyIn keys, int64_t n, int* __restrict__ head) {
+  const bool wide = keys.wide();
   for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+    head[i] = (i == 0 || key_at(keys, wide, i) != key_at(keys, wide, i - 1)) ? 1 : 0;
 }
 
 // cell_id[i] = (number of heads at or before i) - 1; heads record their start.
@@ -167,17 +179,18 @@ __global__ __launch_bounds__(kBlock) void k_prim_flags(const int* __restrict__ c
 
 // pidx holds the exclusive scan of pflag: the primitive index of every point
 // that opens a primitive (a point outside dense cells, or a dense cell's first).
-template <int D, typename K>
-__global__ __launch_bounds__(kPushBlock) void k_prims(const K* __restrict__ keys, const float* __restrict__ xs, int64_t n,
+template <int D>
+__global__ __launch_bounds__(kPushBlock) void k_prims(KeyIn keys, const float* __restrict__ xs, int64_t n,
                                                   const int* __restrict__ cell_id, const int* __restrict__ cell_start,
                                                   const uint8_t* __restrict__ dense, const float4* __restrict__ cell_lo,
                                                   const float4* __restrict__ cell_hi, const int* __restrict__ pidx,
                                                   int* __restrict__ prim_start,
                                                   int* __restrict__ prim_cnt, float4* __restrict__ prim_lo,
-                                                  float4* __restrict__ prim_hi, K* __restrict__ prim_key,
+                                                  float4* __restrict__ prim_hi, uint64_t* __restrict__ prim_key,
                                                   int* __restrict__ dense_list, int* __restrict__ num_dense,
                                                   int* __restrict__ labels, uint8_t* __restrict__ core) {
   __shared__ int s_w[17];
+  const bool wide = keys.wide();
   // Every thread of a workgroup runs the same trip count and reaches the one
   // block_push call of each trip (it synchronises the workgroup).
   for (int64_t base = blockIdx.x * int64_t(kPushBlock); base < n; base += int64_t(gridDim.x) * kPushBlock) {
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(kPushBlock) void k_prims(const K* __restrict__ keys
           prim_cnt[p] = -(cell_start[c + 1] - s);
           prim_lo[p] = make_float4(cl.x, cl.y, cl.z, __int_as_float(-2 - s));
           prim_hi[p] = cell_hi[c];
-          prim_key[p] = keys[i];
+          prim_key[p] = key_at(keys, wide, i);
           pd = p;
         }
       } else {
@@ -209,7 +222,7 @@ __global__ __launch_bounds__(kPushBlock) void k_prims(const K* __restrict__ keys
         prim_start[p] = i;
         prim_cnt[p] = 1;
         prim_lo[p] = make_float4(xs[i], xs[n + i], D == 3 ? xs[2 * n + i] : 0.0f, __int_as_float(i));
-        prim_key[p] = keys[i];
+        prim_key[p] = key_at(keys, wide, i);
       }
     }
     block_push(dense_list, num_dense, opens_dense, pd, s_w);
@@ -223,10 +236,9 @@ inline int grid_for(int64_t n) {
   return static_cast<int>(g);
 }
 
-template <typename K>
-void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
+void cells_t(const KeyIn& keys, int64_t n, int dim, const float* xs, float eps2, int min_pts, int* cell_id,
              int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag,
-             int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, K* prim_key, int* dense_list,
+             int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, uint64_t* prim_key, int* dense_list,
              int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, const CloudParams& cp,
              hipStream_t s) {
   int* d_cells = misc + kMiscNumCells;
@@ -234,7 +246,7 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   int* d_prims = misc + kMiscNumPrims;
   int* d_dense = misc + kMiscNumDense;
   const int g = grid_for(n);
-  hipLaunchKernelGGL(k_cell_heads<K>, dim3(g), dim3(kBlock), 0, s, keys, n, pflag);
+  hipLaunchKernelGGL(k_cell_heads, dim3(g), dim3(kBlock), 0, s, keys, n, pflag);
   device_scan(pflag, cell_id, n, nullptr, bsums, scan_blocks, d_cells, s);
   hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(kBlock), 0, s, pflag, n, cell_id, cell_start, d_cells);
   fill_u32(reinterpret_cast<uint32_t*>(d_cand), 0, 1, s);
@@ -257,31 +269,28 @@ void cells_t(const K* keys, int64_t n, int dim, const float* xs, float eps2, int
   int* pidx = cand;  // candidates are no longer needed; reuse for primitive indices
   device_scan(pflag, pidx, n, nullptr, bsums, scan_blocks, d_prims, s);
   if (dim == 3)
-    hipLaunchKernelGGL((k_prims<3, K>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+    hipLaunchKernelGGL((k_prims<3>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
                        cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
   else
-    hipLaunchKernelGGL((k_prims<2, K>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
+    hipLaunchKernelGGL((k_prims<2>), dim3(gp), dim3(kPushBlock), 0, s, keys, xs, n, cell_id, cell_start, dense,
                        cell_lo, cell_hi, pidx, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list,
                        d_dense, labels, core);
 }
 
 }  // namespace
 
-void densebox_cells(const void* sorted_keys, bool key64, int64_t n, int dim, const float* xs, float eps2, int min_pts,
-                    int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense, float4* cell_lo, float4* cell_hi,
-                    int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi,
-                    void* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc, int* bsums,
-                    int64_t scan_blocks, hipStream_t s, int key_shift, const int* cl_minpts, const float* cl_eps2) {
+void densebox_cells(const void* sorted_keys, bool key64, const int* d_key64, int64_t n, int dim, const float* xs,
+                    float eps2, int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense,
+                    float4* cell_lo, float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
+                    float4* prim_hi, uint64_t* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
+                    int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift, const int* cl_minpts,
+                    const float* cl_eps2) {
+  // per-cloud parameters come with batches, whose keys are always 64-bit
   CloudParams cp{static_cast<const uint64_t*>(sorted_keys), key_shift, cl_minpts, cl_eps2};
-  if (key64)
-    cells_t(static_cast<const uint64_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
-            cell_dense, cell_lo, cell_hi, pflag, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint64_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
-  else
-    cells_t(static_cast<const uint32_t*>(sorted_keys), n, dim, xs, eps2, min_pts, cell_id, cell_start, cand,
-            cell_dense, cell_lo, cell_hi, pflag, prim_start, prim_cnt, prim_lo, prim_hi,
-            static_cast<uint32_t*>(prim_key), dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
+  const KeyIn keys{sorted_keys, d_key64, key64 ? 1 : 0};
+  cells_t(keys, n, dim, xs, eps2, min_pts, cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_start,
+          prim_cnt, prim_lo, prim_hi, prim_key, dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
 }
 
 }  // namespace fdb

@@ -206,35 +206,94 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float* __restrict__ pts
   hist_flush(s_h, passes, hist);
 }
 
-// DenseBox grid (Section 4.2): cell c_k = floor((x_k - lo_k) / h), h = eps/sqrt(d)
-// (inv_h supplied slightly above sqrt(d)/eps), clamped to the grid; the key is
-// the Morton interleave of the cell coordinates, so equal keys are one cell and
-// cells follow the curve.
-template <int D, typename K>
+// The DenseBox grid of one cloud (Section 4.2: cells of side h = eps/sqrt(d)),
+// sized here from the bounds so that nothing returns to the host mid-call. The
+// side is shrunk by 2^-20 so that rounding in the cell index rarely pushes a
+// cell's extent past h (the exactness guard catches the rest). A grid wider than
+// a 64-bit key holds gets wider cells (every pair in a dense cell still passes the
+// guard). The isolated-point test runs for 32-bit keys when its bitmap (one bit
+// per 2^d block of cells, 64-bit words) fits in n 32-bit words.
+template <int D>
+__global__ void k_grid_plan(const uint32_t* __restrict__ bounds, float eps, int64_t n, GridPlan* __restrict__ plan,
+                            uint32_t* __restrict__ info) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  constexpr int maxbits = D == 3 ? 21 : 31;
+  const double side0 = static_cast<double>(eps) / sqrt(static_cast<double>(D)) * (1.0 - 1.0 / 1048576.0);
+  double ext[3] = {0.0, 0.0, 0.0}, emax = 0.0;
+  for (int k = 0; k < D; ++k) {
+    const double e = static_cast<double>(ord2f(bounds[4 + k])) - static_cast<double>(ord2f(bounds[k]));
+    ext[k] = e >= 0.0 && e <= 3.0e38 ? e : 0.0;  // an empty or non-finite extent: one cell
+    emax = ext[k] > emax ? ext[k] : emax;
+  }
+  const double top = static_cast<double>((1u << maxbits) - 2u);  // at most 2^maxbits - 1 cells per axis
+  double side = side0;
+  int coarse = 0;
+  if (!(side > 0.0) || !(emax / side < top)) {
+    side = emax > 0.0 ? emax / top : 1.0;
+    side = side > side0 ? side : side0;
+    coarse = 1;
+  }
+  const float ih = static_cast<float>(1.0 / side);
+  int bits = 0;
+  GridPlan g;
+  for (int k = 0; k < 4; ++k) {
+    g.inv_h[k] = k < D ? ih : 0.0f;
+    uint32_t c = 1;
+    if (k < D) {
+      const double cells = floor(ext[k] / side) + 1.0;
+      c = cells < top + 1.0 ? static_cast<uint32_t>(cells) : static_cast<uint32_t>(top + 1.0);
+    }
+    g.ncell[k] = c;
+    int b = 0;
+    while ((uint64_t(1) << b) < c) ++b;
+    bits = b > bits ? b : bits;
+  }
+  g.bits = bits;
+  g.key64 = D * bits > 32 ? 1 : 0;
+  g.passes = (D * bits + 7) / 8;
+  g.start = (g.passes & 1) ? 0 : 1;
+  g.coarse = coarse;
+  const int lone_shift = D * (bits - 1);
+  g.lone_words = lone_shift <= 6 ? 1 : (int64_t(1) << (lone_shift - 6));
+  g.lone_on = (!g.key64 && bits >= 1 && 2 * g.lone_words <= n) ? 1 : 0;
+  *plan = g;
+  if (coarse) atomicOr(info, FDB_INFO_DENSEBOX_FALLBACK);
+}
+
+// DenseBox cell keys: cell c_k = floor((x_k - lo_k) / h), clamped to the grid; the
+// key is the Morton interleave of the cell coordinates, so equal keys are one cell
+// and cells follow the curve. Written as 32- or 64-bit words as the plan says, into
+// the buffer the plan names, with the identity permutation beside them.
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ pts, int64_t n,
-                                                     const uint32_t* __restrict__ bounds, float ihx, float ihy,
-                                                     float ihz, uint32_t ncx, uint32_t ncy, uint32_t ncz,
-                                                     K* __restrict__ keys, uint32_t* __restrict__ vals, int passes,
-                                                     uint32_t* __restrict__ hist) {
+                                                     const uint32_t* __restrict__ bounds,
+                                                     const GridPlan* __restrict__ plan, void* __restrict__ keys0,
+                                                     void* __restrict__ keys1, uint32_t* __restrict__ vals0,
+                                                     uint32_t* __restrict__ vals1, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_h[8 * 256];
+  const GridPlan g = *plan;
+  const int passes = g.passes;
   hist_clear(s_h, passes);
-  const float ih[3] = {ihx, ihy, ihz};
-  const uint32_t nc[3] = {ncx, ncy, ncz};
+  uint32_t* vals = g.start ? vals1 : vals0;
+  void* keys = g.start ? keys1 : keys0;
   float lo[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) lo[k] = ord2f(bounds[k]);
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     uint32_t c[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) c[k] = quantize(pts[i * D + k], lo[k], ih[k], nc[k] - 1);
+    for (int k = 0; k < D; ++k) c[k] = quantize(pts[i * D + k], lo[k], g.inv_h[k], g.ncell[k] - 1);
     uint64_t code;
     if constexpr (D == 3)
       code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
     else
       code = (spread2(c[0]) << 1) | spread2(c[1]);
-    keys[i] = static_cast<K>(code);
+    if (g.key64)
+      static_cast<uint64_t*>(keys)[i] = code;
+    else
+      static_cast<uint32_t*>(keys)[i] = static_cast<uint32_t>(code);
     vals[i] = static_cast<uint32_t>(i);
-    hist_add(static_cast<K>(code), true, passes, s_h);
+    hist_add(code, true, passes, s_h);
   }
   hist_flush(s_h, passes, hist);
 }
@@ -297,28 +356,24 @@ void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds,
     hipLaunchKernelGGL(k_morton<2>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals, passes, hist);
 }
 
-void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const float* ih,
-                     const uint32_t* nc, int bits, bool key64, void* keys, uint32_t* vals, int sort_bits,
-                     uint32_t* hist, hipStream_t s) {
-  (void)bits;
-  const int passes = (sort_bits + 7) / 8;
-  fill_u32(hist, 0, passes * 256, s);
+void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, GridPlan* plan, uint32_t* info,
+                      hipStream_t s) {
+  if (dim == 3)
+    hipLaunchKernelGGL(k_grid_plan<3>, dim3(1), dim3(64), 0, s, bounds, eps, n, plan, info);
+  else
+    hipLaunchKernelGGL(k_grid_plan<2>, dim3(1), dim3(64), 0, s, bounds, eps, n, plan, info);
+}
+
+void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const GridPlan* plan,
+                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s) {
+  fill_u32(hist, 0, 8 * 256, s);
   int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
-  if (dim == 3) {
-    if (key64)
-      hipLaunchKernelGGL((k_gridkeys<3, uint64_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         ih[2], nc[0], nc[1], nc[2], static_cast<uint64_t*>(keys), vals, passes, hist);
-    else
-      hipLaunchKernelGGL((k_gridkeys<3, uint32_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         ih[2], nc[0], nc[1], nc[2], static_cast<uint32_t*>(keys), vals, passes, hist);
-  } else {
-    if (key64)
-      hipLaunchKernelGGL((k_gridkeys<2, uint64_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         0.0f, nc[0], nc[1], 1u, static_cast<uint64_t*>(keys), vals, passes, hist);
-    else
-      hipLaunchKernelGGL((k_gridkeys<2, uint32_t>), dim3(g), dim3(kBlock), 0, s, pts, n, bounds, ih[0], ih[1],
-                         0.0f, nc[0], nc[1], 1u, static_cast<uint32_t*>(keys), vals, passes, hist);
-  }
+  if (dim == 3)
+    hipLaunchKernelGGL(k_gridkeys<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, plan, keys0, keys1, vals0, vals1,
+                       hist);
+  else
+    hipLaunchKernelGGL(k_gridkeys<2>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, plan, keys0, keys1, vals0, vals1,
+                       hist);
 }
 
 void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,

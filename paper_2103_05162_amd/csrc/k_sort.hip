@@ -85,12 +85,30 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return x - v + add;
 }
 
+// Pass p reads buffer `from` and writes the other. With a plan (a DenseBox grid
+// sized on the device), the pass runs only if the plan's key width is K's and p
+// is below its pass count, and `from` follows the plan's start buffer; without
+// one, the host's pass sequence starts in buffer 0.
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_onesweep(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                     K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
-                                                     int shift, uint32_t epoch, const uint32_t* __restrict__ digoff,
-                                                     uint32_t* __restrict__ tilectr, uint64_t* __restrict__ status,
+__global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __restrict__ k1,
+                                                     uint32_t* __restrict__ v0, uint32_t* __restrict__ v1, int64_t n,
+                                                     int p, const GridPlan* __restrict__ plan,
+                                                     const uint32_t* __restrict__ digoff_all,
+                                                     uint32_t* __restrict__ tilectr_all, uint64_t* __restrict__ status,
                                                      uint32_t* __restrict__ info) {
+  int from = p & 1;
+  if (plan) {
+    if (plan->key64 != (sizeof(K) == 8 ? 1 : 0) || p >= plan->passes) return;  // the whole grid leaves
+    from = (plan->start ^ p) & 1;
+  }
+  const K* __restrict__ kin = from ? k1 : k0;
+  K* __restrict__ kout = from ? k0 : k1;
+  const uint32_t* __restrict__ vin = from ? v1 : v0;
+  uint32_t* __restrict__ vout = from ? v0 : v1;
+  const int shift = 8 * p;
+  const uint32_t epoch = static_cast<uint32_t>(p + 1);
+  const uint32_t* __restrict__ digoff = digoff_all + p * kRadix;
+  uint32_t* __restrict__ tilectr = tilectr_all + p;
   constexpr int kItems = sort_items<K>();
   constexpr int kTile = 256 * kItems;
   static_assert(kTile >= kSortTileMin, "the workspace sizes the status words for kSortTileMin");
@@ -228,19 +246,35 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
     hipLaunchKernelGGL(k_hist<K>, dim3(hg), dim3(kBlock), 0, s, keys0, n, passes, hist);
   }
   hipLaunchKernelGGL(k_digit_offsets, dim3(passes), dim3(kRadix), 0, s, hist, digoff);
-  K* kb[2] = {keys0, keys1};
-  uint32_t* vb[2] = {vals0, vals1};
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_onesweep<K>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, kb[cur], vb[cur],
-                       kb[cur ^ 1], vb[cur ^ 1], n, 8 * p, static_cast<uint32_t>(p + 1), digoff + p * kRadix,
-                       tilectr + p, status, info);
+    hipLaunchKernelGGL(k_onesweep<K>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1, vals0,
+                       vals1, n, p, static_cast<const GridPlan*>(nullptr), digoff, tilectr, status, info);
     cur ^= 1;
   }
   return cur;
 }
 
 }  // namespace
+
+void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, const GridPlan* plan,
+                        const uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
+                        uint32_t* info, hipStream_t s) {
+  if (n <= 1) return;  // the key kernel's start buffer already is buffer 1 when there is nothing to sort
+  const int64_t tiles32 = ceil_div(n, 256 * sort_items<uint32_t>());
+  const int64_t tiles64 = ceil_div(n, 256 * sort_items<uint64_t>());
+  fill_u32(tilectr, 0, 8, s);
+  fill_u32(reinterpret_cast<uint32_t*>(status), 0, tiles32 * kRadix * 2, s);
+  hipLaunchKernelGGL(k_digit_offsets, dim3(8), dim3(kRadix), 0, s, hist, digoff);
+  for (int p = 0; p < 4; ++p)  // 32-bit keys: at most 4 passes
+    hipLaunchKernelGGL(k_onesweep<uint32_t>, dim3(static_cast<unsigned>(tiles32)), dim3(kBlock), 0, s,
+                       static_cast<uint32_t*>(keys0), static_cast<uint32_t*>(keys1), vals0, vals1, n, p, plan, digoff,
+                       tilectr, status, info);
+  for (int p = 0; p < 8; ++p)  // 64-bit keys
+    hipLaunchKernelGGL(k_onesweep<uint64_t>, dim3(static_cast<unsigned>(tiles64)), dim3(kBlock), 0, s,
+                       static_cast<uint64_t*>(keys0), static_cast<uint64_t*>(keys1), vals0, vals1, n, p, plan,
+                       digoff, tilectr, status, info);
+}
 
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
                uint32_t* hist, bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,

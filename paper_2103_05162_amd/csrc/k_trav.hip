@@ -1085,9 +1085,26 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
 // primitive: a segmented OR over the wavefront's 64 primitives, and for its last
 // brick the following primitives of the same brick, read 64 at a time.
 // It also clears the list counters of k_lone_filter, which runs after it.
+// Primitive keys are 64-bit words; the isolated-point test runs on grids keyed in
+// 32 bits, so only the low word carries the key.
+__device__ __forceinline__ uint32_t key32(const uint64_t* __restrict__ pkey, int64_t p) {
+  return static_cast<uint32_t>(pkey[p]);
+}
+
+// Clears the occupancy words (as many as the plan asks for; none when the test
+// does not run).
+__global__ __launch_bounds__(256) void k_lone_clear(const GridPlan* __restrict__ plan, uint64_t* __restrict__ bits) {
+  if (!plan->lone_on) return;
+  const int64_t words = plan->lone_words;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < words; i += int64_t(gridDim.x) * blockDim.x)
+    bits[i] = 0ull;
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ pkey, const int* __restrict__ d_m,
-                                                   uint64_t* __restrict__ bits, int* __restrict__ list_n) {
+__global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ pkey, const int* __restrict__ d_m,
+                                                   const GridPlan* __restrict__ plan, uint64_t* __restrict__ bits,
+                                                   int* __restrict__ list_n) {
+  if (!plan->lone_on) return;
   if (blockIdx.x == 0 && threadIdx.x < kNumXcd) list_n[threadIdx.x] = 0;
   const int m = *d_m;
   const int lane = lane_id();
@@ -1096,7 +1113,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ 
   for (int64_t p0 = (blockIdx.x * int64_t(blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; p0 < m; p0 += waves * 64) {
     const int64_t p = p0 + lane;
     const bool valid = p < m;
-    const uint32_t code = valid ? lone_code<D>(pkey[p]) : 0xffffffffu;
+    const uint32_t code = valid ? lone_code<D>(key32(pkey, p)) : 0xffffffffu;
     const uint32_t word = code >> 6;  // invalid lanes: above every valid brick
     const uint32_t prevw = static_cast<uint32_t>(__shfl_up(static_cast<int>(word), 1));
     const uint32_t nextw = static_cast<uint32_t>(__shfl_down(static_cast<int>(word), 1));
@@ -1116,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ 
     const uint32_t w0 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 0));
     // the wavefront's first run may continue a brick begun by the previous
     // wavefront, which then writes it
-    const bool continued = p0 > 0 && (lone_code<D>(pkey[p0 - 1]) >> 6) == w0;
+    const bool continued = p0 > 0 && (lone_code<D>(key32(pkey, p0 - 1)) >> 6) == w0;
     const bool in_first_run = __popcll(ballot(head) & (lanemask_lt() | (1ull << lane))) == 1;
     const uint32_t w63 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 63));
     uint64_t extra = 0;
@@ -1125,7 +1142,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint32_t* __restrict__ 
     if (p0 + 64 < m && !(continued && w63 == w0)) {
       for (int64_t b = p0 + 64; b < m; b += 64) {
         const int64_t q = b + lane;
-        const uint32_t c2 = q < m ? lone_code<D>(pkey[q]) : 0xffffffffu;
+        const uint32_t c2 = q < m ? lone_code<D>(key32(pkey, q)) : 0xffffffffu;
         const bool in = q < m && (c2 >> 6) == w63;
         uint64_t x = in ? (1ull << brick_bit<D>(c2)) : 0ull;
 #pragma unroll
@@ -1190,10 +1207,11 @@ __device__ __forceinline__ uint64_t axis_bits(int a, int l, int h) {
 // cell (they would be next to it in key order) and the neighbouring lone cells are
 // all empty. Conservative: a false answer only means "walk it".
 template <int D>
-__device__ __forceinline__ bool isolated(const uint32_t* __restrict__ pkey, int m, int p, const LoneGeom& g,
+__device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int m, int p, const LoneGeom& g,
                                          const uint64_t* __restrict__ bits) {
-  const uint32_t lc = lone_code<D>(pkey[p]);
-  if ((p > 0 && lone_code<D>(pkey[p - 1]) == lc) || (p + 1 < m && lone_code<D>(pkey[p + 1]) == lc)) return false;
+  const uint32_t lc = lone_code<D>(key32(pkey, p));
+  if ((p > 0 && lone_code<D>(key32(pkey, p - 1)) == lc) || (p + 1 < m && lone_code<D>(key32(pkey, p + 1)) == lc))
+    return false;
   constexpr int S = kBrickShift<D>, W = 1 << S;
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
@@ -1247,10 +1265,15 @@ __device__ __forceinline__ int64_t lone_segment(int m) {
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint32_t* __restrict__ pkey, LoneGeom g,
+__global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint64_t* __restrict__ pkey,
+                                                     const GridPlan* __restrict__ plan,
                                                      const uint64_t* __restrict__ bits, int* __restrict__ list,
                                                      int* __restrict__ list_n) {
   __shared__ int s_cnt[kLoneRounds * 4 + 1];
+  if (!plan->lone_on) return;
+  LoneGeom g;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.nl[k] = k < D ? (plan->ncell[k] + 1) / 2 : 1;
   const int m = tree_m(a.t);
   const int64_t base = blockIdx.x * int64_t(kLoneRounds * 256);
   if (base >= m) return;  // whole workgroup
@@ -1317,12 +1340,13 @@ __global__ void k_core_dbx(TravArgs a) {
   static_assert(kCoreQ == 1, "a listed query is one primitive");
   // listed queries: XCD x (workgroup index mod kNumXcd) takes segment x of the list
   const int xcd = static_cast<int>(blockIdx.x % kNumXcd);
-  const int* qlist = a.core_list ? a.core_list + xcd * lone_segment(m) : nullptr;
-  const int64_t total = a.core_list ? a.core_qn[xcd] : (m + kCoreQ - 1) / kCoreQ;
-  const int64_t k0 = a.core_list ? int64_t(blockIdx.x / kNumXcd) * blockDim.x
-                                 : xcd_spread(blockIdx.x, blockDim.x, 0, total);
+  const bool listed = a.core_list && (!a.lone_on || *a.lone_on);
+  const int* qlist = listed ? a.core_list + xcd * lone_segment(m) : nullptr;
+  const int64_t total = listed ? a.core_qn[xcd] : (m + kCoreQ - 1) / kCoreQ;
+  const int64_t k0 = listed ? int64_t(blockIdx.x / kNumXcd) * blockDim.x
+                            : xcd_spread(blockIdx.x, blockDim.x, 0, total);
   if (k0 < 0 || k0 >= total) return;
-  const int64_t k = a.core_list ? k0 + threadIdx.x : xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, total);
+  const int64_t k = listed ? k0 + threadIdx.x : xcd_spread(blockIdx.x, blockDim.x, threadIdx.x, total);
   int p[kCoreQ], i[kCoreQ], cnt[kCoreQ];
   bool mine[kCoreQ], active[kCoreQ];
   Scope sc[kCoreQ];
@@ -1826,14 +1850,16 @@ inline dim3 grid_of(int64_t n, int block) {
 }
 
 template <int D>
-void lone_t(const TravArgs& a, const uint32_t* pkey, const LoneGeom& g, uint64_t* bits, int64_t words, int* list,
-            int* list_n, hipStream_t s) {
-  fill_u32(reinterpret_cast<uint32_t*>(bits), 0, 2 * words, s);
+void lone_t(const TravArgs& a, const uint64_t* pkey, const GridPlan* plan, uint64_t* bits, int* list, int* list_n,
+            hipStream_t s) {
+  // the plan allows at most n / 2 words (the bitmap lives in an n-int buffer)
+  const int64_t gc = std::min<int64_t>(std::max<int64_t>(ceil_div(a.n / 2, 256 * 4), 1), 2048);
+  hipLaunchKernelGGL(k_lone_clear, dim3(static_cast<unsigned>(gc)), dim3(256), 0, s, plan, bits);
   const int64_t gb = std::min<int64_t>(ceil_div(a.t.m_cap, 256), 4096);  // 4 wavefronts of 64 primitives
   hipLaunchKernelGGL(k_lone_bits<D>, dim3(static_cast<unsigned>(gb > 0 ? gb : 1)), dim3(256), 0, s, pkey, a.t.d_m,
-                     bits, list_n);
+                     plan, bits, list_n);
   const int64_t gf = ceil_div(a.t.m_cap, kLoneRounds * 256);
-  hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, g,
+  hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, plan,
                      bits, list, list_n);
 }
 
@@ -1842,10 +1868,11 @@ void core_t(const TravArgs& a, bool densebox, hipStream_t s) {
   const dim3 g = grid_of(a.n, a.block), b(a.block);
   const size_t lds = sizeof(int) * kRecNb * a.block;  // neighbour records
   if (densebox && a.core_list) {
-    // kNumXcd segments of at most lone_segment(m) <= this many listed queries
+    // kNumXcd segments of at most lone_segment(m) <= this many listed queries, or
+    // (when the plan turns the list off) every primitive
     const int64_t share = kLoneRounds * 256;
     const int64_t seg = ceil_div(ceil_div(a.t.m_cap, kNumXcd), share) * share;
-    const int64_t gl = kNumXcd * ceil_div(seg, a.block);
+    const int64_t gl = std::max<int64_t>(kNumXcd * ceil_div(seg, a.block), grid_of(ceil_div(a.n, kCoreQ), a.block).x);
     hipLaunchKernelGGL((k_core_dbx<D, B>), dim3(static_cast<unsigned>(gl)), b, kCoreQ * lds, s, a);
   } else if (densebox) {
     hipLaunchKernelGGL((k_core_dbx<D, B>), grid_of(ceil_div(a.n, kCoreQ), a.block), b, kCoreQ * lds, s, a);
@@ -1903,13 +1930,11 @@ void main_dispatch(const TravArgs& a, bool densebox, bool all_core, bool first_b
 
 }  // namespace
 
-void launch_lone_filter(const TravArgs& a, int dim, const uint32_t* prim_key, const uint32_t* ncell, uint64_t* bits,
-                        int64_t words, int* list, int* list_n, hipStream_t s) {
+void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint64_t* bits,
+                        int* list, int* list_n, hipStream_t s) {
   if (a.n <= 0) return;
-  LoneGeom g;
-  for (int k = 0; k < 3; ++k) g.nl[k] = k < dim ? (ncell[k] + 1) / 2 : 1;
-  if (dim == 3) lone_t<3>(a, prim_key, g, bits, words, list, list_n, s);
-  else lone_t<2>(a, prim_key, g, bits, words, list, list_n, s);
+  if (dim == 3) lone_t<3>(a, prim_key, plan, bits, list, list_n, s);
+  else lone_t<2>(a, prim_key, plan, bits, list, list_n, s);
 }
 
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {

@@ -5,6 +5,12 @@ stores the canonical labels' and core flags' SHA-256 (int32 / uint8, little
 endian), K, the core / border / noise counts, and the neighbour-count sums
 used by the cost model (sum |N_eps(x)| and sum min(|N_eps(x)|, minPts)).
 
+Two more files cover the many-cloud workloads, cloud by cloud:
+  * c4_batched_4096: every cloud of the 4096-cloud batch, K and the first 16 hex
+    digits of the SHA-256 of its canonical labels and core flags;
+  * c5_served_sample: the same for a fixed sample of requests of the served trace
+    (the requests' clouds, eps and minPts as the trace draws them).
+
     python tests/golden/make_golden.py [name ...]
 """
 import hashlib
@@ -20,7 +26,12 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from workloads.gen import CONFIGS, workload  # noqa: E402
+from workloads.gen import CONFIGS, batched_clouds, served_trace, workload  # noqa: E402
+
+# the served trace as the benchmark replays it, and the requests sampled from it
+SERVED = dict(requests=22000, rate=2000.0, pool_per_dim=32)
+SERVED_WARM_S = 1.0
+SERVED_SAMPLE = 48
 
 
 def summarize(name: str) -> dict:
@@ -45,9 +56,56 @@ def summarize(name: str) -> dict:
     }
 
 
+def _sha16(a) -> str:
+    return hashlib.sha256(a.tobytes()).hexdigest()[:16]
+
+
+def _cloud_entry(pts, eps, mp, threads):
+    labels, core, k = oracle.dbscan(pts, float(eps), int(mp), method="auto", threads=threads)
+    return [int(k), _sha16(labels.astype("<i4")), _sha16(core.astype(np.uint8))]
+
+
+def summarize_batched() -> dict:
+    threads = len(os.sched_getaffinity(0))
+    clouds, eps, mp = batched_clouds(4096)
+    t0 = time.time()
+    per = []
+    for c, pts in enumerate(clouds):
+        per.append(_cloud_entry(pts, eps[c], mp[c], threads))
+        if c % 512 == 511:
+            print(f"  c4: {c + 1} clouds, {time.time() - t0:.0f} s", flush=True)
+    return {"workload": "c4_batched_4096", "num_clouds": len(clouds), "n": int(sum(len(c) for c in clouds)),
+            "eps_sha256": hashlib.sha256(eps.astype("<f4").tobytes()).hexdigest(),
+            "points_sha256_first_cloud": hashlib.sha256(clouds[0].astype("<f4").tobytes()).hexdigest(),
+            "clouds": per, "oracle_seconds": round(time.time() - t0, 1), "threads": threads}
+
+
+def served_sample_indices(arrival):
+    first = int(np.searchsorted(arrival, SERVED_WARM_S))
+    rng = np.random.default_rng(0)
+    return np.sort(rng.choice(np.arange(first, len(arrival)), size=SERVED_SAMPLE, replace=False))
+
+
+def summarize_served() -> dict:
+    threads = len(os.sched_getaffinity(0))
+    pool, req = served_trace(**SERVED)
+    idx = served_sample_indices(req["arrival_s"])
+    t0 = time.time()
+    per = []
+    for r in idx:
+        d, c = int(req["dim"][r]), int(req["cloud"][r])
+        k, ls, cs = _cloud_entry(pool[d][c], req["eps"][r], req["min_pts"][r], threads)
+        per.append([int(r), d, c, int(req["n"][r]), k, ls, cs])
+    return {"workload": "c5_served_sample", "trace": SERVED, "warm_s": SERVED_WARM_S,
+            "requests": per, "oracle_seconds": round(time.time() - t0, 1), "threads": threads}
+
+
+EXTRA = {"c4_batched_4096": summarize_batched, "c5_served_sample": summarize_served}
+
+
 def main(names):
-    for name in names or list(CONFIGS):
-        out = summarize(name)
+    for name in names or list(CONFIGS) + list(EXTRA):
+        out = EXTRA[name]() if name in EXTRA else summarize(name)
         with open(os.path.join(HERE, f"{name}.json"), "w") as f:
             json.dump(out, f, indent=1)
         print(json.dumps(out), flush=True)

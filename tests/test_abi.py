@@ -20,7 +20,8 @@ def _declared():
 def test_header_declares_the_entry_points():
     names = _declared()
     for must in ("fdb_create", "fdb_destroy", "fdb_workspace_bytes", "fdb_dbscan", "fdb_last_info",
-                 "fdb_status_string", "fdb_set_timing", "fdb_stage_times"):
+                 "fdb_last_status", "fdb_status_string", "fdb_set_timing", "fdb_stage_times", "fdb_dbscan_batched",
+                 "fdb_tune", "fdb_tune_batched", "fdb_tuned_options"):
         assert must in names
 
 
@@ -61,7 +62,41 @@ def test_workspace_is_linear_in_n_and_rejects_bad_arguments():
     assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
     bad = _lib.make_options("fdbscan", "canonical", block_size=100)
     assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    for tile in (-1, 4, 65):
+        bad = _lib.make_options("densebox", "canonical", tile=tile)
+        assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    bad = _lib.make_options("densebox", "canonical", flags=2)
+    assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
+    for ok in (_lib.make_options("densebox", tile=8), _lib.make_options("densebox", tile=64, graph=True)):
+        assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(ok), ctypes.byref(out)) == 0
     assert lib.fdb_workspace_bytes(0, 2, None, ctypes.byref(out)) == 0
+
+
+def test_options_struct_matches_the_header():
+    """fdb_options is six 32-bit fields in the header's order (the binding mirrors it)."""
+    import re as _re
+    from paper_2103_05162_amd import _lib
+    text = open(HEADER).read()
+    body = _re.search(r"typedef struct \{(.*?)\} fdb_options;", text, flags=_re.S).group(1)
+    body = _re.sub(r"/\*.*?\*/", "", body, flags=_re.S)
+    fields = _re.findall(r"(?:int32_t|uint32_t)\s+(\w+);", body)
+    assert fields == [f for f, _ in _lib.FdbOptions._fields_]
+    assert ctypes.sizeof(_lib.FdbOptions) == 24
+
+
+def test_tune_and_status_arguments_are_checked_before_any_gpu_call():
+    from paper_2103_05162_amd import _lib
+    lib = _lib.load()
+    best = _lib.FdbOptions()
+    ms = (ctypes.c_double * 2)()
+    assert lib.fdb_tune(None, None, 10, 3, ctypes.c_float(0.1), 5, None, 3, None, None, None, 0, None,
+                        ctypes.byref(best), ms) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_tune_batched(None, None, 10, None, 1, 3, None, None, None, 3, None, None, None, None, 0, None,
+                                ctypes.byref(best), ms) == _lib.FDB_ERR_INVALID
+    assert lib.fdb_tuned_options(None, 10, 3, 5, 0, None, ctypes.byref(best)) == _lib.FDB_ERR_INVALID
+    v = ctypes.c_uint32(0)
+    assert lib.fdb_last_status(None, None, ctypes.byref(v)) == _lib.FDB_ERR_INVALID
+    assert "another thread" in _lib.status_string(_lib.FDB_ERR_BUSY)
 
 
 def test_null_handle_is_rejected_before_any_gpu_call():

@@ -162,3 +162,78 @@ def test_batch_dbscan_star(dev, algo):
         rl, rc, rk = oracle.dbscan_star(pts, float(eps[c]), int(mp[c]))
         sl = slice(offs[c], offs[c + 1])
         assert k[c] == rk and np.array_equal(core[sl], rc) and np.array_equal(labels[sl], rl), c
+
+
+_LANE = {}
+
+
+def _lane_batch():
+    """~150 clouds of tight 6-point clumps: more than 65,536 dense cells in the
+    batch as a whole, so the dense-cell main phase takes one lane per cell."""
+    if not _LANE:
+        rng = np.random.default_rng(93)
+        clouds, eps, mp = [], [], []
+        for c in range(150):
+            k = int(rng.integers(550, 750))
+            cen = rng.uniform(0, 1, size=(k, 3))
+            pts = np.repeat(cen, 6, axis=0) + 1e-4 * rng.standard_normal((k * 6, 3))
+            noise = rng.uniform(0, 1, size=(int(rng.integers(0, 300)), 3))
+            pts = np.concatenate([pts, noise])[rng.permutation(k * 6 + len(noise))]
+            clouds.append(pts.astype(np.float32))
+            eps.append(float(np.float32(rng.uniform(0.002, 0.004))))
+            mp.append(int(rng.choice([3, 4, 6])))
+        _LANE["case"] = (clouds, np.asarray(eps, np.float32), np.asarray(mp, np.int32))
+    return _LANE["case"]
+
+
+@pytest.mark.parametrize("border", ["canonical", "first", "none"])
+def test_batch_lane_per_cell_kernel_matches_oracle(dev, border):
+    import paper_2103_05162_amd as fdb
+    clouds, eps, mp = _lane_batch()
+    _say(f"[gpu] lane-per-cell batch: {len(clouds)} clouds, {sum(map(len, clouds))} points ({border})")
+    offs, labels, core, k, info = _run_batch(dev, clouds, eps, mp, "densebox", border=border)
+    assert info == 0
+    assert fdb.default_handle(0).last_counts()["dense_cells"] > 65536
+    for c, pts in enumerate(clouds):
+        sl = slice(offs[c], offs[c + 1])
+        if border == "none":
+            rl, rc, rk = oracle.dbscan_star(pts, float(eps[c]), int(mp[c]))
+        else:
+            rl, rc, rk = oracle.dbscan(pts, float(eps[c]), int(mp[c]))
+        assert k[c] == rk, (c, k[c], rk)
+        if border == "first":
+            assert_tolerance_mode(pts, float(eps[c]), labels[sl], core[sl], rl, rc, oracle.check_border)
+        else:
+            assert np.array_equal(core[sl], rc) and np.array_equal(labels[sl], rl), c
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_cloud_wider_than_the_key_range(dev, dim):
+    """A cloud whose extent over the DenseBox cell side exceeds the key bits a
+    batch leaves per axis (its cell coordinates are clamped at the top): clumps
+    near the origin and far out, all clustered as the oracle does."""
+    rng = np.random.default_rng(94 + dim)
+    clouds, eps, mp = [], [], []
+    for c in range(5):
+        pts = rng.uniform(0, 1, size=(800, dim)) * 0.2
+        pts = np.concatenate([pts, 0.1 + 0.003 * rng.standard_normal((400, dim))])
+        clouds.append(pts.astype(np.float32))
+        eps.append(0.01)
+        mp.append(4)
+    # bits per axis below the cloud id: floor((64 - ceil(log2 5)) / d), at most 21 (3D) / 31 (2D)
+    bpd = min(21 if dim == 3 else 31, (64 - 3) // dim)
+    far = 1.5 * (2 ** bpd) * 0.01 / np.sqrt(dim)   # beyond the last key cell on every axis
+    wide = np.concatenate([0.003 * rng.standard_normal((300, dim)),
+                           far + 0.003 * rng.standard_normal((300, dim)),
+                           1.3 * far + 0.003 * rng.standard_normal((300, dim)),
+                           far * rng.uniform(0, 1.3, size=(200, dim))]).astype(np.float32)
+    clouds[2] = wide[rng.permutation(len(wide))]
+    eps, mp = np.asarray(eps, np.float32), np.asarray(mp, np.int32)
+    offs, labels, core, k, info = _run_batch(dev, clouds, eps, mp, "densebox")
+    assert info == 0
+    for c, pts in enumerate(clouds):
+        rl, rc, rk = oracle.dbscan(pts, float(eps[c]), int(mp[c]))
+        sl = slice(offs[c], offs[c + 1])
+        assert k[c] == rk and np.array_equal(core[sl], rc) and np.array_equal(labels[sl], rl), c
+    rl, rc, rk = oracle.dbscan(clouds[2], float(eps[2]), int(mp[2]))
+    assert rk >= 3 and rc.sum() > 600

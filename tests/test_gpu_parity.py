@@ -329,22 +329,77 @@ def test_c1_dbscan_star(dev, algo):
 
 
 def test_automatic_choice(dev):
-    """FDB_ALGO_AUTO runs DenseBox, and FDbscan when the grid cannot be keyed;
-    labels exact either way."""
+    """FDB_ALGO_AUTO runs DenseBox; when the eps grid is too wide for 64-bit keys
+    its cells are widened (FDB_INFO_DENSEBOX_FALLBACK); labels exact either way."""
     import paper_2103_05162_amd as fdb
     h = fdb.default_handle(0)
     w = workload("c3_dense3d_8m", 1 / 64)
     assert_exact(dev, w.points, w.eps, w.min_pts, "auto")
-    assert not h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+    assert not h.last_info() & (fdb.FDB_INFO_AUTO_FDBSCAN | fdb.FDB_INFO_DENSEBOX_FALLBACK)
+    assert h.last_counts()["dense_cells"] > 0
     rng = np.random.default_rng(5)
     sparse = rng.uniform(0, 1, size=(60000, 3)).astype(np.float32)
     assert_exact(dev, sparse, 0.02, 5, "auto")
-    assert not h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
-    # eps tiny against the extent: no 64-bit grid key, so FDbscan runs
+    assert not h.last_info() & fdb.FDB_INFO_DENSEBOX_FALLBACK
+    # eps tiny against the extent: the grid cannot be keyed at eps/sqrt(3)
     wide = sparse.copy()
     wide[0] = (1e7, 1e7, 1e7)
     assert_exact(dev, wide, 1e-3, 3, "auto")
-    assert h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+    assert h.last_info() & fdb.FDB_INFO_DENSEBOX_FALLBACK
+    assert not h.last_info() & fdb.FDB_INFO_AUTO_FDBSCAN
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_grid_keyed_in_64_bits(dev, d):
+    """A DenseBox grid needing more than 32 key bits (3D: > 1024 cells per axis,
+    2D: > 65536) but fitting 64: the device-sized plan picks 64-bit keys and the
+    64-bit sort passes; dense clumps and sparse points alike match the oracle."""
+    import paper_2103_05162_amd as fdb
+    rng = np.random.default_rng(120 + d)
+    eps = 4e-4 if d == 3 else 8e-6
+    cen = rng.uniform(0, 1, size=(300, d))
+    clumps = np.repeat(cen, 40, axis=0) + 0.3 * eps * rng.standard_normal((12000, d))
+    pts = np.concatenate([clumps, rng.uniform(0, 1, size=(20000, d))]).astype(np.float32)
+    pts = pts[rng.permutation(len(pts))]
+    for mp in (2, 5, 30):
+        ref = assert_exact(dev, pts, eps, mp, "densebox")
+        assert not fdb.default_handle(0).last_info() & fdb.FDB_INFO_DENSEBOX_FALLBACK
+        if mp == 5:
+            assert fdb.default_handle(0).last_counts()["dense_cells"] > 100
+            assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
+
+
+def _boundary_pairs(rng, d, eps, word, mp, count):
+    """Pairs (a, b) at distance just inside eps that straddle occupancy-word
+    boundaries: "axis" pairs cross one axis's boundary at a random place on the
+    other axes, "corner" pairs cross every axis's boundary at once (one pair per
+    word corner). Behind each b, away from a, mp - 1 points are packed within
+    0.35 eps of b and more than 1.05 eps from a, so b is core and a (2 neighbours)
+    is a border point of b's cluster: an a wrongly taken as isolated turns into
+    noise and fails the comparison."""
+    nw = int(0.9 / word)
+    corners = np.stack(np.meshgrid(*[np.arange(1, nw)] * d, indexing="ij"), -1).reshape(-1, d) * word
+    ud = np.ones(d) / np.sqrt(d)
+    cand = [(c - 0.3 * eps * ud + rng.uniform(-1e-3, 1e-3, size=d) * eps, ud)
+            for c in corners[rng.permutation(len(corners))[:count]]]
+    for _ in range(20 * count):
+        ax = int(rng.integers(0, d))
+        u = np.zeros(d)
+        u[ax] = 1.0
+        a = rng.uniform(0.05, 0.95, size=d)
+        a[ax] = rng.integers(1, nw) * word - 0.3 * eps
+        cand.append((a, u))
+    pairs = []  # pairs kept 3.5 eps apart, so no pair reaches another
+    for a, u in cand:
+        if len(pairs) < 2 * count and all(np.linalg.norm(a - p[0]) > 3.5 * eps for p in pairs):
+            pairs.append((a, u))
+    out = []
+    for a, u in pairs:
+        b = a + eps * (1 - 1e-6) * u
+        jit = rng.uniform(-0.05, 0.05, size=(mp - 1, d)) * eps
+        pack = b + (0.15 + 0.1 * rng.random((mp - 1, 1))) * eps * u + jit
+        out += [a[None], b[None], pack]
+    return np.concatenate(out), len(pairs)
 
 
 @pytest.mark.parametrize("d", [2, 3])
@@ -352,26 +407,48 @@ def test_isolated_point_test_edges(dev, d):
     """The DenseBox isolated-point test on its edges: a blob of thousands of
     point primitives (no dense cell at minPts 40) whose runs within one occupancy
     word span many wavefronts; pairs just inside eps straddling word boundaries
-    on every axis at once; scattered points that are mostly alone; and a cloud
-    spanning under two grid cells (a one-word map)."""
+    (on one axis, and on every axis at once) whose far partner is core, so their
+    near point must come out as a border point; scattered points that are mostly
+    alone; and clouds spanning a few grid cells (a one-word map) with core,
+    border and noise points in them."""
     rng = np.random.default_rng(70 + d)
     eps = 0.03 if d == 3 else 0.02
     h = eps / np.sqrt(d)              # grid cell side (the bounds below start at 0)
     word = (8 if d == 3 else 16) * h   # side of the cells one occupancy word covers
     blob = 0.5 + rng.uniform(0, 4 * eps, size=(5000 if d == 3 else 3000, d))
     scattered = rng.uniform(0, 1, size=(2000 if d == 3 else 400, d))
-    u = np.ones(d) / np.sqrt(d)
-    k = rng.integers(1, int(0.9 / word), size=(300, 1))
-    a = k * word - 0.3 * eps * u + rng.uniform(-1e-3, 1e-3, size=(300, d)) * eps
-    b = a + eps * (1 - 1e-6) * u
     corners = np.array([np.zeros(d), np.ones(d)])
-    pts = np.concatenate([blob, scattered, a, b, corners]).astype(np.float32)
+    pts = np.concatenate([blob, scattered, corners]).astype(np.float32)
     rng.shuffle(pts)
-    for mp in (2, 40):
+    ref = assert_exact(dev, pts, eps, 40, "densebox")
+    assert (ref[0] == -1).sum() > 100 and ref[1].sum() > 1000
+    for mp in (3, 5):
+        pairs, npairs = _boundary_pairs(rng, d, eps, word, mp, 150)
+        pts = np.concatenate([pairs, scattered, corners]).astype(np.float32)
+        # a points sit at rows 0, mp + 1, 2 (mp + 1), ... of `pairs`
+        a_rows = np.arange(npairs) * (mp + 1)
         ref = assert_exact(dev, pts, eps, mp, "densebox")
-        assert (ref[0] == -1).sum() > 100 and ref[1].sum() > 1000
-    tiny = (rng.uniform(0, 1.5 * h, size=(40, d))).astype(np.float32)
-    ref = assert_exact(dev, tiny, eps, 2, "densebox")
+        border = (~ref[1]) & (ref[0] >= 0)
+        assert border[a_rows].sum() > 0.7 * npairs, "most near points must be border points"
+        assert ref[1][a_rows + 1].all(), "every far partner must be core"
+        assert_exact(dev, pts, eps, mp, "fdbscan", ref=ref)
+    # one-word maps: a tight core group, a bridge point, a border point 1.2 eps
+    # from the group, a noise pair and an isolated point, within 7 cells per axis
+    for mp in (2, 3):
+        e = np.zeros(d); e[0] = 1.0
+        grp = 0.5 * h + rng.uniform(0, 0.02 * eps, size=(5, d))
+        bridge = grp[0] + 0.6 * eps * e
+        bpt = bridge + 0.6 * eps * e
+        far = np.full(d, 6.5 * h)
+        pair = np.stack([far - 0.2 * eps * e, far - 0.2 * eps * e - 0.5 * eps * np.roll(e, 1)])
+        lone = np.zeros(d); lone[-1] = 6.5 * h
+        tiny = np.concatenate([grp, bridge[None], bpt[None], pair, lone[None]]).astype(np.float32)
+        ref = assert_exact(dev, tiny, eps, mp, "densebox")
+        if mp == 3:
+            assert ref[1][:6].all() and not ref[1][6] and ref[0][6] == ref[0][0]
+            assert (ref[0][7:] == -1).all()
+    dense_tiny = rng.uniform(0, 1.5 * h, size=(40, d)).astype(np.float32)
+    ref = assert_exact(dev, dense_tiny, eps, 2, "densebox")
     assert ref[1].all() and ref[2] == 1
 
 
