@@ -105,7 +105,11 @@ enum {
      the buffers' addresses, so it is replayed only for exactly the same pointers,
      sizes and parameters; anything else records a new one (the handle keeps the
      16 most recent). Results are those of the plain call. */
-  FDB_FLAG_GRAPH = 1u
+  FDB_FLAG_GRAPH = 1u,
+  /* Debug: after the fused main phase, check the union-find forest it left
+     (fdb_debug_forest states the invariants) and raise FDB_INFO_FOREST if any
+     point breaks them. One extra pass over the labels; labels are unchanged. */
+  FDB_FLAG_VALIDATE = 2u
 };
 
 /* Information bits, read with fdb_last_info(). */
@@ -118,8 +122,9 @@ enum {
   FDB_INFO_INTERNAL = 4u,          /* a kernel stopped a walk that broke its own bounds; labels undefined */
   FDB_INFO_BAD_PARAMS = 8u,        /* batch: some cloud's eps is not finite and > 0, or its minPts < 1;
                                       that cloud's labels are undefined */
-  FDB_INFO_AUTO_FDBSCAN = 16u      /* no longer raised: the automatic choice always runs DenseBox (a grid
+  FDB_INFO_AUTO_FDBSCAN = 16u,     /* no longer raised: the automatic choice always runs DenseBox (a grid
                                       too wide for 64-bit keys raises FDB_INFO_DENSEBOX_FALLBACK) */
+  FDB_INFO_FOREST = 32u            /* FDB_FLAG_VALIDATE: the union-find forest broke its invariants */
 };
 
 /* Create a handle bound to HIP device `device`. *out receives the handle. */
@@ -248,6 +253,16 @@ fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts);
 fdb_status fdb_set_timing(fdb_handle* h, int32_t enable);
 fdb_status fdb_stage_times(fdb_handle* h, int32_t max, const char** h_names, double* h_ms, int32_t* h_count,
                            int32_t* h_calls);
+
+/* Test hook (synchronous): count the points of a union-find forest parent[n]
+   (device int32, every entry a point index) that break the invariants the fused
+   main phase keeps (Section 3.2's union and claim steps, with roots hooked
+   smaller-index-first): a core point's parent is a core point with a smaller
+   index (or itself), and any other point's parent is itself or a core point;
+   an entry outside [0, n) counts too. is_core: device uint8 [n], or NULL when
+   every point is core. *h_bad receives the count. */
+fdb_status fdb_debug_forest(fdb_handle* h, const int32_t* parent, const uint8_t* is_core, int64_t n,
+                            int64_t* h_bad);
 
 /* Test hook (synchronous, allocates; not for production use): build the LBVH over m
    sorted 64-bit keys h_keys (Karras' hierarchy, ties by index; Section 4.1), return

@@ -7,14 +7,15 @@ include/fdbscan.h); this package marshals torch tensors into that ABI.
 """
 from __future__ import annotations
 
-from ._lib import (FDB_ERR_BUSY, FDB_FLAG_GRAPH, FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS,
-                   FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError, Handle, Server, load,
+from ._lib import (FDB_ERR_BUSY, FDB_FLAG_GRAPH, FDB_FLAG_VALIDATE, FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS,
+                   FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_FOREST, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError, Handle, Server, load,
                    make_options, options_dict, status_string, workspace_bytes, workspace_bytes_batched)
 
 __all__ = ["dbscan", "dbscan_batched", "dbscan_batched_host", "tune", "tune_batched", "Handle", "Server", "FdbError",
            "workspace_bytes", "workspace_bytes_batched", "default_handle", "load", "make_options", "options_dict",
            "status_string", "FDB_INFO_DENSEBOX_FALLBACK", "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL",
-           "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN", "FDB_FLAG_GRAPH", "FDB_ERR_BUSY"]
+           "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN", "FDB_FLAG_GRAPH", "FDB_ERR_BUSY",
+           "FDB_FLAG_VALIDATE", "FDB_INFO_FOREST"]
 
 _handles: dict[int, Handle] = {}
 
@@ -38,7 +39,7 @@ def _check_out(labels, is_core, n):
 
 def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str = "canonical",
            leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
-           want_k: bool = True, workspace=None, tile: int = 0, graph: bool = False):
+           want_k: bool = True, workspace=None, tile: int = 0, graph: bool = False, validate: bool = False):
     """Cluster points ([n, 2] or [n, 3] float32 torch tensor on a HIP device).
 
     Returns (labels int32 [n], is_core bool [n], K). labels are in input order:
@@ -46,7 +47,8 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     border="none" is DBSCAN*: every non-core point is noise).
     K is None when want_k is False (then the call does not wait for the GPU).
     graph=True replays a recorded HIP graph of the launch sequence for repeated
-    calls with the same buffers and parameters.
+    calls with the same buffers and parameters. validate=True checks the
+    union-find forest after the main phase (FDB_INFO_FOREST on a violation).
     """
     import torch
 
@@ -63,7 +65,7 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     if is_core is None:
         is_core = torch.empty(n, dtype=torch.uint8, device=pts.device)
     _check_out(labels, is_core, n)
-    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph)
+    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph, validate=validate)
     stream = torch.cuda.current_stream(pts.device).cuda_stream
     ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
         else (None, 0)
@@ -74,7 +76,7 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
 
 def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border: str = "canonical",
                    leaf_size: int = 0, block_size: int = 0, handle: Handle | None = None, labels=None, is_core=None,
-                   num_clusters=None, workspace=None, tile: int = 0, graph: bool = False):
+                   num_clusters=None, workspace=None, tile: int = 0, graph: bool = False, validate: bool = False):
     """Cluster a batch of clouds in one launch sequence.
 
     points: [N, d] float32 on a HIP device (clouds concatenated); offsets: int64
@@ -106,7 +108,7 @@ def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border:
     _check_out(labels, is_core, n)
     if num_clusters is None:
         num_clusters = torch.empty(b, dtype=torch.int32, device=dev)
-    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph)
+    opt = make_options(algo, border, leaf_size, block_size, tile=tile, graph=graph, validate=validate)
     stream = torch.cuda.current_stream(dev).cuda_stream
     ws_ptr, ws_size = (workspace.data_ptr(), workspace.numel() * workspace.element_size()) if workspace is not None \
         else (None, 0)

@@ -17,7 +17,8 @@ FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX, FDB_ALGO_AUTO = 0, 1, 2
 FDB_BORDER_CANONICAL, FDB_BORDER_FIRST, FDB_BORDER_NONE = 0, 1, 2
 FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FDB_INFO_INTERNAL, FDB_INFO_BAD_PARAMS = 1, 2, 4, 8
 FDB_INFO_AUTO_FDBSCAN = 16
-FDB_FLAG_GRAPH = 1
+FDB_INFO_FOREST = 32
+FDB_FLAG_GRAPH, FDB_FLAG_VALIDATE = 1, 2
 
 ALGOS = {"fdbscan": FDB_ALGO_FDBSCAN, "densebox": FDB_ALGO_DENSEBOX, "auto": FDB_ALGO_AUTO}
 BORDERS = {"canonical": FDB_BORDER_CANONICAL, "first": FDB_BORDER_FIRST, "none": FDB_BORDER_NONE}
@@ -101,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.fdb_last_counts.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fdb_last_counts.restype = ctypes.c_int
     pi32 = ctypes.POINTER(i32)
+    lib.fdb_debug_forest.argtypes = [vp, vp, vp, i64, ctypes.POINTER(i64)]
+    lib.fdb_debug_forest.restype = ctypes.c_int
     lib.fdb_debug_lbvh.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32, i32, i32, pi32, pi32, pi32, pi32]
     lib.fdb_debug_lbvh.restype = ctypes.c_int
     lib.fdb_set_timing.argtypes = [vp, i32]
@@ -136,10 +139,11 @@ def _check(status: int, what: str) -> None:
 
 
 def make_options(algo="fdbscan", border="canonical", leaf_size=0, block_size=0, flags=0, tile=0,
-                 graph=False) -> FdbOptions:
+                 graph=False, validate=False) -> FdbOptions:
     a = ALGOS[algo] if isinstance(algo, str) else int(algo)
     b = BORDERS[border] if isinstance(border, str) else int(border)
-    return FdbOptions(a, b, int(leaf_size), int(block_size), int(tile), int(flags) | (FDB_FLAG_GRAPH if graph else 0))
+    f = int(flags) | (FDB_FLAG_GRAPH if graph else 0) | (FDB_FLAG_VALIDATE if validate else 0)
+    return FdbOptions(a, b, int(leaf_size), int(block_size), int(tile), f)
 
 
 def options_dict(o: FdbOptions) -> dict:
@@ -278,6 +282,14 @@ class Handle:
         v = (ctypes.c_int64 * 4)()
         _check(self._lib.fdb_last_counts(self.ptr, v), "fdb_last_counts")
         return {"clusters": int(v[0]), "cells": int(v[1]), "dense_cells": int(v[2]), "prims": int(v[3])}
+
+    def debug_forest(self, parent_ptr: int, core_ptr: int | None, n: int) -> int:
+        """Test hook: points of the forest parent[n] that break the main phase's invariants."""
+        bad = ctypes.c_int64(-1)
+        _check(self._lib.fdb_debug_forest(self.ptr, ctypes.c_void_p(parent_ptr),
+                                          ctypes.c_void_p(core_ptr) if core_ptr else None, int(n),
+                                          ctypes.byref(bad)), "fdb_debug_forest")
+        return int(bad.value)
 
     def debug_lbvh(self, keys, mask: int = -1, leaf_size: int = 1):
         """Test hook: (gamma, other, leaves reached by a walk masked at `mask`) for sorted keys."""

@@ -239,7 +239,7 @@ bool valid_options(const fdb_options& o) {
   if (o.leaf_size < 0 || o.leaf_size > 1024) return false;
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64 != 0)) return false;
   if (o.tile != 0 && (o.tile < 8 || o.tile > 64)) return false;
-  if (o.flags & ~uint32_t(FDB_FLAG_GRAPH)) return false;
+  if (o.flags & ~uint32_t(FDB_FLAG_GRAPH | FDB_FLAG_VALIDATE)) return false;
   return true;
 }
 
@@ -531,6 +531,19 @@ fdb_status fdb_last_counts(fdb_handle* h, int64_t* h_counts) {
   return FDB_OK;
 }
 
+fdb_status fdb_debug_forest(fdb_handle* h, const int32_t* parent, const uint8_t* is_core, int64_t n,
+                            int64_t* h_bad) {
+  if (!h || !h_bad || n < 0 || n > fdb::kMaxPoints || (n > 0 && !parent)) return FDB_ERR_INVALID;
+  DeviceGuard g(h->device);
+  hipStream_t s = nullptr;
+  fdb::fill_u32(h->d_info, 0, 2, s);
+  fdb::launch_check_forest(parent, is_core, n, h->d_info + 1, h->d_info, s);
+  if (hipMemcpy(h->h_pinned, h->d_info, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return FDB_ERR_HIP;
+  *h_bad = h->h_pinned[1];
+  return FDB_OK;
+}
+
 fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int32_t mask, int32_t leaf_size,
                           int32_t* h_gamma, int32_t* h_other, int32_t* h_leaves, int32_t* h_num_leaves) {
   using namespace fdb;
@@ -710,7 +723,7 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
   h->last_misc = misc;
   h->last_densebox = false;
   h->last_n = n;
-  fill_u32(h->d_info, 0, 1, s);
+  fill_u32(h->d_info, 0, 2, s);  // info bits and the forest check's count
   fill_u32(bounds, 0xffffffffu, 4, s);
   fill_u32(bounds + 4, 0u, 4, s);
   launch_bounds(points, n, dim, bounds, h->d_info, s);
@@ -830,6 +843,7 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     st.mark("main");
     launch_main(ta, dim, false, all_core, first_border && !all_core, 0, s);
   }
+  if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, all_core ? nullptr : core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");
   launch_finalize(lab, n, h->d_info, s);
   if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);
@@ -961,7 +975,7 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
   int* cl_end = at<int>(ws, plan.cl_end);
 
   st.mark("clouds");
-  fill_u32(h->d_info, 0, 1, s);
+  fill_u32(h->d_info, 0, 2, s);  // info bits and the forest check's count
   fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
   int* cl_flags = at<int>(ws, plan.cl_flags);
   batch_prep(points, offsets, num_clouds, n, dim, eps, min_pts, bpd, densebox, at<uint32_t>(ws, plan.cl_ord), cl_lo,
@@ -1056,6 +1070,7 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
     st.mark("main");
     launch_main(ta, dim, false, false, first_border, 0, s);
   }
+  if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");
   launch_finalize(lab, n, h->d_info, s);
   st.mark("cluster_ids");

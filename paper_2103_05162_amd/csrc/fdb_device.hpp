@@ -119,6 +119,7 @@ __device__ __forceinline__ void st_agent64(uint64_t* p, uint64_t v) {
 // Walks are capped: a cycle or a runaway walk (impossible unless something else
 // is broken) raises kInternalBit in *info and stops instead of spinning forever.
 constexpr uint32_t kInternalBit = 4u;  // FDB_INFO_INTERNAL
+constexpr uint32_t kForestBit = 32u;   // FDB_INFO_FOREST
 constexpr int kWalkCap = 1 << 22;
 
 __device__ __forceinline__ int uf_find(int* labels, int x, uint32_t* info) {

@@ -233,6 +233,8 @@ void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int*
 void launch_init_labels(int* labels, int64_t n, hipStream_t s);
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s);
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
+void launch_check_forest(const int* labels, const uint8_t* core, int64_t n, uint32_t* bad, uint32_t* info,
+                         hipStream_t s);
 // Canonical cluster ids (ids 0..K-1 in increasing order of each cluster's
 // smallest core input index). bits: ceil(n/32) leader words followed by as many
 // ints of scratch (fits the n-int lflag array); wpre: ceil(n/32) ints.

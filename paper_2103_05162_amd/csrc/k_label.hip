@@ -43,6 +43,33 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int* labels, int64_t n, uin
   }
 }
 
+// Debug check of the union-find forest the fused main phase leaves (before
+// finalisation). Unions hook the larger root under the smaller one and finds only
+// shorten paths, so a core point's parent is a core point with a smaller index;
+// a claim points a non-core point at a core tree, so any other point's parent is
+// itself or a core point. core == nullptr: every point counts as core (minPts <= 2,
+// whose flags are set only afterwards). Counts the points that break this in
+// *bad and raises kForestBit.
+__global__ __launch_bounds__(kBlock) void k_check_forest(const int* __restrict__ labels,
+                                                         const uint8_t* __restrict__ core, int64_t n,
+                                                         uint32_t* __restrict__ bad, uint32_t* __restrict__ info) {
+  uint32_t cnt = 0;
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
+    const int p = labels[i];
+    bool ok = p >= 0 && p < n;
+    if (ok && p != i) {
+      const bool ci = core ? core[i] != 0 : true;
+      const bool cp = core ? core[p] != 0 : true;
+      ok = cp && (!ci || p < i);
+    }
+    cnt += ok ? 0u : 1u;
+  }
+  if (cnt) {
+    atomicAdd(bad, cnt);
+    atomicOr(info, kForestBit);
+  }
+}
+
 // minPts <= 2 skips the core pass (Algorithm 3). Then every pair within eps is
 // a core pair: with minPts = 2 a point is core iff its set has another member,
 // with minPts = 1 every point is core.
@@ -120,26 +147,47 @@ __global__ __launch_bounds__(kBlock) void k_cluster_ids(const int* __restrict__ 
 // core flag rides in bit 30 of the label (cluster ids stay below 2^30), one
 // random store per point, and k_split_core unpacks it in a coalesced pass.
 constexpr int kCoreBit = 1 << 30;
+constexpr int kScatterItems = 4;
 
 template <bool PACK>
 __global__ __launch_bounds__(kBlock) void k_scatter(const int* __restrict__ labels, const uint8_t* __restrict__ core,
                                                     const uint32_t* __restrict__ perm, const int* __restrict__ cid,
                                                     const int* __restrict__ border, int mode, int64_t n,
                                                     int32_t* __restrict__ out, uint32_t* __restrict__ info) {
-  // mode 0: non-core = noise; 1: non-core from the border pass; 2: first claim
-  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
-    const uint32_t o = perm[i];
-    if (o >= n) {
-      atomicOr(info, kInternalBit);
-      continue;
+  // mode 0: non-core = noise; 1: non-core from the border pass; 2: first claim.
+  // kScatterItems points per thread, their loads issued before any store.
+  const int64_t stride = int64_t(gridDim.x) * kBlock * kScatterItems;
+  for (int64_t base = blockIdx.x * int64_t(kBlock) * kScatterItems + threadIdx.x; base < n; base += stride) {
+    uint32_t o[kScatterItems];
+    int lab[kScatterItems];
+    bool c[kScatterItems];
+#pragma unroll
+    for (int t = 0; t < kScatterItems; ++t) {
+      const int64_t i = base + t * kBlock;
+      const bool in = i < n;
+      o[t] = in ? perm[i] : 0u;
+      c[t] = in && core[i];
+      lab[t] = in ? labels[i] : 0;
     }
-    const bool c = core[i];
-    int v;
-    if (c) v = cid[labels[i]];
-    else if (mode == 1) v = border[i];
-    else if (mode == 2) v = labels[i] != i ? cid[labels[i]] : -1;
-    else v = -1;
-    out[o] = PACK && c && v >= 0 ? (v | kCoreBit) : v;
+    int v[kScatterItems];
+#pragma unroll
+    for (int t = 0; t < kScatterItems; ++t) {
+      const int64_t i = base + t * kBlock;
+      if (c[t]) v[t] = cid[lab[t]];
+      else if (mode == 1) v[t] = i < n ? border[i] : -1;
+      else if (mode == 2) v[t] = lab[t] != i ? cid[lab[t]] : -1;
+      else v[t] = -1;
+    }
+#pragma unroll
+    for (int t = 0; t < kScatterItems; ++t) {
+      const int64_t i = base + t * kBlock;
+      if (i >= n) continue;
+      if (o[t] >= n) {
+        atomicOr(info, kInternalBit);
+        continue;
+      }
+      out[o[t]] = PACK && c[t] && v[t] >= 0 ? (v[t] | kCoreBit) : v[t];
+    }
   }
 }
 
@@ -280,6 +328,12 @@ void launch_init_labels(int* labels, int64_t n, hipStream_t s) {
 
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, info);
+}
+
+void launch_check_forest(const int* labels, const uint8_t* core, int64_t n, uint32_t* bad, uint32_t* info,
+                         hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_check_forest, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, n, bad, info);
 }
 
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s) {

@@ -298,19 +298,41 @@ __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ p
   hist_flush(s_h, passes, hist);
 }
 
-// Gather points into Morton order, structure-of-arrays.
+// Gather points into key order, structure-of-arrays. The reads are random 12-byte
+// rows, so each thread first loads kPermItems indices, then issues all of their
+// row loads before any store: several gathers in flight per lane instead of one.
+constexpr int kPermItems = 4;
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_permute(const float* __restrict__ pts, int64_t n,
                                                     const uint32_t* __restrict__ perm, float* __restrict__ xs,
                                                     uint32_t* __restrict__ info) {
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    int64_t o = perm[i];
-    if (o >= n) {
-      atomicOr(info, kInternalBit);
-      o = 0;
+  const int64_t stride = int64_t(gridDim.x) * kBlock * kPermItems;
+  for (int64_t base = blockIdx.x * int64_t(kBlock) * kPermItems + threadIdx.x; base < n; base += stride) {
+    int64_t o[kPermItems];
+#pragma unroll
+    for (int t = 0; t < kPermItems; ++t) {
+      const int64_t i = base + t * kBlock;
+      o[t] = i < n ? static_cast<int64_t>(perm[i]) : 0;
+    }
+    float v[kPermItems][D];
+#pragma unroll
+    for (int t = 0; t < kPermItems; ++t) {
+      if (o[t] >= n) {
+        atomicOr(info, kInternalBit);
+        o[t] = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) v[t][k] = pts[o[t] * D + k];
     }
 #pragma unroll
-    for (int k = 0; k < D; ++k) xs[k * n + i] = pts[o * D + k];
+    for (int t = 0; t < kPermItems; ++t) {
+      const int64_t i = base + t * kBlock;
+      if (i < n) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xs[k * n + i] = v[t][k];
+      }
+    }
   }
 }
 
@@ -378,7 +400,7 @@ void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bound
 
 void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,
                     hipStream_t s) {
-  int g = grid_for(n, kBlock * 4);
+  int g = grid_for(n, kBlock * kPermItems);
   if (dim == 3)
     hipLaunchKernelGGL(k_permute<3>, dim3(g), dim3(kBlock), 0, s, pts, n, perm, xs, info);
   else

@@ -29,7 +29,7 @@ import oracle  # noqa: E402
 from workloads.gen import CONFIGS, batched_clouds, served_trace, workload  # noqa: E402
 
 # the served trace as the benchmark replays it, and the requests sampled from it
-SERVED = dict(requests=22000, rate=2000.0, pool_per_dim=32)
+SERVED = dict(requests=22000, rate=2000.0, pool_per_dim=128)
 SERVED_WARM_S = 1.0
 SERVED_SAMPLE = 48
 

@@ -65,7 +65,7 @@ def test_workspace_is_linear_in_n_and_rejects_bad_arguments():
     for tile in (-1, 4, 65):
         bad = _lib.make_options("densebox", "canonical", tile=tile)
         assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
-    bad = _lib.make_options("densebox", "canonical", flags=2)
+    bad = _lib.make_options("densebox", "canonical", flags=4)  # no such flag
     assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(bad), ctypes.byref(out)) == _lib.FDB_ERR_INVALID
     for ok in (_lib.make_options("densebox", tile=8), _lib.make_options("densebox", tile=64, graph=True)):
         assert lib.fdb_workspace_bytes(10, 3, ctypes.byref(ok), ctypes.byref(out)) == 0

@@ -424,7 +424,10 @@ def test_isolated_point_test_edges(dev, d):
     assert (ref[0] == -1).sum() > 100 and ref[1].sum() > 1000
     for mp in (3, 5):
         pairs, npairs = _boundary_pairs(rng, d, eps, word, mp, 150)
-        pts = np.concatenate([pairs, scattered, corners]).astype(np.float32)
+        # scattered points kept 3 eps away from the pairs, so none adds a neighbour
+        # to a near point (which would make it core instead of border)
+        gap = np.min(np.linalg.norm(scattered[:, None, :] - pairs[None, :, :], axis=2), axis=1)
+        pts = np.concatenate([pairs, scattered[gap > 3 * eps], corners]).astype(np.float32)
         # a points sit at rows 0, mp + 1, 2 (mp + 1), ... of `pairs`
         a_rows = np.arange(npairs) * (mp + 1)
         ref = assert_exact(dev, pts, eps, mp, "densebox")
