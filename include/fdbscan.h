@@ -53,7 +53,8 @@ typedef enum {
   FDB_ERR_HIP = 3,       /* a HIP runtime call failed */
   FDB_ERR_NONFINITE = 4, /* a coordinate is NaN or infinite (reported when the call waits) */
   FDB_ERR_INTERNAL = 5,  /* a kernel's own consistency check failed (reported when the call waits) */
-  FDB_ERR_BUSY = 6       /* another host thread is inside a call on the same handle */
+  FDB_ERR_BUSY = 6,      /* another host thread is inside a call on the same handle */
+  FDB_ERR_SCRATCH = 7    /* fdb_dbscan_noalloc: the input needs more than FDB_NOALLOC_SCRATCH_BYTES */
 } fdb_status;
 
 typedef enum {
@@ -163,6 +164,32 @@ fdb_status fdb_workspace_bytes(int64_t n, int32_t dim, const fdb_options* opt, s
 fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
                       const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Size of the library's static device scratch that fdb_dbscan_noalloc works in
+   (one copy per GPU the library runs on, held until the process ends). */
+#define FDB_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * fdb_dbscan without any allocation, for callers that cannot allocate device or
+ * host memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Arguments, results and errors are those of fdb_dbscan with
+ * workspace = NULL, except:
+ *   - the workspace is the library's static scratch of FDB_NOALLOC_SCRATCH_BYTES
+ *     on the handle's device (no hipMalloc, no hipFree, no allocating library
+ *     call; the handle was set up by fdb_create). An input whose
+ *     fdb_workspace_bytes exceeds it returns FDB_ERR_SCRATCH before any launch
+ *     (64 MiB holds about 250k 3D points for DenseBox, 450k for FDbscan);
+ *   - opt->flags must not hold FDB_FLAG_GRAPH (recording a graph allocates):
+ *     FDB_ERR_INVALID;
+ *   - stage timing (fdb_set_timing) is not recorded.
+ * Every call on one GPU, from any handle, shares that GPU's scratch, which keeps
+ * the last call's contents (each call clears what it needs): calls that overlap on
+ * one GPU (other streams, other host threads with other handles) race and give
+ * undefined labels. Order them on one stream or serialise them.
+ */
+fdb_status fdb_dbscan_noalloc(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                              const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
+                              hipStream_t stream);
 
 /*
  * Cluster a batch of independent point clouds in one launch sequence (every

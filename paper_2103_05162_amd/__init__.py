@@ -7,15 +7,16 @@ include/fdbscan.h); this package marshals torch tensors into that ABI.
 """
 from __future__ import annotations
 
-from ._lib import (FDB_ERR_BUSY, FDB_FLAG_GRAPH, FDB_FLAG_VALIDATE, FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS,
-                   FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_FOREST, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError, Handle, Server, load,
+from ._lib import (FDB_ERR_BUSY, FDB_ERR_SCRATCH, FDB_FLAG_GRAPH, FDB_FLAG_VALIDATE, FDB_INFO_FOREST,
+                   FDB_NOALLOC_SCRATCH_BYTES, FDB_INFO_AUTO_FDBSCAN, FDB_INFO_BAD_PARAMS,
+                   FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_INTERNAL, FDB_INFO_NONFINITE, FdbError, Handle, Server, load,
                    make_options, options_dict, status_string, workspace_bytes, workspace_bytes_batched)
 
-__all__ = ["dbscan", "dbscan_batched", "dbscan_batched_host", "tune", "tune_batched", "Handle", "Server", "FdbError",
+__all__ = ["dbscan", "dbscan_noalloc", "dbscan_batched", "dbscan_batched_host", "tune", "tune_batched", "Handle", "Server", "FdbError",
            "workspace_bytes", "workspace_bytes_batched", "default_handle", "load", "make_options", "options_dict",
            "status_string", "FDB_INFO_DENSEBOX_FALLBACK", "FDB_INFO_NONFINITE", "FDB_INFO_INTERNAL",
-           "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN", "FDB_FLAG_GRAPH", "FDB_ERR_BUSY",
-           "FDB_FLAG_VALIDATE", "FDB_INFO_FOREST"]
+           "FDB_INFO_BAD_PARAMS", "FDB_INFO_AUTO_FDBSCAN", "FDB_FLAG_GRAPH", "FDB_ERR_BUSY", "FDB_ERR_SCRATCH",
+           "FDB_NOALLOC_SCRATCH_BYTES", "FDB_FLAG_VALIDATE", "FDB_INFO_FOREST"]
 
 _handles: dict[int, Handle] = {}
 
@@ -72,6 +73,29 @@ def dbscan(points, eps: float, min_pts: int, algo: str = "fdbscan", border: str 
     k = h.dbscan_raw(pts.data_ptr() if n else 0, n, d, eps, min_pts, labels.data_ptr() if n else 0,
                      is_core.data_ptr() if n else 0, stream, opt, want_k, ws_ptr, ws_size)
     return labels, is_core.view(torch.bool), k
+
+
+def dbscan_noalloc(points, eps: float, min_pts: int, labels, is_core, algo: str = "fdbscan",
+                   border: str = "canonical", leaf_size: int = 0, block_size: int = 0, tile: int = 0,
+                   handle: Handle | None = None, want_k: bool = True):
+    """fdb_dbscan_noalloc: dbscan() in the library's static scratch, with caller-owned
+    outputs (labels int32 [n], is_core uint8 [n]); nothing is allocated. Returns K
+    (None when want_k is False)."""
+    import torch
+
+    if not isinstance(points, torch.Tensor) or points.device.type != "cuda":
+        raise TypeError("points must be a torch tensor on a HIP device")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] not in (2, 3) \
+            or not points.is_contiguous():
+        raise ValueError("points must be contiguous float32 with shape [n, 2] or [n, 3]")
+    n, d = points.shape
+    _check_out(labels, is_core, n)
+    dev = points.device.index if points.device.index is not None else torch.cuda.current_device()
+    h = handle if handle is not None else default_handle(dev)
+    opt = make_options(algo, border, leaf_size, block_size, tile=tile)
+    stream = torch.cuda.current_stream(points.device).cuda_stream
+    return h.dbscan_noalloc_raw(points.data_ptr() if n else 0, n, d, eps, min_pts, labels.data_ptr() if n else 0,
+                                is_core.data_ptr() if n else 0, stream, opt, want_k)
 
 
 def dbscan_batched(points, offsets, eps, min_pts, algo: str = "fdbscan", border: str = "canonical",

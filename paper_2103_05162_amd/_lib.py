@@ -12,7 +12,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdbscan.so")
 
-FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL, FDB_ERR_BUSY = range(7)
+(FDB_OK, FDB_ERR_INVALID, FDB_ERR_NOMEM, FDB_ERR_HIP, FDB_ERR_NONFINITE, FDB_ERR_INTERNAL, FDB_ERR_BUSY,
+ FDB_ERR_SCRATCH) = range(8)
+FDB_NOALLOC_SCRATCH_BYTES = 64 << 20
 FDB_ALGO_FDBSCAN, FDB_ALGO_DENSEBOX, FDB_ALGO_AUTO = 0, 1, 2
 FDB_BORDER_CANONICAL, FDB_BORDER_FIRST, FDB_BORDER_NONE = 0, 1, 2
 FDB_INFO_DENSEBOX_FALLBACK, FDB_INFO_NONFINITE, FDB_INFO_INTERNAL, FDB_INFO_BAD_PARAMS = 1, 2, 4, 8
@@ -80,6 +82,9 @@ def load() -> ctypes.CDLL:
     lib.fdb_dbscan.argtypes = [vp, vp, i64, i32, ctypes.c_float, i32, ctypes.POINTER(FdbOptions), vp, vp,
                                ctypes.POINTER(i32), vp, sz, vp]
     lib.fdb_dbscan.restype = ctypes.c_int
+    lib.fdb_dbscan_noalloc.argtypes = [vp, vp, i64, i32, ctypes.c_float, i32, ctypes.POINTER(FdbOptions), vp, vp,
+                                       ctypes.POINTER(i32), vp]
+    lib.fdb_dbscan_noalloc.restype = ctypes.c_int
     lib.fdb_workspace_bytes_batched.argtypes = [i64, i32, i32, ctypes.POINTER(FdbOptions), ctypes.POINTER(sz)]
     lib.fdb_workspace_bytes_batched.restype = ctypes.c_int
     lib.fdb_dbscan_batched.argtypes = [vp, vp, i64, vp, i32, i32, vp, vp, ctypes.POINTER(FdbOptions), vp, vp, vp, vp,
@@ -198,6 +203,19 @@ class Handle:
                                   ctypes.c_void_p(workspace_ptr) if workspace_ptr else None, int(workspace_size),
                                   ctypes.c_void_p(stream))
         _check(st, "fdb_dbscan")
+        return int(k.value) if want_k else None
+
+    def dbscan_noalloc_raw(self, points_ptr: int, n: int, dim: int, eps: float, min_pts: int, labels_ptr: int,
+                           core_ptr: int | None, stream: int, options: FdbOptions | None = None,
+                           want_k: bool = True):
+        """fdb_dbscan_noalloc on raw device pointers. Returns K (or None when want_k is False)."""
+        k = ctypes.c_int32(-1)
+        st = self._lib.fdb_dbscan_noalloc(self.ptr, ctypes.c_void_p(points_ptr), int(n), int(dim),
+                                          ctypes.c_float(eps), int(min_pts),
+                                          ctypes.byref(options) if options is not None else None,
+                                          ctypes.c_void_p(labels_ptr), ctypes.c_void_p(core_ptr) if core_ptr else None,
+                                          ctypes.byref(k) if want_k else None, ctypes.c_void_p(stream))
+        _check(st, "fdb_dbscan_noalloc")
         return int(k.value) if want_k else None
 
     def dbscan_batched_raw(self, points_ptr: int, n_total: int, offsets_ptr: int, num_clouds: int, dim: int,

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -150,11 +151,37 @@ struct fdb_handle {
   hipStream_t cap_stream = nullptr;     // stream that graph recordings are captured on
   std::vector<fdb::GraphRec> graphs;    // recorded launch sequences, most recent last
   std::vector<fdb::TuneEntry> tune;     // launch shapes chosen by fdb_tune (and the tune cache file)
+  void* scratch = nullptr;              // this device's copy of the library's static scratch (device address)
 };
+
+// Workspace of fdb_dbscan_noalloc: device memory of the library itself, one copy
+// per GPU that the library runs on, held until the process ends. In host code this
+// name is a host-side stand-in, never a device address: fdb_create looks up the
+// current device's copy with hipGetSymbolAddress (once per device) and every
+// launch takes that pointer, as it takes a caller's workspace.
+static __device__ __align__(256) unsigned char scratch[FDB_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
 using fdb::ceil_div;
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// The device address of `scratch` on `device` (the current device), looked up on
+// the first request for that device.
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device >= 0 && device < kScratchDevices && g_scratch_ptr[device]) return g_scratch_ptr[device];
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (device >= 0 && device < kScratchDevices) g_scratch_ptr[device] = p;
+  return p;
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -418,7 +445,7 @@ fdb_status dbscan_batched_entry(fdb_handle* h, const float* points, int64_t n_to
 void load_tune_file(fdb_handle* h);
 fdb_status dbscan_entry(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
                         const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
-                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+                        void* workspace, size_t workspace_bytes, hipStream_t stream, bool may_time = true);
 
 template <typename T>
 T* at(void* base, size_t off) {
@@ -438,6 +465,8 @@ const char* fdb_status_string(fdb_status s) {
     case FDB_ERR_NONFINITE: return "non-finite coordinate";
     case FDB_ERR_INTERNAL: return "internal consistency check failed";
     case FDB_ERR_BUSY: return "another thread is inside a call on this handle";
+    case FDB_ERR_SCRATCH:
+      return "input needs more workspace than the library's static scratch (FDB_NOALLOC_SCRATCH_BYTES)";
   }
   return "unknown status";
 }
@@ -461,6 +490,7 @@ fdb_status fdb_create(fdb_handle** out, int device) {
     delete h;
     return FDB_ERR_NOMEM;
   }
+  h->scratch = scratch_address(device);  // nullptr: fdb_dbscan_noalloc reports FDB_ERR_HIP
   load_tune_file(h);
   *out = h;
   return FDB_OK;
@@ -636,13 +666,29 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
                       workspace_bytes, stream);
 }
 
+fdb_status fdb_dbscan_noalloc(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
+                              const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
+                              hipStream_t stream) {
+  if (!h) return FDB_ERR_INVALID;
+  fdb_options o{};
+  if (opt) o = *opt;
+  if (!valid_options(o) || (o.flags & FDB_FLAG_GRAPH)) return FDB_ERR_INVALID;  // instantiating a graph allocates
+  if ((dim != 2 && dim != 3) || n < 0 || n > fdb::kMaxPoints) return FDB_ERR_INVALID;
+  if (fdb::make_plan(n, dim, o.algo).bytes > FDB_NOALLOC_SCRATCH_BYTES) return FDB_ERR_SCRATCH;
+  if (!h->scratch) return FDB_ERR_HIP;
+  CallGuard busy(h);
+  if (!busy.ok) return FDB_ERR_BUSY;
+  return dbscan_entry(h, points, n, dim, eps, min_pts, &o, labels, is_core, h_num_clusters, h->scratch,
+                      FDB_NOALLOC_SCRATCH_BYTES, stream, false);
+}
+
 }  // extern "C"
 
 namespace {
 
 fdb_status dbscan_entry(fdb_handle* h, const float* points, int64_t n, int32_t dim, float eps, int32_t min_pts,
                         const fdb_options* opt, int32_t* labels, uint8_t* is_core, int32_t* h_num_clusters,
-                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+                        void* workspace, size_t workspace_bytes, hipStream_t stream, bool may_time) {
   using namespace fdb;
   fdb_options o{};
   if (opt) o = *opt;
@@ -672,7 +718,7 @@ fdb_status dbscan_entry(fdb_handle* h, const float* points, int64_t n, int32_t d
     h->last_densebox = o.algo != FDB_ALGO_FDBSCAN;
     h->last_n = n;
   } else {
-    st = dbscan_launch(h, args, o, plan, ws, stream, h->timing);
+    st = dbscan_launch(h, args, o, plan, ws, stream, h->timing && may_time);
   }
   if (st != FDB_OK) return st;
   if (h_num_clusters) {
