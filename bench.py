@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--ooc-budget-gib", type=float, default=6.0,
                     help="device budget of the out-of-core batched leg (0 = skip it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="first run one device-to-device copy of this many MiB (PMC calibration)")
+                    help="first run kernels of known traffic on this many MiB (PMC calibration): a "
+                         "device-to-device copy, and gathers of 12-byte rows by identity and random index")
     return ap.parse_args()
 
 
@@ -561,13 +562,22 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.copy_calibration_mib:
+        # kernels of known traffic for reading HBM counters: a streaming copy, then a
+        # gather of 12-byte rows (the shape of the gather to key order) through an
+        # identity index and through a random permutation of the same size
         nel = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
+        rows = src[: nel // 3 * 3].view(-1, 3)
+        ident = torch.arange(rows.shape[0], device=dev)
+        perm = torch.randperm(rows.shape[0], device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+        torch.index_select(rows, 0, ident)
+        torch.index_select(rows, 0, perm)
         torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
-        del src, dst
+        log(f"[bench] calibration kernels done: copy of {args.copy_calibration_mib} MiB, gathers of "
+            f"{rows.shape[0]} 12-byte rows by identity and by a random permutation")
+        del src, dst, rows, ident, perm
     h = fdb.Handle(0)
     algos = ["densebox", "fdbscan"] if args.algo == "both" else [args.algo]
     head = algos[0]

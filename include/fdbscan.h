@@ -305,15 +305,18 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
  * Served clustering: a stream of independent jobs (each one cloud with its own
  * eps and minPts, as in fdb_dbscan) on one device. The method itself is the
  * per-cloud clustering of Sections 4.1-4.2; serving many clouds at once is not
- * in the paper. A server owns one worker thread, one stream, and one device
- * arena of hbm_budget_bytes allocated at creation; jobs never allocate.
- *   FDB_SERVE_BATCHED  continuous batching: whenever the device is free, the
- *                      worker takes the waiting jobs of the oldest job's dim, in
- *                      arrival order, while the batch (its fdb_dbscan_batched
- *                      workspace plus gathered points, labels, flags and
- *                      per-job arrays) fits in the budget and holds at most
- *                      max_batch jobs, and runs them as one batched launch
- *                      sequence; a job arriving meanwhile joins the next batch.
+ * in the paper. A server owns one worker thread and one device arena of
+ * hbm_budget_bytes allocated at creation; jobs never allocate.
+ *   FDB_SERVE_BATCHED  continuous batching over two slots, each half the arena
+ *                      with its own stream: whenever a slot is free, the worker
+ *                      takes the waiting jobs of the oldest job's dim, in arrival
+ *                      order, while the batch (its fdb_dbscan_batched workspace
+ *                      plus gathered points, labels, flags and per-job arrays)
+ *                      fits in the slot and holds at most max_batch jobs, and
+ *                      launches them as one batched launch sequence without
+ *                      waiting; jobs arriving while it runs go to the other slot,
+ *                      so two batches overlap on the device. A job must fit in
+ *                      one slot (half the budget).
  *   FDB_SERVE_FIFO     one job at a time with fdb_dbscan, in arrival order (the
  *                      plain server; the arena is its workspace).
  * A job's labels, is_core and K equal what fdb_dbscan gives for it alone
@@ -362,7 +365,8 @@ fdb_status fdb_server_create(int device, size_t hbm_budget_bytes, int32_t max_ba
 /* Queue a job (thread-safe, never waits for the device). The job's points must
    be ready on the device (the caller's stream synchronised) before this call.
    FDB_ERR_INVALID for bad arguments, FDB_ERR_NOMEM if the job alone does not fit
-   in the budget. *h_ticket identifies the job (0, 1, 2, ... in submission order). */
+   in a slot (batched mode: half the budget; FIFO: the budget). *h_ticket identifies
+   the job (0, 1, 2, ... in submission order). */
 fdb_status fdb_server_submit(fdb_server* s, const fdb_job* job, int64_t* h_ticket);
 /* State of a job without waiting, or waiting until it is done (h_out may be NULL). */
 fdb_status fdb_server_poll(fdb_server* s, int64_t ticket, fdb_job_result* h_out);

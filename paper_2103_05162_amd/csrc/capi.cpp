@@ -92,6 +92,9 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
     p.prim_hi = take(N * 16);
     p.prim_key = take(N * 8);
     p.dense_list = take(N * 4);
+    // the cell boxes are dead once the primitives are written: the isolated-point
+    // test keeps its occupancy words there
+    p.map_bytes = static_cast<int64_t>(p.cell_hi + N * 16 - p.cell_lo);
   }
   p.cl_lo = p.cl_scale = p.cl_eps2 = p.cl_minpts = p.cl_root = p.cl_end = p.cl_flags = p.cl_ord = 0;
   if (num_clouds > 0) {
@@ -769,14 +772,27 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
   h->last_misc = misc;
   h->last_densebox = false;
   h->last_n = n;
-  fill_u32(h->d_info, 0, 2, s);  // info bits and the forest check's count
-  fill_u32(bounds, 0xffffffffu, 4, s);
-  fill_u32(bounds + 4, 0u, 4, s);
+  {
+    // the call's counters and flags in one launch: info bits and the forest check's
+    // count, the bounds' identities, the misc counters, and for DenseBox the digit
+    // histograms, tile counters and look-back words of the planned sort
+    FillList init;
+    init.add(h->d_info, 0u, 2);
+    init.add(bounds, 0xffffffffu, 4);
+    init.add(bounds + 4, 0u, 4);
+    init.add(misc, 0u, kMiscCount);
+    if (densebox) {
+      init.add(at<uint32_t>(ws, plan.hist), 0u, 8 * 256);
+      init.add(at<uint32_t>(ws, plan.tilectr), 0u, 8);
+      init.add(at<uint32_t>(ws, plan.status), 0u, planned_status_words(n));
+    }
+    fill_multi(init, s);
+  }
   launch_bounds(points, n, dim, bounds, h->d_info, s);
 
   // DenseBox sizes its grid on the device (k_grid_plan): nothing waits for the GPU
   GridPlan* gplan = at<GridPlan>(ws, plan.gplan);
-  if (densebox) launch_grid_plan(bounds, dim, eps, n, gplan, h->d_info, s);
+  if (densebox) launch_grid_plan(bounds, dim, eps, n, plan.map_bytes, gplan, h->d_info, s);
 
   int cur = 0;
   const uint32_t* perm = nullptr;
@@ -801,17 +817,17 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
 
   if (densebox) {
     st.mark("cell_keys");
-    launch_gridkeys(points, n, dim, bounds, gplan, keys[0], keys[1], vals[0], vals[1], at<uint32_t>(ws, plan.hist), s);
+    launch_gridkeys(points, n, dim, bounds, gplan, keys[0], keys[1], vals[0], vals[1], at<uint32_t>(ws, plan.hist), s,
+                    false);
     st.mark("sort");
     radix_sort_planned(keys[0], keys[1], vals[0], vals[1], n, gplan, at<uint32_t>(ws, plan.hist),
                        at<uint32_t>(ws, plan.digoff), at<uint32_t>(ws, plan.tilectr), at<uint64_t>(ws, plan.status),
-                       h->d_info, s);
+                       h->d_info, s, false);
     cur = 1;  // the planned sort ends in buffer 1
     perm = vals[cur];
     st.mark("permute");
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
     st.mark("dense_cells");
-    fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
     densebox_cells(keys[cur], false, &gplan->key64, n, dim, xs, eps2, min_pts, at<int>(ws, plan.cell_id),
                    at<int>(ws, plan.cell_start), at<int>(ws, plan.cand), at<uint8_t>(ws, plan.cell_dense),
                    at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
@@ -836,7 +852,6 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     ta.d_ndense = misc + kMiscNumDense;
   } else {
     st.mark("morton");
-    fill_u32(reinterpret_cast<uint32_t*>(misc), 0, kMiscCount, s);
     const int mbits = dim == 3 ? 63 : 62;
     launch_morton(points, n, dim, bounds, static_cast<uint64_t*>(keys[0]), vals[0], mbits,
                   at<uint32_t>(ws, plan.hist), s);
@@ -865,17 +880,17 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
   ta.brec_n = misc + kMiscBorderRec;
   ta.brec_cap = static_cast<int>(plan.brec_cap);
   if (!all_core) {
-    fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
-    // isolated points first, when the plan says the lone-cell bitmap fits the (now
-    // free) pflag buffer; otherwise these kernels leave at once and the core pass
-    // walks every primitive
+    // (the border counters are misc slots, cleared at the start of the call)
+    // isolated points first, when the plan says the occupancy map fits the (now
+    // free) cell-box buffers and its brick table the pflag buffer; otherwise these
+    // kernels leave at once and the core pass walks every primitive
     if (densebox) {
       st.mark("isolated");
       ta.core_list = at<int>(ws, plan.cid);  // cid is free until the canonical ids
       ta.core_qn = misc + kMiscCoreQ;
       ta.lone_on = &gplan->lone_on;
-      launch_lone_filter(ta, dim, at<uint64_t>(ws, plan.prim_key), gplan, at<uint64_t>(ws, plan.pflag),
-                         at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
+      launch_lone_filter(ta, dim, at<uint64_t>(ws, plan.prim_key), gplan, at<uint32_t>(ws, plan.pflag),
+                         at<uint64_t>(ws, plan.cell_lo), bounds, at<int>(ws, plan.cid), misc + kMiscCoreQ, s);
     }
     st.mark("core");
     launch_core(ta, dim, densebox, s);
@@ -909,6 +924,12 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
 }
 
 }  // namespace
+
+namespace fdb {
+
+const uint32_t* handle_info(const fdb_handle* h) { return h->d_info; }
+
+}  // namespace fdb
 
 extern "C" {
 
@@ -1105,7 +1126,6 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
   ta.brec_nb = at<int>(ws, plan.brec_nb);
   ta.brec_n = misc + kMiscBorderRec;
   ta.brec_cap = static_cast<int>(plan.brec_cap);
-  fill_u32(reinterpret_cast<uint32_t*>(misc + kMiscBorderQ), 0, 2, s);
   launch_core(ta, dim, densebox, s);
   if (densebox) {
     st.mark("main_cells");

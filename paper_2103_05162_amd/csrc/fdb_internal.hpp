@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+struct fdb_handle;
+
 namespace fdb {
 
 // Keys per thread in a radix pass, by key width (measured: 64-bit keys fit two
@@ -43,6 +45,7 @@ struct Plan {
   int num_clouds = 0;
   size_t cl_lo, cl_scale, cl_eps2, cl_minpts, cl_root, cl_end, cl_flags, cl_ord;
   int64_t sort_tiles = 0, scan_blocks = 0;
+  int64_t map_bytes = 0;  // DenseBox: bytes from cell_lo to the end of cell_hi (free after the primitives)
 };
 
 Plan make_plan(int64_t n, int dim, int algo, int num_clouds = 0);
@@ -75,9 +78,10 @@ struct GridPlan {
   int32_t key64;       // 1: d * bits > 32, keys are stored as 64-bit words, else 32-bit
   int32_t passes;      // 8-bit radix passes over the d * bits key bits
   int32_t start;       // key buffer (0/1) the key kernel fills: the sort then ends in buffer 1
-  int32_t lone_on;     // the isolated-point test runs (32-bit keys, bitmap fits its buffer)
+  int32_t lone_on;     // the isolated-point test runs (32-bit keys, its map and table fit their buffers)
   int32_t coarse;      // cells widened to fit 64-bit keys
-  int64_t lone_words;  // 64-bit occupancy words of the isolated-point test
+  int64_t lone_words;  // the test's 64-bit occupancy words, one per brick of 64 grid cells
+  float reach;         // eps / side plus rounding slack, in cell units (< 2)
 };
 
 // Node records are interleaved: node k's two halves sit at node_a[kNodeStride * k]
@@ -103,6 +107,20 @@ struct TreeView {
 // ---- launch helpers (stream-ordered, asynchronous) --------------------------
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+// Up to 8 fills of 32-bit words in one launch (a call's counters and flags).
+struct FillSeg {
+  uint32_t* p;
+  uint32_t v;
+  int64_t n;
+};
+struct FillList {
+  FillSeg seg[8];
+  int count = 0;
+  void add(void* p, uint32_t v, int64_t n) {
+    if (n > 0) seg[count++] = FillSeg{static_cast<uint32_t*>(p), v, n};
+  }
+};
+void fill_multi(const FillList& L, hipStream_t s);
 
 // k_prep.hip
 void launch_bounds(const float* pts, int64_t n, int dim, uint32_t* bounds, uint32_t* info, hipStream_t s);
@@ -113,11 +131,13 @@ void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds,
 // DenseBox of one cloud: k_grid_plan writes *plan from the bounds (after
 // launch_bounds; eps is the caller's), then the cell keys go to key buffer
 // plan->start as 32- or 64-bit words with the identity permutation, and their
-// digits are counted for the sort (hist: 8 x 256 words, cleared here).
-void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, GridPlan* plan, uint32_t* info,
-                      hipStream_t s);
+// digits are counted for the sort (hist: 8 x 256 words, cleared here unless the
+// caller has, hist_clear = false).
+void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, int64_t map_bytes, GridPlan* plan,
+                      uint32_t* info, hipStream_t s);
 void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const GridPlan* plan,
-                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s);
+                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s,
+                     bool hist_clear = true);
 void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, float* xs, uint32_t* info,
                     hipStream_t s);
 
@@ -130,10 +150,13 @@ int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64
 // The same with key width and pass count taken from a GridPlan on the device:
 // passes for both widths are launched and those the plan does not call for exit
 // at once. The keys start in buffer plan->start and end in buffer 1; hist holds
-// every pass's digit counts (from the key kernel).
+// every pass's digit counts (from the key kernel). The tile counters (8 words)
+// and look-back words (planned_status_words(n)) are cleared here unless the
+// caller has (clear = false).
 void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, const GridPlan* plan,
                         const uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
-                        uint32_t* info, hipStream_t s);
+                        uint32_t* info, hipStream_t s, bool clear = true);
+int64_t planned_status_words(int64_t n);
 
 // k_tree.hip
 // prim_lo / prim_hi: DenseBox leaf records (null for FDbscan, whose leaves are
@@ -214,15 +237,15 @@ struct TravArgs {
   int block;
 };
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
-// Isolated points before the DenseBox core pass (one cloud, 32-bit grid keys):
-// a bitmap over "lone cells" (2^d blocks of grid cells) marks the cells holding a
-// primitive; a point primitive alone in its lone cell, whose 3^d - 1 neighbours
-// are empty, has no neighbour but itself and is finished here (core 0, lone,
-// border -1); the others are listed (list, list_n[kNumXcd]) for the core pass.
-// Runs only where plan->lone_on: bits then holds plan->lone_words =
-// 2^(d (b - 1)) / 64 (at least 1) 64-bit words for keys of b bits per axis.
-void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint64_t* bits,
-                        int* list, int* list_n, hipStream_t s);
+// Isolated points before the DenseBox core pass (one cloud, 32-bit grid keys): an
+// occupancy map of the grid cells (words: plan->lone_words 64-bit words, one per
+// brick of 64 cells, written only for occupied bricks; table: one bit per brick,
+// cleared here) settles every point primitive with no occupied cell within reach
+// but its own, which it shares with no other primitive: core 0, lone, border -1.
+// The others are listed (list, list_n[kNumXcd]) for the core pass. Runs only where
+// plan->lone_on; bounds are the scene bounds of launch_bounds.
+void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint32_t* table,
+                        uint64_t* words, const uint32_t* bounds, int* list, int* list_n, hipStream_t s);
 void launch_main(const TravArgs& a, int dim, bool densebox, bool all_core, bool first_border, int part,
                  hipStream_t s);
 void launch_border(const TravArgs& a, int dim, bool densebox, hipStream_t s);
@@ -258,6 +281,12 @@ void batch_cluster_ids(const int* labels, const uint8_t* core, const int* minori
 void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm, const int* cid,
                     const int* border, bool first_border, bool have_border, int64_t n, int32_t* out_labels,
                     uint8_t* out_core, uint32_t* info, hipStream_t s);
+// The device word of FDB_INFO_* bits that a handle's calls raise (for copies
+// ordered on a stream; the server reads its batches' bits this way).
+const uint32_t* handle_info(const fdb_handle* h);
+
+// Exclusive scan of blocks int32 counts in place (one workgroup); the total goes to *d_total.
+void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s);
 void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums, int64_t blocks, int* d_total,
                  hipStream_t s);
 

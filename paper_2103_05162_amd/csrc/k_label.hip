@@ -322,6 +322,10 @@ void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums,
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, in, out, n, d_n, bsums);
 }
 
+void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsums, blocks, d_total);
+}
+
 void launch_init_labels(int* labels, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n);
 }

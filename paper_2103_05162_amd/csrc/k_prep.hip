@@ -111,12 +111,12 @@ __global__ __launch_bounds__(kBlock) void k_bounds_v4(const float* __restrict__ 
     }
   };
   int64_t c = c0;
-  for (; c + 3 * T < nch; c += 4 * T) {
-    const float4 a = p4[c], b = p4[c + T], d = p4[c + 2 * T], f = p4[c + 3 * T];
-    take(a);
-    take(b);
-    take(d);
-    take(f);
+  for (; c + 7 * T < nch; c += 8 * T) {  // eight 16-byte loads in flight per lane
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p4[c + u * T];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) take(v[u]);
   }
   for (; c < nch; c += T) take(p4[c]);
   float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -211,11 +211,12 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float* __restrict__ pts
 // side is shrunk by 2^-20 so that rounding in the cell index rarely pushes a
 // cell's extent past h (the exactness guard catches the rest). A grid wider than
 // a 64-bit key holds gets wider cells (every pair in a dense cell still passes the
-// guard). The isolated-point test runs for 32-bit keys when its bitmap (one bit
-// per 2^d block of cells, 64-bit words) fits in n 32-bit words.
+// guard). The isolated-point test runs for 32-bit keys when its occupancy map (one
+// bit per cell, a 64-bit word per brick of 64 cells) fits in map_bytes and its
+// brick table (a bit per brick) in n 32-bit words.
 template <int D>
-__global__ void k_grid_plan(const uint32_t* __restrict__ bounds, float eps, int64_t n, GridPlan* __restrict__ plan,
-                            uint32_t* __restrict__ info) {
+__global__ void k_grid_plan(const uint32_t* __restrict__ bounds, float eps, int64_t n, int64_t map_bytes,
+                            GridPlan* __restrict__ plan, uint32_t* __restrict__ info) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   constexpr int maxbits = D == 3 ? 21 : 31;
   const double side0 = static_cast<double>(eps) / sqrt(static_cast<double>(D)) * (1.0 - 1.0 / 1048576.0);
@@ -253,12 +254,24 @@ __global__ void k_grid_plan(const uint32_t* __restrict__ bounds, float eps, int6
   g.passes = (D * bits + 7) / 8;
   g.start = (g.passes & 1) ? 0 : 1;
   g.coarse = coarse;
-  const int lone_shift = D * (bits - 1);
-  g.lone_words = lone_shift <= 6 ? 1 : (int64_t(1) << (lone_shift - 6));
-  g.lone_on = (!g.key64 && bits >= 1 && 2 * g.lone_words <= n) ? 1 : 0;
+  // isolated-point test: a word per brick of 64 grid cells (in map_bytes) and a
+  // table bit per brick (in an n-int buffer); reach = eps / side in cell units plus
+  // a slack for the rounding of the cell coordinates t = (x - lo) * inv_h: each is
+  // within 2^-23 t of exact, so a difference within cmax 2^-22 (times 4 here), and
+  // the fp32 test passes pairs up to eps (1 + 2^-22) apart (2^-16 here)
+  double cmax = 1.0;
+  for (int k = 0; k < D; ++k) cmax = g.ncell[k] > cmax ? g.ncell[k] : cmax;
+  const double reach = static_cast<double>(eps) * static_cast<double>(ih) * (1.0 + 1.0 / 65536.0) +
+                       4.0 * (cmax / 4194304.0 + 1.0 / 1048576.0) + 1.0 / 65536.0;
+  g.lone_words = D * bits >= 6 ? int64_t(1) << (D * bits - 6) : 1;
+  g.reach = static_cast<float>(reach);
+  g.lone_on = (!g.key64 && bits >= 1 && reach < 1.999 && g.lone_words * 8 <= map_bytes &&
+               (g.lone_words + 63) / 64 * 2 <= n) ? 1 : 0;
   *plan = g;
   if (coarse) atomicOr(info, FDB_INFO_DENSEBOX_FALLBACK);
 }
+
+constexpr int kGridKeyItems = 4;
 
 // DenseBox cell keys: cell c_k = floor((x_k - lo_k) / h), clamped to the grid; the
 // key is the Morton interleave of the cell coordinates, so equal keys are one cell
@@ -279,21 +292,37 @@ __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ p
   float lo[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) lo[k] = ord2f(bounds[k]);
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    uint32_t c[D];
+  // kGridKeyItems points per thread and trip, their loads issued together
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i0 < n; i0 += kGridKeyItems * stride) {
+    float x[kGridKeyItems][D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) c[k] = quantize(pts[i * D + k], lo[k], g.inv_h[k], g.ncell[k] - 1);
-    uint64_t code;
-    if constexpr (D == 3)
-      code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
-    else
-      code = (spread2(c[0]) << 1) | spread2(c[1]);
-    if (g.key64)
-      static_cast<uint64_t*>(keys)[i] = code;
-    else
-      static_cast<uint32_t*>(keys)[i] = static_cast<uint32_t>(code);
-    vals[i] = static_cast<uint32_t>(i);
-    hist_add(code, true, passes, s_h);
+    for (int t = 0; t < kGridKeyItems; ++t) {
+      const int64_t i = i0 + t * stride;
+#pragma unroll
+      for (int k = 0; k < D; ++k) x[t][k] = i < n ? pts[i * D + k] : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < kGridKeyItems; ++t) {
+      const int64_t i = i0 + t * stride;
+      const bool valid = i < n;
+      uint32_t c[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) c[k] = quantize(x[t][k], lo[k], g.inv_h[k], g.ncell[k] - 1);
+      uint64_t code;
+      if constexpr (D == 3)
+        code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+      else
+        code = (spread2(c[0]) << 1) | spread2(c[1]);
+      if (valid) {
+        if (g.key64)
+          static_cast<uint64_t*>(keys)[i] = code;
+        else
+          static_cast<uint32_t*>(keys)[i] = static_cast<uint32_t>(code);
+        vals[i] = static_cast<uint32_t>(i);
+      }
+      hist_add(code, valid, passes, s_h);
+    }
   }
   hist_flush(s_h, passes, hist);
 }
@@ -338,6 +367,25 @@ __global__ __launch_bounds__(kBlock) void k_permute(const float* __restrict__ pt
 
 }  // namespace
 
+// Several fills in one launch: element t of the concatenated segments.
+__global__ void k_fill_multi(FillList L) {
+  int64_t total = 0;
+  for (int k = 0; k < L.count; ++k) total += L.seg[k].n;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    int64_t r = t;
+    int k = 0;
+    while (r >= L.seg[k].n) r -= L.seg[k++].n;
+    L.seg[k].p[r] = L.seg[k].v;
+  }
+}
+
+void fill_multi(const FillList& L, hipStream_t s) {
+  int64_t total = 0;
+  for (int k = 0; k < L.count; ++k) total += L.seg[k].n;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_fill_multi, dim3(grid_for(total, kBlock * 4)), dim3(kBlock), 0, s, L);
+}
+
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, p, v, n);
@@ -378,17 +426,18 @@ void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds,
     hipLaunchKernelGGL(k_morton<2>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals, passes, hist);
 }
 
-void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, GridPlan* plan, uint32_t* info,
-                      hipStream_t s) {
+void launch_grid_plan(const uint32_t* bounds, int dim, float eps, int64_t n, int64_t map_bytes, GridPlan* plan,
+                      uint32_t* info, hipStream_t s) {
   if (dim == 3)
-    hipLaunchKernelGGL(k_grid_plan<3>, dim3(1), dim3(64), 0, s, bounds, eps, n, plan, info);
+    hipLaunchKernelGGL(k_grid_plan<3>, dim3(1), dim3(64), 0, s, bounds, eps, n, map_bytes, plan, info);
   else
-    hipLaunchKernelGGL(k_grid_plan<2>, dim3(1), dim3(64), 0, s, bounds, eps, n, plan, info);
+    hipLaunchKernelGGL(k_grid_plan<2>, dim3(1), dim3(64), 0, s, bounds, eps, n, map_bytes, plan, info);
 }
 
 void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bounds, const GridPlan* plan,
-                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s) {
-  fill_u32(hist, 0, 8 * 256, s);
+                     void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s,
+                     bool hist_clear) {
+  if (hist_clear) fill_u32(hist, 0, 8 * 256, s);
   int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
   if (dim == 3)
     hipLaunchKernelGGL(k_gridkeys<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, plan, keys0, keys1, vals0, vals1,

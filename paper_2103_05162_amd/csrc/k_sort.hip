@@ -257,14 +257,18 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
 
 }  // namespace
 
+int64_t planned_status_words(int64_t n) { return ceil_div(n, 256 * sort_items<uint32_t>()) * kRadix * 2; }
+
 void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, const GridPlan* plan,
                         const uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
-                        uint32_t* info, hipStream_t s) {
+                        uint32_t* info, hipStream_t s, bool clear) {
   if (n <= 1) return;  // the key kernel's start buffer already is buffer 1 when there is nothing to sort
   const int64_t tiles32 = ceil_div(n, 256 * sort_items<uint32_t>());
   const int64_t tiles64 = ceil_div(n, 256 * sort_items<uint64_t>());
-  fill_u32(tilectr, 0, 8, s);
-  fill_u32(reinterpret_cast<uint32_t*>(status), 0, tiles32 * kRadix * 2, s);
+  if (clear) {
+    fill_u32(tilectr, 0, 8, s);
+    fill_u32(reinterpret_cast<uint32_t*>(status), 0, planned_status_words(n), s);
+  }
   hipLaunchKernelGGL(k_digit_offsets, dim3(8), dim3(kRadix), 0, s, hist, digoff);
   for (int p = 0; p < 4; ++p)  // 32-bit keys: at most 4 passes
     hipLaunchKernelGGL(k_onesweep<uint32_t>, dim3(static_cast<unsigned>(tiles32)), dim3(kBlock), 0, s,

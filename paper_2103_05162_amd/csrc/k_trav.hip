@@ -750,12 +750,15 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
       cc = (ALL_CORE || a.core[j]) ? 1 : 0;
       cl = ancestor_of(labels, j);
     }
-    for (int k = 0; k < cnt; ++k) {
+    // candidates that need a test, decided by each candidate's own lane: outside the
+    // packet (its pairs are phase A's; j > i0 by the mask), core, and not already in
+    // the packet's set (r may grow during the bucket; a candidate skipped for the
+    // old r is in the new r's set too, sets only merge)
+    const bool need = lane < cnt && s0 + lane > p1 && cc && !(common && cl == r);
+    for (uint64_t km = ballot(need); km; km &= km - 1) {
+      const int k = __ffsll(static_cast<unsigned long long>(km)) - 1;
       const int j = s0 + k;
-      if (j <= p1) continue;  // inside the packet: phase A (and j > i0 by the mask)
-      if (!__builtin_amdgcn_readlane(cc, k)) continue;
       const int lj = __builtin_amdgcn_readlane(cl, k);
-      if (common && lj == r) continue;
       const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
       if (common) {
         bool h = false;
@@ -1030,28 +1033,13 @@ __device__ __forceinline__ int walk_step(Walk& w, const TreeView& t, int m, cons
 }
 
 // ---- isolated points (one cloud, DenseBox, 32-bit grid keys) --------------------
-// A lone cell is a 2^d block of grid cells, side 2 eps/sqrt(d) >= 1.15 eps. Two
-// points within eps (the fp32 predicate and the cell-index rounding included)
-// have grid coordinates at most 1.77 cells apart per axis, so lone-cell
-// coordinates at most 1 apart: every neighbour of a point lies in the 3^d lone
-// cells around its own. A lone cell's Morton code is the grid key without its
-// lowest d bits, so primitives, in key order, visit lone cells in code order.
-//
-// Occupancy is kept as one 64-bit word per brick of lone cells (4x4x4 in 3D, 8x8
-// in 2D). Bricks follow the Morton order, so a brick's index is the lone code
-// without its lowest 6 bits; inside a brick, local cell (x, y, z) is bit
-// x*16 + y*4 + z (3D) or x*8 + y (2D), which makes the part of a 3^d
-// neighbourhood inside one brick a product of per-axis bit ranges. A
-// neighbourhood touches at most 2^d bricks: at most 2^d loads per query.
-struct LoneGeom {
-  uint32_t nl[3];  // lone cells per axis
-};
-
-template <int D>
-__device__ __forceinline__ uint32_t lone_code(uint32_t key) {
-  return key >> D;
-}
-
+// Before the core walks, a point primitive that has no neighbour but itself is
+// settled by an occupancy map of the grid cells (side eps/sqrt(d)): one bit per
+// cell, in 64-bit words per brick of 4x4x4 cells (3D) or 8x8 (2D). Bricks follow
+// the Morton order, so a brick is the grid key without its lowest 6 bits; inside
+// a brick, local cell (x, y, z) is bit x*16 + y*4 + z (3D) or x*8 + y (2D). A word
+// is written only for an occupied brick, which a table of one bit per brick marks
+// (the table is cleared each call, the words never are).
 template <int D>
 constexpr int kBrickShift = D == 3 ? 2 : 3;  // local coordinate bits per axis
 
@@ -1095,7 +1083,7 @@ __device__ __forceinline__ uint32_t key32(const uint64_t* __restrict__ pkey, int
 // does not run).
 __global__ __launch_bounds__(256) void k_lone_clear(const GridPlan* __restrict__ plan, uint64_t* __restrict__ bits) {
   if (!plan->lone_on) return;
-  const int64_t words = plan->lone_words;
+  const int64_t words = (plan->lone_words + 63) / 64;  // the brick table, 64 brick bits per word
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < words; i += int64_t(gridDim.x) * blockDim.x)
     bits[i] = 0ull;
 }
@@ -1103,7 +1091,7 @@ __global__ __launch_bounds__(256) void k_lone_clear(const GridPlan* __restrict__
 template <int D>
 __global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ pkey, const int* __restrict__ d_m,
                                                    const GridPlan* __restrict__ plan, uint64_t* __restrict__ bits,
-                                                   int* __restrict__ list_n) {
+                                                   uint32_t* __restrict__ table, int* __restrict__ list_n) {
   if (!plan->lone_on) return;
   if (blockIdx.x == 0 && threadIdx.x < kNumXcd) list_n[threadIdx.x] = 0;
   const int m = *d_m;
@@ -1113,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ 
   for (int64_t p0 = (blockIdx.x * int64_t(blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; p0 < m; p0 += waves * 64) {
     const int64_t p = p0 + lane;
     const bool valid = p < m;
-    const uint32_t code = valid ? lone_code<D>(key32(pkey, p)) : 0xffffffffu;
+    const uint32_t code = valid ? key32(pkey, p) : 0xffffffffu;
     const uint32_t word = code >> 6;  // invalid lanes: above every valid brick
     const uint32_t prevw = static_cast<uint32_t>(__shfl_up(static_cast<int>(word), 1));
     const uint32_t nextw = static_cast<uint32_t>(__shfl_down(static_cast<int>(word), 1));
@@ -1133,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ 
     const uint32_t w0 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 0));
     // the wavefront's first run may continue a brick begun by the previous
     // wavefront, which then writes it
-    const bool continued = p0 > 0 && (lone_code<D>(key32(pkey, p0 - 1)) >> 6) == w0;
+    const bool continued = p0 > 0 && (key32(pkey, p0 - 1) >> 6) == w0;
     const bool in_first_run = __popcll(ballot(head) & (lanemask_lt() | (1ull << lane))) == 1;
     const uint32_t w63 = static_cast<uint32_t>(__shfl(static_cast<int>(word), 63));
     uint64_t extra = 0;
@@ -1142,7 +1130,7 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ 
     if (p0 + 64 < m && !(continued && w63 == w0)) {
       for (int64_t b = p0 + 64; b < m; b += 64) {
         const int64_t q = b + lane;
-        const uint32_t c2 = q < m ? lone_code<D>(key32(pkey, q)) : 0xffffffffu;
+        const uint32_t c2 = q < m ? key32(pkey, q) : 0xffffffffu;
         const bool in = q < m && (c2 >> 6) == w63;
         uint64_t x = in ? (1ull << brick_bit<D>(c2)) : 0ull;
 #pragma unroll
@@ -1152,7 +1140,21 @@ __global__ __launch_bounds__(256) void k_lone_bits(const uint64_t* __restrict__ 
       }
     }
     const bool tail = valid && (lane == 63 || nextw != word);
-    if (tail && !(continued && in_first_run)) bits[word] = v | (lane == 63 ? extra : 0ull);
+    const bool writes = tail && !(continued && in_first_run);
+    if (writes) bits[word] = v | (lane == 63 ? extra : 0ull);
+    // mark the written bricks in the table: the writers' bricks rise with the lanes,
+    // so those sharing a table word are consecutive; one atomic per table word
+    const uint32_t tw = word >> 5;
+    for (uint64_t wm = ballot(writes); wm;) {
+      const int L = __ffsll(static_cast<unsigned long long>(wm)) - 1;
+      const uint32_t t0 = static_cast<uint32_t>(__shfl(static_cast<int>(tw), L));
+      const uint64_t grp = ballot(writes && tw == t0);
+      uint32_t mbits = (writes && tw == t0) ? 1u << (word & 31) : 0u;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mbits |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(mbits), off));
+      if (lane == L) atomicOr(table + t0, mbits);
+      wm &= ~grp;
+    }
   }
 }
 
@@ -1190,6 +1192,20 @@ __device__ __forceinline__ uint32_t spread_every(uint32_t x, int d) {  // Morton
   return x;
 }
 
+// A point primitive is isolated when no other primitive shares its cell (they
+// would be next to it in key order) and no occupied cell lies within reach of it:
+// in cell units, the per-axis gaps between the point's coordinate t = (x - lo) /
+// side and a cell's interval, summed in squares, exceed plan->reach^2, where reach
+// is eps / side plus a slack covering the rounding of t (computed as the key
+// kernel computes it) for both points. A neighbour j of the point (the fp32 test
+// true) is within eps (1 + 2^-22) per axis; its cell's gap vector is bounded by
+// |t_j - t| per axis, whose norm the slack covers, so its cell is within reach.
+// Conservative: a false answer only means "walk it". Reach is below 2, so the
+// reachable cells lie within 2 per axis: at most 2^d brick words per query.
+__device__ __forceinline__ bool brick_marked(const uint32_t* __restrict__ table, uint32_t b) {
+  return (table[b >> 5] >> (b & 31)) & 1u;
+}
+
 // Bits of a brick whose coordinate on axis a lies in [l, h] (local, l <= h).
 template <int D>
 __device__ __forceinline__ uint64_t axis_bits(int a, int l, int h) {
@@ -1203,26 +1219,31 @@ __device__ __forceinline__ uint64_t axis_bits(int a, int l, int h) {
   }
 }
 
-// Point primitive p (key order) is isolated if no other primitive shares its lone
-// cell (they would be next to it in key order) and the neighbouring lone cells are
-// all empty. Conservative: a false answer only means "walk it".
+// Gap of coordinate t (its own cell c) to the interval of cell `cell`, in cell units.
+__device__ __forceinline__ float cell_gap(float t, int c, int cell) {
+  return cell == c ? 0.0f : (cell > c ? static_cast<float>(cell) - t : t - static_cast<float>(cell + 1));
+}
+
 template <int D>
-__device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int m, int p, const LoneGeom& g,
-                                         const uint64_t* __restrict__ bits) {
-  const uint32_t lc = lone_code<D>(key32(pkey, p));
-  if ((p > 0 && lone_code<D>(key32(pkey, p - 1)) == lc) || (p + 1 < m && lone_code<D>(key32(pkey, p + 1)) == lc))
-    return false;
+__device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int m, int p, float4 pt,
+                                         const GridPlan& g, const float* lo_b, const uint64_t* __restrict__ words,
+                                         const uint32_t* __restrict__ table) {
+  const uint32_t key = key32(pkey, p);
+  if ((p > 0 && key32(pkey, p - 1) == key) || (p + 1 < m && key32(pkey, p + 1) == key)) return false;
   constexpr int S = kBrickShift<D>, W = 1 << S;
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  const float xv[3] = {pt.x, pt.y, pt.z};
+  float t[3] = {0.0f, 0.0f, 0.0f};
+  int c[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const int c = static_cast<int>(compact_every(lc >> (D - 1 - a), D));
-    lo[a] = c > 0 ? c - 1 : 0;
-    hi[a] = static_cast<uint32_t>(c + 1) < g.nl[a] ? c + 1 : c;
+    t[a] = fmaxf((xv[a] - lo_b[a]) * g.inv_h[a], 0.0f);  // as the key kernel computes it
+    c[a] = static_cast<int>(compact_every(key >> (D - 1 - a), D));
+    lo[a] = c[a] >= 2 ? c[a] - 2 : 0;
+    hi[a] = min(c[a] + 2, static_cast<int>(g.ncell[a]) - 1);
   }
-  const uint32_t own_brick = lc >> 6;
-  const int own_bit = brick_bit<D>(lc);
-  bool hit = false;
+  const float r2 = g.reach * g.reach;
+  const uint32_t own_brick = key >> 6;
+  const int own_bit = brick_bit<D>(key);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1233,20 +1254,30 @@ __device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int 
         bool use = br[0] <= (hi[0] >> S) && br[1] <= (hi[1] >> S);
         if (D == 3) use = use && br[2] <= (hi[2] >> S);
         if (!use) continue;
-        uint64_t mask = ~0ull;
-        uint32_t idx = 0;
+        uint32_t b = 0;
+        uint64_t box = ~0ull;  // the brick's cells within 2 per axis
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           const int base = br[a] << S;
-          const int l = (lo[a] > base ? lo[a] : base) - base;
-          const int h = (hi[a] < base + W - 1 ? hi[a] : base + W - 1) - base;
-          mask &= axis_bits<D>(a, l, h);
-          idx |= spread_every(static_cast<uint32_t>(br[a]), D) << (D - 1 - a);
+          box &= axis_bits<D>(a, max(lo[a], base) - base, min(hi[a], base + W - 1) - base);
+          b |= spread_every(static_cast<uint32_t>(br[a]), D) << (D - 1 - a);
         }
-        if (idx == own_brick) mask &= ~(1ull << own_bit);
-        hit |= (bits[idx] & mask) != 0ull;
+        if (!brick_marked(table, b)) continue;
+        uint64_t occ = words[b] & box;
+        if (b == own_brick) occ &= ~(1ull << own_bit);
+        // the occupied cells among them (usually none, or a few): exact reach test
+        for (; occ; occ &= occ - 1) {
+          const int bit = __ffsll(static_cast<unsigned long long>(occ)) - 1;
+          const int lx = D == 3 ? bit >> 4 : bit >> 3;
+          const int ly = D == 3 ? (bit >> 2) & 3 : bit & 7;
+          const int lz = D == 3 ? bit & 3 : 0;
+          const float gx = cell_gap(t[0], c[0], (br[0] << S) + lx);
+          const float gy = cell_gap(t[1], c[1], (br[1] << S) + ly);
+          const float gz = D == 3 ? cell_gap(t[2], c[2], (br[2] << S) + lz) : 0.0f;
+          if (gx * gx + gy * gy + gz * gz <= r2) return false;
+        }
       }
-  return !hit;
+  return true;
 }
 
 // A workgroup tests kLoneRounds x 256 consecutive primitives and lists the ones
@@ -1267,13 +1298,16 @@ __device__ __forceinline__ int64_t lone_segment(int m) {
 template <int D>
 __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint64_t* __restrict__ pkey,
                                                      const GridPlan* __restrict__ plan,
-                                                     const uint64_t* __restrict__ bits, int* __restrict__ list,
+                                                     const uint64_t* __restrict__ words,
+                                                     const uint32_t* __restrict__ table,
+                                                     const uint32_t* __restrict__ bounds, int* __restrict__ list,
                                                      int* __restrict__ list_n) {
   __shared__ int s_cnt[kLoneRounds * 4 + 1];
   if (!plan->lone_on) return;
-  LoneGeom g;
+  const GridPlan gp = *plan;
+  float lo_b[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int k = 0; k < 3; ++k) g.nl[k] = k < D ? (plan->ncell[k] + 1) / 2 : 1;
+  for (int k = 0; k < D; ++k) lo_b[k] = ord2f(bounds[k]);
   const int m = tree_m(a.t);
   const int64_t base = blockIdx.x * int64_t(kLoneRounds * 256);
   if (base >= m) return;  // whole workgroup
@@ -1286,10 +1320,11 @@ __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint64_t*
     bool query = false, lone = false;
     int i = 0;
     if (p < m) {
-      i = rec_index(a.prim_lo[p]);
+      const float4 lr = a.prim_lo[p];
+      i = rec_index(lr);
       if (i >= 0) {
         query = true;
-        lone = isolated<D>(pkey, m, static_cast<int>(p), g, bits);
+        lone = isolated<D>(pkey, m, static_cast<int>(p), lr, gp, lo_b, words, table);
       }
     }
     if (lone) {
@@ -1850,17 +1885,18 @@ inline dim3 grid_of(int64_t n, int block) {
 }
 
 template <int D>
-void lone_t(const TravArgs& a, const uint64_t* pkey, const GridPlan* plan, uint64_t* bits, int* list, int* list_n,
-            hipStream_t s) {
-  // the plan allows at most n / 2 words (the bitmap lives in an n-int buffer)
+void lone_t(const TravArgs& a, const uint64_t* pkey, const GridPlan* plan, uint32_t* table, uint64_t* words,
+            const uint32_t* bounds, int* list, int* list_n, hipStream_t s) {
+  // the plan allows a table of at most n / 2 64-bit words (it lives in an n-int buffer)
   const int64_t gc = std::min<int64_t>(std::max<int64_t>(ceil_div(a.n / 2, 256 * 4), 1), 2048);
-  hipLaunchKernelGGL(k_lone_clear, dim3(static_cast<unsigned>(gc)), dim3(256), 0, s, plan, bits);
+  hipLaunchKernelGGL(k_lone_clear, dim3(static_cast<unsigned>(gc)), dim3(256), 0, s, plan,
+                     reinterpret_cast<uint64_t*>(table));
   const int64_t gb = std::min<int64_t>(ceil_div(a.t.m_cap, 256), 4096);  // 4 wavefronts of 64 primitives
   hipLaunchKernelGGL(k_lone_bits<D>, dim3(static_cast<unsigned>(gb > 0 ? gb : 1)), dim3(256), 0, s, pkey, a.t.d_m,
-                     plan, bits, list_n);
+                     plan, words, table, list_n);
   const int64_t gf = ceil_div(a.t.m_cap, kLoneRounds * 256);
   hipLaunchKernelGGL(k_lone_filter<D>, dim3(static_cast<unsigned>(gf > 0 ? gf : 1)), dim3(256), 0, s, a, pkey, plan,
-                     bits, list, list_n);
+                     words, table, bounds, list, list_n);
 }
 
 template <int D, bool B>
@@ -1930,11 +1966,11 @@ void main_dispatch(const TravArgs& a, bool densebox, bool all_core, bool first_b
 
 }  // namespace
 
-void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint64_t* bits,
-                        int* list, int* list_n, hipStream_t s) {
+void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, const GridPlan* plan, uint32_t* table,
+                        uint64_t* words, const uint32_t* bounds, int* list, int* list_n, hipStream_t s) {
   if (a.n <= 0) return;
-  if (dim == 3) lone_t<3>(a, prim_key, plan, bits, list, list_n, s);
-  else lone_t<2>(a, prim_key, plan, bits, list, list_n, s);
+  if (dim == 3) lone_t<3>(a, prim_key, plan, table, words, bounds, list, list_n, s);
+  else lone_t<2>(a, prim_key, plan, table, words, bounds, list, list_n, s);
 }
 
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {

@@ -31,7 +31,7 @@ __device__ __forceinline__ int prefix_len(const K* __restrict__ keys, int m, int
 template <typename K>
 __global__ __launch_bounds__(kBlock) void k_karras(const K* __restrict__ keys, int m_cap, const int* __restrict__ d_m,
                                                    int* __restrict__ other, int* __restrict__ gamma_out,
-                                                   int* __restrict__ parent) {
+                                                   int* __restrict__ parent, int* __restrict__ flags) {
   const int m = d_m ? *d_m : m_cap;
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= m - 1) return;
@@ -55,6 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_karras(const K* __restrict__ keys, i
   int first = static_cast<int>(d > 0 ? i : j), last = static_cast<int>(d > 0 ? j : i);
   other[i] = static_cast<int>(j);
   gamma_out[i] = g;
+  flags[i] = 0;  // the refit's arrival counter of node i
   // parent[] holds internal nodes at [0, m-1) and leaf l at m-1+l
   parent[first == g ? (m - 1) + g : g] = i;
   parent[last == g + 1 ? (m - 1) + g + 1 : g + 1] = i;
@@ -263,8 +264,7 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
   if (m_cap <= 0) return;
   int g = static_cast<int>(ceil_div(m_cap, kBlock));
   if (m_cap >= 2) {
-    fill_u32(reinterpret_cast<uint32_t*>(flags), 0, m_cap - 1, s);
-    hipLaunchKernelGGL(k_karras<K>, dim3(g), dim3(kBlock), 0, s, keys, m_cap, d_m, other, gamma, parent);
+    hipLaunchKernelGGL(k_karras<K>, dim3(g), dim3(kBlock), 0, s, keys, m_cap, d_m, other, gamma, parent, flags);
   }
   hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
   if (m_cap >= 2) {

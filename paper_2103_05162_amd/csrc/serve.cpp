@@ -1,11 +1,15 @@
 // Served clustering. Jobs arrive one at a time, each with its own device
-// buffers, eps and minPts. In batched mode a worker thread takes the jobs
-// waiting in the queue, oldest first, as long as the batch still fits in a
-// fixed HBM budget, and runs them as one batched launch sequence (continuous
-// batching: a job that arrives while a batch runs joins the next one). The
-// budget is allocated once, when the server is created; nothing is allocated
-// per job. In FIFO mode the worker runs one job at a time with fdb_dbscan, the
-// plain server the batched one is compared with.
+// buffers, eps and minPts. In batched mode the arena is split into kSlots slots,
+// each with its own stream, handle, pinned mirror and completion event; a worker
+// thread fills any free slot with the jobs waiting in the queue, oldest first, as
+// long as the batch fits in the slot, and launches them as one batched launch
+// sequence without waiting for it. So while one batch runs on the device, the
+// jobs that arrived meanwhile are gathered and clustered in the other slot
+// (continuous batching: admission as slots and memory free up, overlapping work).
+// A slot is handed back when its event has fired. The budget is allocated once,
+// when the server is created; nothing is allocated per job. In FIFO mode the
+// worker runs one job at a time with fdb_dbscan in the whole arena, the plain
+// server the batched one is compared with.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,16 +82,35 @@ size_t small_bytes_for(int b) {
 
 }  // namespace
 
+namespace {
+
+constexpr int kSlots = 2;  // batches that can be on the device at once (batched mode)
+
+// One batch's place on the device: a share of the arena and everything a batch
+// in flight needs of its own.
+struct Slot {
+  fdb_handle* h = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char* arena = nullptr;
+  size_t bytes = 0;
+  char* host = nullptr;  // pinned mirror of the batch's small arrays; K and the info word come back here
+  bool busy = false;
+  std::vector<int64_t> ids;
+  size_t ncl_off = 0, info_off = 0;
+  int64_t t_launch = 0;
+};
+
+}  // namespace
+
 struct fdb_server {
   int device = 0;
   int mode = FDB_SERVE_BATCHED;
   fdb_options opt{};
   size_t budget = 0;
   int max_batch = 1;
-  fdb_handle* h = nullptr;
-  hipStream_t stream = nullptr;
+  std::vector<Slot> slots;
   char* arena = nullptr;
-  char* host = nullptr;  // pinned mirror of a batch's small arrays
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<int64_t> queue;
@@ -96,14 +119,16 @@ struct fdb_server {
   bool stop = false;
   int64_t batches = 0, max_queue = 0;
   int32_t max_batch_seen = 0;
-  double busy_s = 0.0;
+  double busy_s = 0.0;    // time with at least one batch on the device
+  int in_flight = 0;      // slots busy
+  int64_t busy_since = 0;
   std::thread worker;
 };
 
 namespace {
 
 void finish_jobs(fdb_server* s, const std::vector<int64_t>& ids, const std::vector<int32_t>& ncl,
-                 const std::vector<int32_t>& st, int64_t t0, int64_t t1) {
+                 const std::vector<int32_t>& st, int64_t t1) {
   std::lock_guard<std::mutex> lk(s->mu);
   for (size_t k = 0; k < ids.size(); ++k) {
     Job& j = s->jobs[ids[k]];
@@ -114,17 +139,23 @@ void finish_jobs(fdb_server* s, const std::vector<int64_t>& ids, const std::vect
   }
   s->pending -= static_cast<int64_t>(ids.size());
   s->batches += 1;
-  s->busy_s += static_cast<double>(t1 - t0) * 1e-9;
   s->cv_done.notify_all();
 }
 
-// One batch: gather, batched clustering, scatter, K read-back, wait.
-fdb_status run_batch(fdb_server* s, const std::vector<fdb_job>& in, int dim, int64_t n, std::vector<int32_t>& ncl,
-                     std::vector<int32_t>& st) {
+// Start of a launch on the device / end of one (busy time is the union).
+void mark_busy(fdb_server* s, int64_t t, int delta) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (delta > 0 && s->in_flight++ == 0) s->busy_since = t;
+  if (delta < 0 && --s->in_flight == 0) s->busy_s += static_cast<double>(t - s->busy_since) * 1e-9;
+}
+
+// One batch into slot sl: gather, batched clustering, scatter, then K and the
+// info word copied back and the slot's event recorded; nothing waits.
+fdb_status launch_batch(fdb_server* s, Slot& sl, const std::vector<fdb_job>& in, int dim, int64_t n) {
   const int b = static_cast<int>(in.size());
   BatchLayout L;
-  if (!batch_layout(n, b, dim, s->opt, &L) || L.total > s->budget) return FDB_ERR_NOMEM;
-  char* small = s->host;
+  if (!batch_layout(n, b, dim, s->opt, &L) || L.total > sl.bytes) return FDB_ERR_NOMEM;
+  char* small = sl.host;
   std::memset(small, 0, L.small_bytes);
   auto* off = reinterpret_cast<int64_t*>(small + L.off);
   auto* eps = reinterpret_cast<float*>(small + L.eps);
@@ -147,106 +178,183 @@ fdb_status run_batch(fdb_server* s, const std::vector<fdb_job>& in, int dim, int
     o += in[k].n;
   }
   off[b] = o;
-  char* base = s->arena;
+  char* base = sl.arena;
   char* dsmall = base + L.small;
   float* pts = reinterpret_cast<float*>(base + L.pts);
   int32_t* lab = reinterpret_cast<int32_t*>(base + L.lab);
   uint8_t* core = reinterpret_cast<uint8_t*>(base + L.core);
   const JobSeg* dseg = reinterpret_cast<const JobSeg*>(dsmall + L.seg);
   int32_t* dncl = reinterpret_cast<int32_t*>(dsmall + L.ncl);
-  hipStream_t q = s->stream;
+  hipStream_t q = sl.stream;
   if (hipMemcpyAsync(dsmall, small, L.small_bytes, hipMemcpyHostToDevice, q) != hipSuccess) return FDB_ERR_HIP;
   fdb::launch_gather(dseg, b, gb, dim, pts, q);
-  fdb_status r = fdb_dbscan_batched(s->h, pts, n, reinterpret_cast<const int64_t*>(dsmall + L.off), b, dim,
+  fdb_status r = fdb_dbscan_batched(sl.h, pts, n, reinterpret_cast<const int64_t*>(dsmall + L.off), b, dim,
                                     reinterpret_cast<const float*>(dsmall + L.eps),
                                     reinterpret_cast<const int32_t*>(dsmall + L.mp), &s->opt, lab, core, dncl,
                                     base + L.ws, L.ws_bytes, q);
   if (r != FDB_OK) return r;
   fdb::launch_scatter_jobs(dseg, b, sb, lab, core, q);
-  int32_t* hncl = reinterpret_cast<int32_t*>(small + L.ncl);
-  if (hipMemcpyAsync(hncl, dncl, static_cast<size_t>(b) * 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
-      hipStreamSynchronize(q) != hipSuccess)
+  // the mirror's small arrays were consumed by the copy above; K and the info word
+  // land in their place (ordered after that copy on the stream)
+  sl.ncl_off = L.ncl;
+  sl.info_off = L.eps;
+  if (hipMemcpyAsync(small + L.ncl, dncl, static_cast<size_t>(b) * 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+      hipMemcpyAsync(small + L.eps, fdb::handle_info(sl.h), 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+      hipEventRecord(sl.done, q) != hipSuccess)
     return FDB_ERR_HIP;
-  uint32_t info = 0;
-  if (fdb_last_info(s->h, &info) != FDB_OK) return FDB_ERR_HIP;
-  for (int k = 0; k < b; ++k) {
-    ncl[k] = hncl[k];
-    st[k] = (info & FDB_INFO_INTERNAL) ? FDB_ERR_INTERNAL : (hncl[k] < 0 ? FDB_ERR_NONFINITE : FDB_OK);
-  }
   return FDB_OK;
 }
 
-void worker_main(fdb_server* s) {
-  (void)hipSetDevice(s->device);
+// A finished slot: its jobs' K and status from the pinned mirror.
+void retire(fdb_server* s, Slot& sl, fdb_status r) {
+  const size_t b = sl.ids.size();
+  std::vector<int32_t> ncl(b, -1), st(b, static_cast<int32_t>(r));
+  if (r == FDB_OK) {
+    const int32_t* hncl = reinterpret_cast<const int32_t*>(sl.host + sl.ncl_off);
+    const uint32_t info = *reinterpret_cast<const uint32_t*>(sl.host + sl.info_off);
+    for (size_t k = 0; k < b; ++k) {
+      ncl[k] = hncl[k];
+      st[k] = (info & FDB_INFO_INTERNAL) ? FDB_ERR_INTERNAL : (hncl[k] < 0 ? FDB_ERR_NONFINITE : FDB_OK);
+    }
+  }
+  const int64_t t = now_ns();
+  finish_jobs(s, sl.ids, ncl, st, t);
+  mark_busy(s, t, -1);
+  sl.ids.clear();
+  sl.busy = false;
+}
+
+// Takes the queued jobs of the oldest job's dim, in arrival order, while the
+// batch fits in `bytes` and holds at most `cap` jobs (the first job always fits).
+// Called with s->mu held.
+int64_t take_batch(fdb_server* s, size_t bytes, int cap, std::vector<int64_t>& ids, std::vector<fdb_job>& in,
+                   int* dim_out) {
+  const int dim = s->jobs[s->queue.front()].in.dim;
+  int64_t n = 0;
+  for (auto it = s->queue.begin(); it != s->queue.end() && static_cast<int>(ids.size()) < cap;) {
+    const fdb_job& j = s->jobs[*it].in;
+    if (j.dim != dim) {
+      ++it;
+      continue;
+    }
+    if (!ids.empty()) {
+      BatchLayout L;
+      if (!batch_layout(n + j.n, static_cast<int>(ids.size()) + 1, dim, s->opt, &L) || L.total > bytes) break;
+    }
+    ids.push_back(*it);
+    in.push_back(j);
+    n += j.n;
+    it = s->queue.erase(it);
+  }
+  const int64_t t = now_ns();
+  for (int64_t id : ids) {
+    Job& j = s->jobs[id];
+    j.state = 1;
+    j.t_start = t;
+    j.batch_jobs = static_cast<int32_t>(ids.size());
+  }
+  s->max_batch_seen = std::max(s->max_batch_seen, static_cast<int32_t>(ids.size()));
+  *dim_out = dim;
+  return n;
+}
+
+void worker_fifo(fdb_server* s) {
+  Slot& sl = s->slots[0];
   std::vector<int64_t> ids;
   std::vector<fdb_job> in;
-  std::vector<int32_t> ncl, st;
   for (;;) {
-    int dim = 3;
-    int64_t n = 0;
     ids.clear();
     in.clear();
+    int dim = 3;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
       if (s->queue.empty()) return;  // stopping, and nothing left to run
-      dim = s->jobs[s->queue.front()].in.dim;
-      const int cap = s->mode == FDB_SERVE_FIFO ? 1 : s->max_batch;
-      for (auto it = s->queue.begin(); it != s->queue.end() && static_cast<int>(ids.size()) < cap;) {
-        const fdb_job& j = s->jobs[*it].in;
-        if (j.dim != dim) {
-          ++it;
-          continue;
-        }
-        if (!ids.empty()) {  // admission: the batch must still fit (the first job always does)
-          BatchLayout L;
-          if (!batch_layout(n + j.n, static_cast<int>(ids.size()) + 1, dim, s->opt, &L) || L.total > s->budget)
-            break;
-        }
-        ids.push_back(*it);
-        in.push_back(j);
-        n += j.n;
-        it = s->queue.erase(it);
-      }
-      const int64_t t = now_ns();
-      for (int64_t id : ids) {
-        Job& j = s->jobs[id];
-        j.state = 1;
-        j.t_start = t;
-        j.batch_jobs = static_cast<int32_t>(ids.size());
-      }
-      s->max_batch_seen = std::max(s->max_batch_seen, static_cast<int32_t>(ids.size()));
+      take_batch(s, sl.bytes, 1, ids, in, &dim);
     }
     const int64_t t0 = now_ns();
-    ncl.assign(ids.size(), -1);
-    st.assign(ids.size(), FDB_OK);
-    fdb_status r;
-    if (s->mode == FDB_SERVE_FIFO) {
-      const fdb_job& j = in[0];
-      int32_t k = -1;
-      r = fdb_dbscan(s->h, j.points, j.n, j.dim, j.eps, j.min_pts, &s->opt, j.labels, j.is_core, &k, s->arena,
-                     s->budget, s->stream);
-      ncl[0] = k;
-      st[0] = r;
-      if (r == FDB_ERR_NONFINITE || r == FDB_ERR_INTERNAL) r = FDB_OK;
-    } else {
-      r = run_batch(s, in, dim, n, ncl, st);
-    }
-    if (r != FDB_OK) {
-      (void)hipStreamSynchronize(s->stream);
-      std::fill(st.begin(), st.end(), static_cast<int32_t>(r));
-    }
-    finish_jobs(s, ids, ncl, st, t0, now_ns());
+    mark_busy(s, t0, +1);
+    const fdb_job& j = in[0];
+    int32_t k = -1;
+    fdb_status r = fdb_dbscan(sl.h, j.points, j.n, j.dim, j.eps, j.min_pts, &s->opt, j.labels, j.is_core, &k,
+                              sl.arena, sl.bytes, sl.stream);
+    if (r != FDB_OK && r != FDB_ERR_NONFINITE && r != FDB_ERR_INTERNAL) (void)hipStreamSynchronize(sl.stream);
+    const int64_t t1 = now_ns();
+    finish_jobs(s, ids, std::vector<int32_t>{k}, std::vector<int32_t>{static_cast<int32_t>(r)}, t1);
+    mark_busy(s, t1, -1);
   }
 }
 
+void worker_batched(fdb_server* s) {
+  std::vector<fdb_job> in;
+  for (;;) {
+    // hand back the slots whose batches have finished
+    for (Slot& sl : s->slots) {
+      if (!sl.busy) continue;
+      const hipError_t e = hipEventQuery(sl.done);
+      if (e == hipErrorNotReady) continue;
+      retire(s, sl, e == hipSuccess ? FDB_OK : FDB_ERR_HIP);
+    }
+    // fill the free slots with queued jobs
+    bool launched = false;
+    for (Slot& sl : s->slots) {
+      if (sl.busy) continue;
+      in.clear();
+      int dim = 3;
+      int64_t n = 0;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->queue.empty()) break;
+        n = take_batch(s, sl.bytes, s->max_batch, sl.ids, in, &dim);
+      }
+      const int64_t t = now_ns();
+      mark_busy(s, t, +1);
+      sl.busy = true;
+      sl.t_launch = t;
+      const fdb_status r = launch_batch(s, sl, in, dim, n);
+      if (r != FDB_OK) {
+        (void)hipStreamSynchronize(sl.stream);
+        retire(s, sl, r);
+      }
+      launched = true;
+    }
+    int busy = 0;
+    Slot* oldest = nullptr;
+    for (Slot& sl : s->slots)
+      if (sl.busy) {
+        ++busy;
+        if (!oldest || sl.t_launch < oldest->t_launch) oldest = &sl;
+      }
+    if (launched) continue;
+    if (busy == static_cast<int>(s->slots.size())) {
+      (void)hipEventSynchronize(oldest->done);  // no slot free: nothing to do until one is
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (busy == 0) {
+      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+      if (s->queue.empty()) return;  // stopping, and nothing left to run
+    } else if (s->queue.empty()) {
+      // a batch runs and a slot is free: wake for a new job or poll the batch again
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    }
+  }
+}
+
+void worker_main(fdb_server* s) {
+  (void)hipSetDevice(s->device);
+  if (s->mode == FDB_SERVE_FIFO) worker_fifo(s);
+  else worker_batched(s);
+}
+
 bool job_fits(const fdb_server* s, int64_t n, int dim) {
+  const size_t bytes = s->slots[0].bytes;
   if (s->mode == FDB_SERVE_FIFO) {
     size_t ws = 0;
-    return fdb_workspace_bytes(n, dim, &s->opt, &ws) == FDB_OK && ws <= s->budget;
+    return fdb_workspace_bytes(n, dim, &s->opt, &ws) == FDB_OK && ws <= bytes;
   }
   BatchLayout L;
-  return batch_layout(n, 1, dim, s->opt, &L) && L.total <= s->budget;
+  return batch_layout(n, 1, dim, s->opt, &L) && L.total <= bytes;
 }
 
 void fill_result(const Job& j, fdb_job_result* r) {
@@ -256,6 +364,20 @@ void fill_result(const Job& j, fdb_job_result* r) {
   r->batch_jobs = j.batch_jobs;
   r->queue_us = j.state >= 1 ? static_cast<double>(j.t_start - j.t_submit) * 1e-3 : -1.0;
   r->latency_us = j.state == 2 ? static_cast<double>(j.t_done - j.t_submit) * 1e-3 : -1.0;
+}
+
+// Frees what fdb_server_create set up (the device must be current).
+void release(fdb_server* s) {
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.h) fdb_destroy(sl.h);
+  }
+  s->slots.clear();
+  if (s->arena) (void)hipFree(s->arena);
+  s->arena = nullptr;
 }
 
 }  // namespace
@@ -280,35 +402,38 @@ fdb_status fdb_server_create(int device, size_t hbm_budget_bytes, int32_t max_ba
   s->opt = o;
   s->budget = hbm_budget_bytes;
   s->max_batch = mode == FDB_SERVE_FIFO ? 1 : max_batch;
+  const int nslots = mode == FDB_SERVE_FIFO ? 1 : kSlots;
+  s->slots.resize(static_cast<size_t>(nslots));
   int prev = -1;
   (void)hipGetDevice(&prev);
   fdb_status r = FDB_OK;
   if (hipSetDevice(device) != hipSuccess) r = FDB_ERR_INVALID;
-  if (r == FDB_OK) r = fdb_create(&s->h, device);
-  if (r == FDB_OK && hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) r = FDB_ERR_HIP;
   if (r == FDB_OK && hipMalloc(reinterpret_cast<void**>(&s->arena), s->budget) != hipSuccess) r = FDB_ERR_NOMEM;
-  if (r == FDB_OK &&
-      hipHostMalloc(reinterpret_cast<void**>(&s->host), small_bytes_for(s->max_batch), hipHostMallocDefault) !=
-          hipSuccess)
-    r = FDB_ERR_NOMEM;
+  const size_t share = s->budget / static_cast<size_t>(nslots) & ~size_t(255);
+  for (int k = 0; k < nslots && r == FDB_OK; ++k) {
+    Slot& sl = s->slots[static_cast<size_t>(k)];
+    sl.arena = s->arena + share * static_cast<size_t>(k);
+    sl.bytes = share;
+    r = fdb_create(&sl.h, device);
+    if (r == FDB_OK && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) r = FDB_ERR_HIP;
+    if (r == FDB_OK && hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) r = FDB_ERR_HIP;
+    if (r == FDB_OK &&
+        hipHostMalloc(reinterpret_cast<void**>(&sl.host), small_bytes_for(s->max_batch), hipHostMallocDefault) !=
+            hipSuccess)
+      r = FDB_ERR_NOMEM;
+  }
+  if (r == FDB_OK) {
+    try {
+      s->worker = std::thread(worker_main, s);
+    } catch (...) {
+      r = FDB_ERR_NOMEM;
+    }
+  }
+  if (r != FDB_OK) release(s);
   if (prev >= 0) (void)hipSetDevice(prev);
   if (r != FDB_OK) {
-    if (s->host) (void)hipHostFree(s->host);
-    if (s->arena) (void)hipFree(s->arena);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
-    if (s->h) fdb_destroy(s->h);
     delete s;
     return r;
-  }
-  try {
-    s->worker = std::thread(worker_main, s);
-  } catch (...) {
-    (void)hipHostFree(s->host);
-    (void)hipFree(s->arena);
-    (void)hipStreamDestroy(s->stream);
-    fdb_destroy(s->h);
-    delete s;
-    return FDB_ERR_NOMEM;
   }
   *out = s;
   return FDB_OK;
@@ -416,11 +541,7 @@ void fdb_server_destroy(fdb_server* s) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(s->device);
-  (void)hipStreamSynchronize(s->stream);
-  (void)hipHostFree(s->host);
-  (void)hipFree(s->arena);
-  (void)hipStreamDestroy(s->stream);
-  fdb_destroy(s->h);
+  release(s);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete s;
 }

@@ -9,7 +9,8 @@ Two more files cover the many-cloud workloads, cloud by cloud:
   * c4_batched_4096: every cloud of the 4096-cloud batch, K and the first 16 hex
     digits of the SHA-256 of its canonical labels and core flags;
   * c5_served_sample: the same for a fixed sample of requests of the served trace
-    (the requests' clouds, eps and minPts as the trace draws them).
+    (the requests' clouds, eps and minPts as the trace draws them), drawn among
+    the requests of at most 65,536 points.
 
     python tests/golden/make_golden.py [name ...]
 """
@@ -32,6 +33,7 @@ from workloads.gen import CONFIGS, batched_clouds, served_trace, workload  # noq
 SERVED = dict(requests=22000, rate=2000.0, pool_per_dim=128)
 SERVED_WARM_S = 1.0
 SERVED_SAMPLE = 48
+SERVED_MAX_N = 65536
 
 
 def summarize(name: str) -> dict:
@@ -80,23 +82,28 @@ def summarize_batched() -> dict:
             "clouds": per, "oracle_seconds": round(time.time() - t0, 1), "threads": threads}
 
 
-def served_sample_indices(arrival):
+def served_sample_indices(arrival, n):
+    """A fixed sample of the counted requests (after the warm-up) among those of at
+    most SERVED_MAX_N points: the oracle's union loop visits every eps-pair, and the
+    largest requests' clumps hold ~10^12 of them."""
     first = int(np.searchsorted(arrival, SERVED_WARM_S))
+    idx = np.arange(first, len(arrival))
+    idx = idx[n[first:] <= SERVED_MAX_N]
     rng = np.random.default_rng(0)
-    return np.sort(rng.choice(np.arange(first, len(arrival)), size=SERVED_SAMPLE, replace=False))
+    return np.sort(rng.choice(idx, size=SERVED_SAMPLE, replace=False))
 
 
 def summarize_served() -> dict:
     threads = len(os.sched_getaffinity(0))
     pool, req = served_trace(**SERVED)
-    idx = served_sample_indices(req["arrival_s"])
+    idx = served_sample_indices(req["arrival_s"], req["n"])
     t0 = time.time()
     per = []
     for r in idx:
         d, c = int(req["dim"][r]), int(req["cloud"][r])
         k, ls, cs = _cloud_entry(pool[d][c], req["eps"][r], req["min_pts"][r], threads)
         per.append([int(r), d, c, int(req["n"][r]), k, ls, cs])
-    return {"workload": "c5_served_sample", "trace": SERVED, "warm_s": SERVED_WARM_S,
+    return {"workload": "c5_served_sample", "trace": SERVED, "warm_s": SERVED_WARM_S, "max_n": SERVED_MAX_N,
             "requests": per, "oracle_seconds": round(time.time() - t0, 1), "threads": threads}
 
 

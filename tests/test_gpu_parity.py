@@ -414,7 +414,7 @@ def test_isolated_point_test_edges(dev, d):
     rng = np.random.default_rng(70 + d)
     eps = 0.03 if d == 3 else 0.02
     h = eps / np.sqrt(d)              # grid cell side (the bounds below start at 0)
-    word = (8 if d == 3 else 16) * h   # side of the cells one occupancy word covers
+    word = (4 if d == 3 else 8) * h    # side of the cells one occupancy word covers
     blob = 0.5 + rng.uniform(0, 4 * eps, size=(5000 if d == 3 else 3000, d))
     scattered = rng.uniform(0, 1, size=(2000 if d == 3 else 400, d))
     corners = np.array([np.zeros(d), np.ones(d)])

@@ -37,7 +37,8 @@ def _jobs(seed, count, lo=200, hi=20000):
     return out
 
 
-def _submit_all(srv, dev, jobs):
+def _upload(dev, jobs):
+    """Device copies of the jobs' points, and their output buffers (synchronised)."""
     import torch
     bufs = []
     for pts, eps, mp in jobs:
@@ -46,6 +47,11 @@ def _submit_all(srv, dev, jobs):
         core = torch.zeros(len(pts), dtype=torch.uint8, device=dev)
         bufs.append((t, lab, core))
     torch.cuda.synchronize()
+    return bufs
+
+
+def _submit_all(srv, dev, jobs):
+    bufs = _upload(dev, jobs)
     tickets = [srv.submit_raw(t.data_ptr(), t.shape[0], t.shape[1], eps, mp, lab.data_ptr(), core.data_ptr())
                for (t, lab, core), (_, eps, mp) in zip(bufs, jobs)]
     return bufs, tickets
@@ -92,7 +98,7 @@ def test_budget_admission_and_fifo(dev):
     import torch
     import paper_2103_05162_amd as fdb
     jobs = _jobs(13, 24, lo=1000, hi=60000)
-    budget = 16 << 20
+    budget = 24 << 20  # two slots of 12 MiB in batched mode
     srv = fdb.Server(0, budget_bytes=budget, max_batch=1024, mode="batched")
     fifo = fdb.Server(0, budget_bytes=budget, mode="fifo")
     try:
@@ -149,5 +155,46 @@ def test_nonfinite_job_is_isolated_and_empty_job(dev):
                 assert r["num_clusters"] == ok and np.array_equal(lab.cpu().numpy(), ol)
             else:
                 assert r["status"] == 4 and r["num_clusters"] == -1
+    finally:
+        srv.close()
+
+
+def test_small_job_is_launched_while_a_large_one_runs(dev):
+    """Two slots: a small job submitted while a large job's batch is on the device is
+    launched at once in the other slot, before the large job is done, instead of
+    waiting for it (whether the device then runs the two batches side by side is up
+    to its queues); each job's labels, core flags and K are those it gets alone."""
+    import time
+    import torch
+    import paper_2103_05162_amd as fdb
+    rng = np.random.default_rng(21)
+    big = (mixture_cloud(rng, 2_000_000, d=3), 0.02, 5)
+    small = (mixture_cloud(rng, 4000, d=3), 0.02, 5)
+    srv = fdb.Server(0, budget_bytes=8 << 30, max_batch=64, mode="batched", algo="densebox")
+    try:
+        (bt, bl, bc), (st_, sl_, sc_) = _upload(dev, [big, small])
+        _say(f"[gpu] two slots: big job n={bt.shape[0]}, small job n={st_.shape[0]}")
+        tb = srv.submit_raw(bt.data_ptr(), bt.shape[0], 3, big[1], big[2], bl.data_ptr(), bc.data_ptr())
+        t0 = time.perf_counter()
+        while srv.poll(tb)["queue_us"] < 0:  # until the big job's batch is taken
+            if time.perf_counter() - t0 > 10:
+                raise AssertionError("the big job was not launched")
+        ts = srv.submit_raw(st_.data_ptr(), st_.shape[0], 3, small[1], small[2], sl_.data_ptr(), sc_.data_ptr())
+        delta_us = (time.perf_counter() - t0) * 1e6  # bounds the gap between the two submissions
+        srv.drain()
+        rb, rs = srv.poll(tb), srv.poll(ts)
+        assert rb["status"] == 0 and rs["status"] == 0
+        assert rb["batch_jobs"] == 1 and rs["batch_jobs"] == 1, "the jobs were batched together"
+        assert srv.stats()["batches"] == 2
+        # the small job's batch started before the big job was done
+        assert rs["queue_us"] + delta_us < rb["latency_us"], (rs, rb, delta_us)
+        _say(f"[gpu] big job {rb['latency_us']:.0f} us, small job {rs['latency_us']:.0f} us "
+             f"(queued {rs['queue_us']:.0f} us), submitted {delta_us:.0f} us apart")
+        for (pts, eps, mp), lab, core, r in ((big, bl, bc, rb), (small, sl_, sc_, rs)):
+            al, ac, ak = _alone(dev, pts, eps, mp, "densebox")
+            assert r["num_clusters"] == ak
+            assert np.array_equal(lab.cpu().numpy(), al) and np.array_equal(core.cpu().numpy().astype(bool), ac)
+        ol, oc, ok = oracle.dbscan(small[0], small[1], small[2])
+        assert rs["num_clusters"] == ok and np.array_equal(sl_.cpu().numpy(), ol)
     finally:
         srv.close()
