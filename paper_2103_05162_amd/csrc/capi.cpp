@@ -59,8 +59,8 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.node_b = p.node_a + 16;
   p.rope = take(N * 4);
   p.leaf_rope = take(N * 4);
-  p.parent = take(2 * N * 4);
-  p.flags = take(N * 4);
+  p.ends = take(N * 4);
+  p.cut = take(static_cast<size_t>(kCutMax) * 32);
   p.other = take(N * 4);
   p.gamma = take(N * 4);
   p.labels = take(N * 4);
@@ -597,8 +597,7 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
   float4* nb = na + 1;
   int* rope = reinterpret_cast<int*>(p); p += M * 4;
   int* lrope = reinterpret_cast<int*>(p); p += M * 4;
-  int* parent = reinterpret_cast<int*>(p); p += 2 * M * 4;
-  int* flags = reinterpret_cast<int*>(p); p += M * 4;
+  int* ends = reinterpret_cast<int*>(p); p += M * 4;
   int* other = reinterpret_cast<int*>(p); p += M * 4;
   int* gamma = reinterpret_cast<int*>(p); p += M * 4;
   int* leaves = reinterpret_cast<int*>(p); p += M * 4;
@@ -609,7 +608,7 @@ fdb_status fdb_debug_lbvh(fdb_handle* h, const uint64_t* h_keys, int32_t m, int3
   if (st == FDB_OK) {
     fill_u32(reinterpret_cast<uint32_t*>(xs), 0, 3 * M, s);
     fill_u32(h->d_info, 0, 1, s);
-    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, na, nb, rope, lrope, parent, flags, other, gamma, nullptr,
+    build_lbvh(keys, true, m, 3, xs, m, nullptr, nullptr, na, nb, rope, lrope, ends, other, gamma, nullptr,
                h->d_info, s);
     TreeView t{na, nb, rope, lrope, m, nullptr, leaf_size};
     launch_debug_walk(t, m, mask, leaves, count, m, h->d_info, s);
@@ -840,10 +839,13 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
-               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
-               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
+               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.ends),
+               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s,
+               at<float4>(ws, plan.cut), misc + kMiscCut);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = misc + kMiscNumPrims;
+    ta.t.cut = at<float4>(ws, plan.cut);
+    ta.t.cut_n = misc + kMiscCut;
     ta.prim_start = at<int>(ws, plan.prim_start);
     ta.prim_cnt = at<int>(ws, plan.prim_cnt);
     ta.prim_lo = at<float4>(ws, plan.prim_lo);
@@ -865,10 +867,12 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     st.mark("lbvh");
     build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
-               at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
-               nullptr, h->d_info, s);
+               at<int>(ws, plan.ends), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
+               nullptr, h->d_info, s, at<float4>(ws, plan.cut), misc + kMiscCut);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = nullptr;
+    ta.t.cut = at<float4>(ws, plan.cut);
+    ta.t.cut_n = misc + kMiscCut;
   }
 
   const bool all_core = min_pts <= 2;
@@ -906,11 +910,14 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
   }
   if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, all_core ? nullptr : core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");
-  launch_finalize(lab, n, h->d_info, s);
+  // with final core flags the pass also takes each cluster's smallest input index
+  if (all_core) launch_finalize(lab, n, h->d_info, s);
+  else launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig));
   if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);
   st.mark("cluster_ids");
   canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), at<int>(ws, plan.rank),
-                at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s);
+                at<int>(ws, plan.bsums), plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, true,
+                !all_core);
   const bool have_border = !all_core && o.border == FDB_BORDER_CANONICAL;  // DBSCAN*: non-core stays noise
   if (have_border) {
     st.mark("border");
@@ -1097,7 +1104,7 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
-               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.parent), at<int>(ws, plan.flags),
+               at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.ends),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
     batch_roots(offsets, num_clouds, n, at<int>(ws, plan.cand), misc + kMiscNumPrims, at<int>(ws, plan.other),
                 cl_root, cl_end, h->d_info, s);
@@ -1113,7 +1120,7 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
     st.mark("lbvh");
     build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
-               at<int>(ws, plan.parent), at<int>(ws, plan.flags), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
+               at<int>(ws, plan.ends), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
                nullptr, h->d_info, s);
     batch_roots(offsets, num_clouds, n, nullptr, nullptr, at<int>(ws, plan.other), cl_root, cl_end, h->d_info, s);
     ta.t.d_m = nullptr;
@@ -1138,12 +1145,12 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
   }
   if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");
-  launch_finalize(lab, n, h->d_info, s);
+  launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig));  // batches run the core pass
   st.mark("cluster_ids");
   int* rank = at<int>(ws, plan.rank);
   uint32_t* lbits = at<uint32_t>(ws, plan.lflag);
   canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), lbits, rank, at<int>(ws, plan.bsums),
-                plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false);
+                plan.scan_blocks, at<int>(ws, plan.cid), misc + kMiscNumClusters, s, false, true);
   batch_cluster_ids(lab, core, at<int>(ws, plan.minorig), lbits, rank, pkeys, shift, offsets, num_clouds, n,
                     misc + kMiscNumClusters, cl_flags, at<int>(ws, plan.cid), num_clusters, s);
   if (o.border == FDB_BORDER_CANONICAL) {

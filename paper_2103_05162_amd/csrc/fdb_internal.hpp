@@ -34,7 +34,7 @@ struct Plan {
   // common
   size_t bounds, misc, gplan, keys0, keys1, vals0, vals1, hist, digoff, tilectr, status;
   size_t xs;                       // dim * n floats, sorted SoA
-  size_t node_a, node_b, rope, leaf_rope, parent, flags, other, gamma;
+  size_t node_a, node_b, rope, leaf_rope, ends, other, gamma, cut;
   size_t labels, core, lone, qborder, brec_i, brec_nb;
   int64_t brec_cap = 0;
   size_t minorig, lflag, rank, bsums, cid, border;
@@ -59,6 +59,7 @@ enum MiscSlot : int {
   kMiscNumDense = 4,     // DenseBox: dense cells
   kMiscBorderQ = 5,      // entries of the border query list (filled by the core pass)
   kMiscBorderRec = 6,    // border neighbour records asked for by the core pass
+  kMiscCut = 7,          // entries of the hierarchy's cut (TreeView::cut)
   kMiscCoreQ = 8,        // DenseBox: point primitives left for the core pass by the isolated-point test,
                          // one count per XCD segment (slots 8 .. 15)
   kMiscCount = 16
@@ -102,7 +103,20 @@ struct TreeView {
   int m_cap;       // number of primitives, or an upper bound when d_m is set
   const int* d_m;  // device-side primitive count (DenseBox), or null
   int leaf_size;   // subtrees of at most this many primitives are scanned linearly
+  // A cut through the hierarchy (single-cloud trees): the maximal subtrees of at
+  // most cut_span(m) primitives, as pairs {lo.xyz, node ref} {hi.xyz, last
+  // primitive}, *cut_n of them; a box walk over the whole tree tests these at once
+  // instead of descending from the root. Null, or a count above kCutMax: no cut.
+  const float4* cut = nullptr;
+  const int* cut_n = nullptr;
 };
+
+constexpr int kCutMax = 4096;
+constexpr int kCutDiv = 256;   // the cut holds about kCutDiv to 2 kCutDiv subtrees
+constexpr int kCutUnroll = 4;         // cut entries a lane loads at once
+__host__ __device__ inline int cut_span(int m) {
+  return (m + kCutDiv - 1) / kCutDiv > 64 ? (m + kCutDiv - 1) / kCutDiv : 64;
+}
 
 // ---- launch helpers (stream-ordered, asynchronous) --------------------------
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -160,11 +174,13 @@ int64_t planned_status_words(int64_t n);
 
 // k_tree.hip
 // prim_lo / prim_hi: DenseBox leaf records (null for FDbscan, whose leaves are
-// the sorted points); see TravArgs.
+// the sorted points); see TravArgs. ends: m words of scratch; other / gamma:
+// each internal node's other range end and split (m - 1 words each). cut / cut_n:
+// the cut of TreeView (kCutMax pairs, and a counter the caller zeroed), or null.
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
                 const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
-                int* leaf_rope, int* parent, int* flags, int* other, int* gamma, const int* d_m, uint32_t* info,
-                hipStream_t s);
+                int* leaf_rope, int* ends, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s,
+                float4* cut = nullptr, int* cut_n = nullptr);
 
 // k_dense.hip
 // sorted_keys are 64-bit words when key64 (or, with d_key64 set, when *d_key64 on
@@ -254,16 +270,20 @@ void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int*
 
 // k_label.hip
 void launch_init_labels(int* labels, int64_t n, hipStream_t s);
-void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s);
+// With minorig (core flags final): also the smallest input index (perm) of each
+// root's core points, in minorig[root] (filled here first).
+void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s, const uint8_t* core = nullptr,
+                     const uint32_t* perm = nullptr, int* minorig = nullptr);
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
 void launch_check_forest(const int* labels, const uint8_t* core, int64_t n, uint32_t* bad, uint32_t* info,
                          hipStream_t s);
 // Canonical cluster ids (ids 0..K-1 in increasing order of each cluster's
 // smallest core input index). bits: ceil(n/32) leader words followed by as many
 // ints of scratch (fits the n-int lflag array); wpre: ceil(n/32) ints.
+// minorig_ready: launch_finalize already filled minorig.
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
                    uint32_t* bits, int* wpre, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
-                   bool ids = true);
+                   bool ids = true, bool minorig_ready = false);
 
 // k_batch.hip
 void batch_prep(const float* pts, const int64_t* off, int num_clouds, int64_t n, int dim, const float* eps,

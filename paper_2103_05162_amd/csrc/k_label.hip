@@ -43,6 +43,51 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int* labels, int64_t n, uin
   }
 }
 
+// Finalisation fused with the smallest input index per cluster (for when the
+// core flags are final): lanes run the same trip count, so a wavefront whose core
+// lanes all reach one root reduces first and issues a single atomic.
+__global__ __launch_bounds__(kBlock) void k_finalize_min(int* labels, const uint8_t* __restrict__ core,
+                                                         const uint32_t* __restrict__ perm, int64_t n,
+                                                         int* __restrict__ minorig, uint32_t* __restrict__ info) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int64_t base = blockIdx.x * int64_t(kBlock) + (threadIdx.x & ~63); base < n; base += stride) {
+    const int64_t i = base + lane;
+    int r = -1;
+    bool valid = false;
+    int o = 0x7fffffff;
+    if (i < n) {
+      r = labels[i];
+      valid = core[i] != 0;
+      if (valid) o = static_cast<int>(perm[i]);
+      for (int64_t it = 0;; ++it) {
+        if (r < 0 || r >= n || it > n) {
+          atomicOr(info, kInternalBit);
+          r = static_cast<int>(i);
+          break;
+        }
+        const int q = labels[r];
+        if (q == r) break;
+        r = q;
+      }
+      labels[i] = r;
+    }
+    const uint64_t vm = ballot(valid);
+    if (vm == 0) continue;
+    const int leader = __ffsll(static_cast<unsigned long long>(vm)) - 1;
+    const int r0 = __shfl(r, leader);
+    if (ballot(valid && r != r0) == 0) {
+      for (int off = 32; off > 0; off >>= 1) {
+        const int y = __shfl_xor(o, off);
+        o = y < o ? y : o;
+      }
+      if (lane == leader) atomicMin(minorig + r0, o);
+    } else if (valid) {
+      atomicMin(minorig + r, o);
+    }
+  }
+}
+
 // Debug check of the union-find forest the fused main phase leaves (before
 // finalisation). Unions hook the larger root under the smaller one and finds only
 // shorten paths, so a core point's parent is a core point with a smaller index;
@@ -330,8 +375,14 @@ void launch_init_labels(int* labels, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n);
 }
 
-void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, info);
+void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s, const uint8_t* core, const uint32_t* perm,
+                     int* minorig) {
+  if (minorig) {
+    fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
+    hipLaunchKernelGGL(k_finalize_min, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, n, minorig, info);
+  } else {
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, info);
+  }
 }
 
 void launch_check_forest(const int* labels, const uint8_t* core, int64_t n, uint32_t* bad, uint32_t* info,
@@ -351,13 +402,15 @@ void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_
 
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
                    uint32_t* bits, int* wpre, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
-                   bool ids) {
+                   bool ids, bool minorig_ready) {
   const int g = grid_for(n);
   const int64_t words = ceil_div(n, 32);
   int* cnt = reinterpret_cast<int*>(bits + words);
-  fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
   fill_u32(bits, 0, words, s);
-  hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
+  if (!minorig_ready) {
+    fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
+    hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
+  }
   hipLaunchKernelGGL(k_leader_bits, dim3(g), dim3(kBlock), 0, s, labels, core, minorig, n, bits);
   hipLaunchKernelGGL(k_word_popc, dim3(grid_for(words)), dim3(kBlock), 0, s, bits, words, cnt);
   device_scan(cnt, wpre, words, nullptr, bsums, scan_blocks, d_k, s);

@@ -220,8 +220,37 @@ __device__ __forceinline__ void traverse_box_wide(const TreeView& t, int m, cons
                                                   uint32_t* stack, F&& visit) {
   if (m <= 0 || mask >= sc.end) return;
   const int lane = lane_id();
-  if (lane == 0) stack[0] = sc.start;
-  int top = 1;
+  int top = 0;
+  // a walk over the whole tree starts from the cut: its boxes are tested 64 at a
+  // time and the ones within reach pushed, instead of descending from the root
+  const int nc = t.cut && sc.start == 0 && sc.end == m - 1 ? *t.cut_n : 0;
+  if (nc > 0 && nc <= kCutMax) {
+    for (int b = 0; b < nc && top >= 0; b += 64 * kCutUnroll) {
+      float4 ca[kCutUnroll], cb[kCutUnroll];
+#pragma unroll
+      for (int u = 0; u < kCutUnroll; ++u) {  // the loads of kCutUnroll chunks in flight together
+        const int c = min(b + u * 64 + lane, nc - 1);
+        ca[u] = t.cut[2 * c];
+        cb[u] = t.cut[2 * c + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kCutUnroll; ++u) {
+        const bool hit = b + u * 64 + lane < nc && __float_as_int(cb[u].w) > mask &&
+                         boxbox_dist2<D>(lo, hi, ca[u].x, ca[u].y, ca[u].z, cb[u].x, cb[u].y, cb[u].z) <= sc.eps2;
+        const uint64_t hm = ballot(hit);
+        if (top < 0 || top + __popcll(hm) > kWideStack) {
+          top = -1;  // more than the stack holds: start from the root instead
+        } else {
+          if (hit) stack[top + __popcll(hm & lanemask_lt())] = __float_as_uint(ca[u].w);
+          top += __popcll(hm);
+        }
+      }
+    }
+  }
+  if (nc <= 0 || nc > kCutMax || top < 0) {
+    if (lane == 0) stack[0] = sc.start;
+    top = 1;
+  }
   int64_t guard = 0;
   const int64_t max_rounds = 2 * int64_t(m) + 2;
   while (top > 0) {
@@ -309,8 +338,37 @@ __device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m
       if (visit_lanes(b + lane <= e ? b + lane : -1)) return true;
     return false;
   };
-  if (lane == 0) stack[0] = sc.start;
-  int top = 1;
+  int top = 0;
+  // a walk over the whole tree starts from the cut: its boxes are tested 64 at a
+  // time and the ones within reach pushed, instead of descending from the root
+  const int nc = t.cut && sc.start == 0 && sc.end == m - 1 ? *t.cut_n : 0;
+  if (nc > 0 && nc <= kCutMax) {
+    for (int b = 0; b < nc && top >= 0; b += 64 * kCutUnroll) {
+      float4 ca[kCutUnroll], cb[kCutUnroll];
+#pragma unroll
+      for (int u = 0; u < kCutUnroll; ++u) {  // the loads of kCutUnroll chunks in flight together
+        const int c = min(b + u * 64 + lane, nc - 1);
+        ca[u] = t.cut[2 * c];
+        cb[u] = t.cut[2 * c + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < kCutUnroll; ++u) {
+        const bool hit = b + u * 64 + lane < nc && __float_as_int(cb[u].w) > mask &&
+                         boxbox_dist2<D>(lo, hi, ca[u].x, ca[u].y, ca[u].z, cb[u].x, cb[u].y, cb[u].z) <= sc.eps2;
+        const uint64_t hm = ballot(hit);
+        if (top < 0 || top + __popcll(hm) > kWideStack) {
+          top = -1;  // more than the stack holds: start from the root instead
+        } else {
+          if (hit) stack[top + __popcll(hm & lanemask_lt())] = __float_as_uint(ca[u].w);
+          top += __popcll(hm);
+        }
+      }
+    }
+  }
+  if (nc <= 0 || nc > kCutMax || top < 0) {
+    if (lane == 0) stack[0] = sc.start;
+    top = 1;
+  }
   int64_t guard = 0;
   const int64_t max_rounds = 2 * int64_t(m) + 2;
   while (top > 0) {
@@ -1201,10 +1259,8 @@ __device__ __forceinline__ uint32_t spread_every(uint32_t x, int d) {  // Morton
 // true) is within eps (1 + 2^-22) per axis; its cell's gap vector is bounded by
 // |t_j - t| per axis, whose norm the slack covers, so its cell is within reach.
 // Conservative: a false answer only means "walk it". Reach is below 2, so the
-// reachable cells lie within 2 per axis: at most 2^d brick words per query.
-__device__ __forceinline__ bool brick_marked(const uint32_t* __restrict__ table, uint32_t b) {
-  return (table[b >> 5] >> (b & 31)) & 1u;
-}
+// reachable cells lie within 2 per axis: at most 2^d brick words per query, each
+// current only when its bit in the table is set.
 
 // Bits of a brick whose coordinate on axis a lies in [l, h] (local, l <= h).
 template <int D>
@@ -1228,9 +1284,16 @@ template <int D>
 __device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int m, int p, float4 pt,
                                          const GridPlan& g, const float* lo_b, const uint64_t* __restrict__ words,
                                          const uint32_t* __restrict__ table) {
+  // Straight-line on purpose: the three keys are loaded together, then every
+  // brick's table bit and word together (a word of an unmarked brick is stale
+  // and discarded), so a query waits for two memory round trips, not one per
+  // brick. Bricks outside the grid load brick 0 and are masked out.
   const uint32_t key = key32(pkey, p);
-  if ((p > 0 && key32(pkey, p - 1) == key) || (p + 1 < m && key32(pkey, p + 1) == key)) return false;
+  const uint32_t kprev = key32(pkey, p > 0 ? p - 1 : p);
+  const uint32_t knext = key32(pkey, p + 1 < m ? p + 1 : p);
+  const bool shared = (p > 0 && kprev == key) || (p + 1 < m && knext == key);
   constexpr int S = kBrickShift<D>, W = 1 << S;
+  constexpr int NB = D == 3 ? 8 : 4;  // bricks that can hold cells within 2 per axis
   const float xv[3] = {pt.x, pt.y, pt.z};
   float t[3] = {0.0f, 0.0f, 0.0f};
   int c[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -1241,43 +1304,55 @@ __device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int 
     lo[a] = c[a] >= 2 ? c[a] - 2 : 0;
     hi[a] = min(c[a] + 2, static_cast<int>(g.ncell[a]) - 1);
   }
-  const float r2 = g.reach * g.reach;
+  uint32_t bidx[NB];
+  uint64_t bbox[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    const int br[3] = {(lo[0] >> S) + (n >> (D - 1)), (lo[1] >> S) + ((n >> (D - 2)) & 1), (lo[2] >> S) + (n & 1)};
+    bool use = br[0] <= (hi[0] >> S) && br[1] <= (hi[1] >> S);
+    if (D == 3) use = use && br[2] <= (hi[2] >> S);
+    uint32_t b = 0;
+    uint64_t box = ~0ull;  // the brick's cells within 2 per axis
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int base = br[a] << S;
+      box &= axis_bits<D>(a, max(lo[a], base) - base, min(hi[a], base + W - 1) - base);
+      b |= spread_every(static_cast<uint32_t>(br[a]), D) << (D - 1 - a);
+    }
+    bidx[n] = use ? b : 0u;
+    bbox[n] = use ? box : 0ull;
+  }
+  uint32_t tw[NB];
+  uint64_t ww[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    tw[n] = table[bidx[n] >> 5];
+    ww[n] = words[bidx[n]];
+  }
   const uint32_t own_brick = key >> 6;
   const int own_bit = brick_bit<D>(key);
+  const float r2 = g.reach * g.reach;
+  bool near = shared;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int k = 0; k < (D == 3 ? 2 : 1); ++k) {
-        const int br[3] = {(lo[0] >> S) + i, (lo[1] >> S) + j, (lo[2] >> S) + k};
-        bool use = br[0] <= (hi[0] >> S) && br[1] <= (hi[1] >> S);
-        if (D == 3) use = use && br[2] <= (hi[2] >> S);
-        if (!use) continue;
-        uint32_t b = 0;
-        uint64_t box = ~0ull;  // the brick's cells within 2 per axis
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const int base = br[a] << S;
-          box &= axis_bits<D>(a, max(lo[a], base) - base, min(hi[a], base + W - 1) - base);
-          b |= spread_every(static_cast<uint32_t>(br[a]), D) << (D - 1 - a);
-        }
-        if (!brick_marked(table, b)) continue;
-        uint64_t occ = words[b] & box;
-        if (b == own_brick) occ &= ~(1ull << own_bit);
-        // the occupied cells among them (usually none, or a few): exact reach test
-        for (; occ; occ &= occ - 1) {
-          const int bit = __ffsll(static_cast<unsigned long long>(occ)) - 1;
-          const int lx = D == 3 ? bit >> 4 : bit >> 3;
-          const int ly = D == 3 ? (bit >> 2) & 3 : bit & 7;
-          const int lz = D == 3 ? bit & 3 : 0;
-          const float gx = cell_gap(t[0], c[0], (br[0] << S) + lx);
-          const float gy = cell_gap(t[1], c[1], (br[1] << S) + ly);
-          const float gz = D == 3 ? cell_gap(t[2], c[2], (br[2] << S) + lz) : 0.0f;
-          if (gx * gx + gy * gy + gz * gz <= r2) return false;
-        }
-      }
-  return true;
+  for (int n = 0; n < NB; ++n) {
+    uint64_t occ = (tw[n] >> (bidx[n] & 31)) & 1u ? ww[n] & bbox[n] : 0ull;
+    if (bidx[n] == own_brick) occ &= ~(1ull << own_bit);
+    // the occupied cells among them (usually none, or a few): exact reach test
+    const int bx = static_cast<int>(compact_every(bidx[n] >> (D - 1), D)) << S;
+    const int by = static_cast<int>(compact_every(bidx[n] >> (D - 2), D)) << S;
+    const int bz = D == 3 ? static_cast<int>(compact_every(bidx[n], D)) << S : 0;
+    for (; occ && !near; occ &= occ - 1) {
+      const int bit = __ffsll(static_cast<unsigned long long>(occ)) - 1;
+      const int lx = D == 3 ? bit >> 4 : bit >> 3;
+      const int ly = D == 3 ? (bit >> 2) & 3 : bit & 7;
+      const int lz = D == 3 ? bit & 3 : 0;
+      const float gx = cell_gap(t[0], c[0], bx + lx);
+      const float gy = cell_gap(t[1], c[1], by + ly);
+      const float gz = D == 3 ? cell_gap(t[2], c[2], bz + lz) : 0.0f;
+      near = gx * gx + gy * gy + gz * gz <= r2;
+    }
+  }
+  return !near;
 }
 
 // A workgroup tests kLoneRounds x 256 consecutive primitives and lists the ones
@@ -1288,7 +1363,7 @@ __device__ __forceinline__ bool isolated(const uint64_t* __restrict__ pkey, int 
 // never passes its own primitive range, so the list needs m entries. The core pass
 // gives segment s to the workgroups of XCD s: each XCD walks one contiguous range
 // of the curve, as it does without the test.
-constexpr int kLoneRounds = 8;
+constexpr int kLoneRounds = 4;
 
 __device__ __forceinline__ int64_t lone_segment(int m) {
   const int64_t share = kLoneRounds * 256;
@@ -1320,12 +1395,12 @@ __global__ __launch_bounds__(256) void k_lone_filter(TravArgs a, const uint64_t*
     bool query = false, lone = false;
     int i = 0;
     if (p < m) {
+      // the test's loads do not wait for the record (a dense cell's answer is discarded)
       const float4 lr = a.prim_lo[p];
+      const bool iso = isolated<D>(pkey, m, static_cast<int>(p), lr, gp, lo_b, words, table);
       i = rec_index(lr);
-      if (i >= 0) {
-        query = true;
-        lone = isolated<D>(pkey, m, static_cast<int>(p), lr, gp, lo_b, words, table);
-      }
+      query = i >= 0;
+      lone = query && iso;
     }
     if (lone) {
       a.core[i] = 0;
@@ -1395,6 +1470,9 @@ __global__ void k_core_dbx(TravArgs a) {
     sc[t] = scope_of<B>(a, m, i[t]);
     cnt[t] = 0;
     rec_init(rec[t], s_rec + t * kRecNb * blockDim.x);
+  }
+#pragma unroll
+  for (int t = 0; t < kCoreQ; ++t) {
     walk_init<false>(w[t], m, sc[t], 0, mine[t]);
     active[t] = mine[t] && !walk_done(w[t]);
   }

@@ -1,8 +1,11 @@
 // Linear BVH over m primitives sorted by Morton key (Section 4.1 uses an LBVH
-// in the manner of Karras 2012): one thread per internal node finds its leaf
-// range and split from the longest common prefix of neighbouring keys (equal
-// keys compare by index), a second pass writes the escape links ("ropes") for
-// stack-less traversal, and a bottom-up pass computes exact min/max boxes.
+// in the manner of Karras 2012). The hierarchy is Karras' binary radix tree over
+// the keys (equal keys compare by index), numbered as Karras numbers it, but it is
+// built bottom-up in the same pass that computes the exact min/max boxes (the
+// agglomerative order of Apetrei 2014): every leaf climbs, a node merges with the
+// neighbour across its more similar edge, and the second of two arrivers at a
+// split carries the merged node on. A second pass writes the escape links
+// ("ropes") for stack-less traversal.
 #include "fdb_device.hpp"
 #include "fdb_internal.hpp"
 
@@ -23,43 +26,6 @@ __device__ __forceinline__ int prefix_len(const K* __restrict__ keys, int m, int
     return __clzll(static_cast<unsigned long long>(a ^ b));
   else
     return __clz(static_cast<uint32_t>(a ^ b));
-}
-
-// Internal node i: its range is [min(i,j), max(i,j)] and its split gamma
-// separates [first, gamma] from [gamma+1, last]. Children are internal node
-// gamma / gamma+1, or leaves when their side holds one primitive.
-template <typename K>
-__global__ __launch_bounds__(kBlock) void k_karras(const K* __restrict__ keys, int m_cap, const int* __restrict__ d_m,
-                                                   int* __restrict__ other, int* __restrict__ gamma_out,
-                                                   int* __restrict__ parent, int* __restrict__ flags) {
-  const int m = d_m ? *d_m : m_cap;
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= m - 1) return;
-  int dl = prefix_len(keys, m, i, int64_t(i) - 1);
-  int dr = prefix_len(keys, m, i, int64_t(i) + 1);
-  int d = dr > dl ? 1 : -1;
-  int dmin = dr > dl ? dl : dr;
-  int64_t lmax = 2;
-  while (prefix_len(keys, m, i, i + lmax * d) > dmin) lmax <<= 1;
-  int64_t l = 0;
-  for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
-    if (prefix_len(keys, m, i, i + (l + t) * d) > dmin) l += t;
-  int64_t j = i + l * d;
-  int dnode = prefix_len(keys, m, i, j);
-  int64_t s = 0, t = l;
-  do {
-    t = (t + 1) >> 1;
-    if (prefix_len(keys, m, i, i + (s + t) * d) > dnode) s += t;
-  } while (t > 1);
-  int g = static_cast<int>(i + s * d + (d < 0 ? -1 : 0));
-  int first = static_cast<int>(d > 0 ? i : j), last = static_cast<int>(d > 0 ? j : i);
-  other[i] = static_cast<int>(j);
-  gamma_out[i] = g;
-  flags[i] = 0;  // the refit's arrival counter of node i
-  // parent[] holds internal nodes at [0, m-1) and leaf l at m-1+l
-  parent[first == g ? (m - 1) + g : g] = i;
-  parent[last == g + 1 ? (m - 1) + g + 1 : g + 1] = i;
-  if (i == 0) parent[0] = -1;
 }
 
 // Pre-order successor of a subtree whose last leaf is l: the right child of the
@@ -174,59 +140,109 @@ __device__ __forceinline__ Box load_node_buf(__amdgpu_buffer_rsrc_t r, int k) {
   return b;
 }
 
-// Bottom-up refit: each leaf walks towards the root; at every internal node the
-// second of the two arriving threads merges its box with the sibling's and
-// continues upwards, so every box is the exact min/max of its leaves. A node
-// whose leaves all belong to this workgroup's kRefitBlock (its index then lies among
-// them too) is met in LDS: each arriver leaves its box in the slot of its side
-// and counts itself with a workgroup-scope atomic. Only nodes spanning
-// workgroups take the device-scope protocol, so most arrivals never leave the CU.
-constexpr int kRefitBlock = 256;  // leaves per workgroup of the refit
+// Bottom-up build and refit. Node [i, j] (i < j) of Karras' tree has the split
+// where the common prefix of neighbouring keys is shortest inside it; its parent
+// adds the neighbour across the edge (i-1 | i or j | j+1) with the longer common
+// prefix, and that edge is the parent's split. Karras' numbering follows: a left
+// child [i, s] is node s, a right child [s+1, j] is node s+1, and the root is 0.
+// Each leaf climbs: at split s the two children meet, the second arriver learns
+// the other's far end and box, writes the parent (range end, split, box) at the
+// parent's own index once it knows on which side the parent hangs, and goes on.
+//
+// A meeting whose parent lies within this workgroup's kRefitBlock leaves is held
+// in LDS (box in the slot of the arriver's side, far end by an atomic exchange).
+// Both arrivers decide that alike from the prefix lengths of the workgroup's
+// leaves: a left child [i, s] inside the workgroup has its sibling end inside it
+// exactly when some edge in (s, L1] is less similar than s, which a suffix
+// minimum over the workgroup's edges answers; a right child likewise with a
+// prefix minimum. Other meetings exchange the far end through ends[s] (cleared
+// to -1 beforehand) with one device-scope atomic exchange, after the first
+// arriver's node stores have drained; node records are written and read with
+// agent-scope (L2-bypassing) accesses, since the sibling may run on another XCD.
+constexpr int kRefitBlock = 256;  // leaves per workgroup of the build
 
-template <int D, bool BUF>
-__global__ __launch_bounds__(kRefitBlock) void k_refit(int m_cap, const int* __restrict__ d_m, const float* __restrict__ xs,
-                                                  int64_t n,
-                                                  LeafSrc ls, const int* __restrict__ other, const int* __restrict__ gamma,
-                                                  const int* __restrict__ parent, int* __restrict__ flags,
-                                                  float4* node_a, float4* node_b, uint32_t* __restrict__ info) {
-  __shared__ int s_arrive[kRefitBlock];
-  __shared__ float s_side[2][6][kRefitBlock];  // [child side][lo.xyz, hi.xyz][node - first leaf]
+// Common-prefix length of edge k (keys k and k+1); -1 for the edges before the
+// first and after the last key, which are less similar than every inner edge.
+template <typename K>
+__device__ __forceinline__ int edge_len(const K* __restrict__ keys, int m, int64_t k) {
+  return k < 0 || k >= m - 1 ? -1 : prefix_len(keys, m, static_cast<int>(k), k + 1);
+}
+
+__device__ __forceinline__ void cut_add(float4* cut, int* cut_n, uint32_t ref, int last, const Box& b) {
+  const int k = atomicAdd(cut_n, 1);
+  if (k >= kCutMax) return;  // too many: the walks then ignore the cut
+  cut[2 * k] = make_float4(b.lo[0], b.lo[1], b.lo[2], __uint_as_float(ref));
+  cut[2 * k + 1] = make_float4(b.hi[0], b.hi[1], b.hi[2], __int_as_float(last));
+}
+
+template <typename K, int D, bool BUF>
+__global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ keys, int m_cap,
+                                                     const int* __restrict__ d_m, const float* __restrict__ xs,
+                                                     int64_t n, LeafSrc ls, int* __restrict__ other,
+                                                     int* __restrict__ gamma, int* __restrict__ ends, float4* node_a,
+                                                     float4* node_b, uint32_t* __restrict__ info,
+                                                     float4* __restrict__ cut, int* __restrict__ cut_n) {
+  constexpr int E = kRefitBlock + 1;  // edges L0-1 .. L0+255
+  __shared__ int s_far[kRefitBlock];
+  __shared__ float s_side[2][6][kRefitBlock];  // [child side][lo.xyz, hi.xyz][split - L0]
+  __shared__ int s_pmin[E], s_smin[E], s_len[E];
   const int m = d_m ? *d_m : m_cap;
   const int L0 = blockIdx.x * kRefitBlock;
   if (m < 2 || L0 >= m) return;  // whole workgroup
-  s_arrive[threadIdx.x] = 0;
-  __syncthreads();
   const int L1 = min(L0 + kRefitBlock, m) - 1;  // this workgroup's leaves are [L0, L1]
-  const int l = L0 + static_cast<int>(threadIdx.x);
+  const int t = threadIdx.x;
+  const int ne = L1 - L0 + 2;  // edges L0-1 .. L1, entry e is edge L0-1+e
+  s_far[t] = -1;
+  for (int e = t; e < ne; e += kRefitBlock) s_len[e] = s_pmin[e] = s_smin[e] = edge_len(keys, m, int64_t(L0) - 1 + e);
+  __syncthreads();
+  for (int off = 1; off < ne; off <<= 1) {  // prefix and suffix minima of the edge lengths
+    int a[2], b[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = t + r * kRefitBlock;
+      a[r] = e < ne && e >= off ? s_pmin[e - off] : 0x7fffffff;
+      b[r] = e + off < ne ? s_smin[e + off] : 0x7fffffff;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = t + r * kRefitBlock;
+      if (e < ne) {
+        s_pmin[e] = min(s_pmin[e], a[r]);
+        s_smin[e] = min(s_smin[e], b[r]);
+      }
+    }
+    __syncthreads();
+  }
+  const int l = L0 + t;
   if (l >= m) return;
   const __amdgpu_buffer_rsrc_t rb =
       __builtin_amdgcn_make_buffer_rsrc(node_a, 0, BUF ? m_cap * (16 * kNodeStride) : 0, kBufferWord3);
+  auto len = [&](int64_t k) -> int {
+    return k >= L0 - 1 && k <= L1 ? s_len[k - (L0 - 1)] : edge_len(keys, m, k);
+  };
   Box box = leaf_box<D>(l, xs, n, ls);
-  int prev = l;
-  bool prev_leaf = true;
-  int p = parent[(m - 1) + l];
-  while (p >= 0) {
-    if (p >= m - 1) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    const int o = other[p], g = gamma[p];
-    const int first = o < p ? o : p, last = o > p ? o : p;
-    if (first < 0 || last >= m || g < first || g >= last) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    const bool left_leaf = first == g, right_leaf = last == g + 1;
-    const bool came_left = prev == g && prev_leaf == left_leaf;
+  int i = l, j = l;
+  int dl = len(i - 1), dr = len(j);
+  for (int level = 0; level < m; ++level) {
+    if (i == 0 && j == m - 1) return;  // the root, written when it was made
+    const bool left = dr > dl;          // this node is its parent's left child
+    const int sp = left ? j : i - 1;    // the parent's split
+    const bool inside = i >= L0 && j <= L1 &&
+                        (left ? sp + 1 <= L1 && s_smin[sp + 1 - (L0 - 1)] < dr
+                              : sp >= L0 && s_pmin[sp - 1 - (L0 - 1)] < dl);
+    const int mine = left ? i : j;  // this node's far end, seen from the split
+    int far;
     Box sib;
-    if (first >= L0 && last <= L1) {
-      const int slot = p - L0, side = came_left ? 0 : 1;
+    if (inside) {
+      const int slot = sp - L0, side = left ? 0 : 1;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         s_side[side][k][slot] = box.lo[k];
         s_side[side][3 + k][slot] = box.hi[k];
       }
-      if (__hip_atomic_fetch_add(&s_arrive[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) return;
+      far = __hip_atomic_exchange(&s_far[slot], mine, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (far < 0) return;  // first arriver
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         sib.lo[k] = s_side[side ^ 1][k][slot];
@@ -234,69 +250,97 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit(int m_cap, const int* __r
       }
     } else {
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's node stores have landed
-      if (atomicAdd(flags + p, 1) == 0) return;
-      if (came_left)
-        sib = right_leaf ? leaf_box<D>(g + 1, xs, n, ls)
-                         : (BUF ? load_node_buf(rb, g + 1) : load_node(node_a, node_b, g + 1));
-      else
-        sib = left_leaf ? leaf_box<D>(g, xs, n, ls) : (BUF ? load_node_buf(rb, g) : load_node(node_a, node_b, g));
+      far = atomicExch(ends + sp, mine);
+      if (far < 0) return;  // first arriver
+      // the sibling: [sp+1, far] (right) or [far, sp] (left); a leaf when it is one key
+      const int sl = left ? sp + 1 : sp;
+      if (far < 0 || far >= m || (left ? far < sl : far > sl)) {
+        atomicOr(info, kInternalBit);
+        return;
+      }
+      if (far == sl) sib = leaf_box<D>(sl, xs, n, ls);
+      else sib = BUF ? load_node_buf(rb, sl) : load_node(node_a, node_b, sl);
     }
+    const Box own = box;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       box.lo[k] = fminf(box.lo[k], sib.lo[k]);
       box.hi[k] = fmaxf(box.hi[k], sib.hi[k]);
     }
+    if (cut) {
+      // a child of at most span primitives under a larger parent is a cut node
+      const int a0 = left ? i : far, a1 = sp, b0 = sp + 1, b1 = left ? far : j;
+      const int span = cut_span(m);
+      if (b1 - a0 + 1 > span) {
+        if (a1 - a0 + 1 <= span)
+          cut_add(cut, cut_n, a0 == a1 ? (kLeaf | static_cast<uint32_t>(a1)) : static_cast<uint32_t>(a1), a1,
+                  left ? own : sib);
+        if (b1 - b0 + 1 <= span)
+          cut_add(cut, cut_n, b0 == b1 ? (kLeaf | static_cast<uint32_t>(b0)) : static_cast<uint32_t>(b0), b1,
+                  left ? sib : own);
+      }
+    }
+    // the merged node keeps one edge and takes the sibling's far edge
+    if (left) {
+      j = far;
+      dr = len(j);
+    } else {
+      i = far;
+      dl = len(i - 1);
+    }
+    // the new node's index: its own parent side decides it
+    const int p = i == 0 && j == m - 1 ? 0 : (dr > dl ? j : i);
+    const int o = p == i ? j : i;
     if (BUF)
-      store_node_buf(rb, p, box, o, g);
+      store_node_buf(rb, p, box, o, sp);
     else
-      store_node(node_a, node_b, p, box, o, g);
-    prev = p;
-    prev_leaf = false;
-    p = parent[p];
+      store_node(node_a, node_b, p, box, o, sp);
+    other[p] = o;
+    gamma[p] = sp;
   }
+  atomicOr(info, kInternalBit);  // more levels than keys: the keys changed under the build
 }
 
 // m_cap: number of primitives, or an upper bound when d_m (device) holds it.
+// ends: m_cap words, the far-end exchange of meetings across workgroups.
 template <typename K>
 void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs, int64_t n_pts,
-             const LeafSrc& ls, float4* node_a, float4* node_b, int* rope,
-             int* leaf_rope, int* parent, int* flags, int* other, int* gamma, uint32_t* info, hipStream_t s) {
+             const LeafSrc& ls, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends, int* other,
+             int* gamma, uint32_t* info, hipStream_t s, float4* cut, int* cut_n) {
   if (m_cap <= 0) return;
   int g = static_cast<int>(ceil_div(m_cap, kBlock));
   if (m_cap >= 2) {
-    hipLaunchKernelGGL(k_karras<K>, dim3(g), dim3(kBlock), 0, s, keys, m_cap, d_m, other, gamma, parent, flags);
-  }
-  hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
-  if (m_cap >= 2) {
+    fill_u32(reinterpret_cast<uint32_t*>(ends), 0xffffffffu, m_cap, s);
     const bool buf = m_cap <= kRefitBufMaxNodes;
     const dim3 rg(static_cast<unsigned>(ceil_div(m_cap, kRefitBlock))), rb(kRefitBlock);
     if (dim == 3 && buf)
-      hipLaunchKernelGGL((k_refit<3, true>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
-                         node_a, node_b, info);
+      hipLaunchKernelGGL((k_build_up<K, 3, true>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
+                         node_a, node_b, info, cut, cut_n);
     else if (dim == 3)
-      hipLaunchKernelGGL((k_refit<3, false>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
-                         node_a, node_b, info);
+      hipLaunchKernelGGL((k_build_up<K, 3, false>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
+                         node_a, node_b, info, cut, cut_n);
     else if (buf)
-      hipLaunchKernelGGL((k_refit<2, true>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
-                         node_a, node_b, info);
+      hipLaunchKernelGGL((k_build_up<K, 2, true>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
+                         node_a, node_b, info, cut, cut_n);
     else
-      hipLaunchKernelGGL((k_refit<2, false>), rg, rb, 0, s, m_cap, d_m, xs, n_pts, ls, other, gamma, parent, flags,
-                         node_a, node_b, info);
+      hipLaunchKernelGGL((k_build_up<K, 2, false>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
+                         node_a, node_b, info, cut, cut_n);
   }
+  hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
 }
 
 }  // namespace
 
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
-                const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* parent,
-                int* flags, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s) {
+                const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends,
+                int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s, float4* cut, int* cut_n) {
   const LeafSrc ls{prim_lo, prim_hi};
   if (key64)
-    build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, parent,
-            flags, other, gamma, info, s);
+    build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
+            other, gamma, info, s, cut, cut_n);
   else
-    build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, parent,
-            flags, other, gamma, info, s);
+    build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
+            other, gamma, info, s, cut, cut_n);
 }
 
 }  // namespace fdb

@@ -44,3 +44,58 @@ def test_masked_walk_reaches_exactly_the_leaves_above_the_mask(h, seed):
         for mask in sorted({-1, 0, m // 3, m - 2, m - 1, int(rng.integers(0, m))}):
             _, _, leaves = h.debug_lbvh(keys, mask=mask, leaf_size=leaf)
             assert leaves.tolist() == list(range(mask + 1, m)), (m, bits, leaf, mask)
+
+
+def _prefix(keys, m, i, j):
+    # common-prefix length of sorted keys i and j (64-bit), equal keys told apart by index
+    if j < 0 or j >= m:
+        return -1
+    a, b = int(keys[i]), int(keys[j])
+    if a == b:
+        return 64 + 32 - (i ^ j).bit_length()
+    return 64 - (a ^ b).bit_length()
+
+
+def _karras_top_down(keys):
+    """Karras' rule for internal node i (range direction, extent by doubling and
+    binary search, split by binary search), written out from the definition."""
+    m = len(keys)
+    other, gamma = [], []
+    for i in range(m - 1):
+        dl, dr = _prefix(keys, m, i, i - 1), _prefix(keys, m, i, i + 1)
+        d = 1 if dr > dl else -1
+        dmin = min(dl, dr)
+        lmax = 2
+        while _prefix(keys, m, i, i + lmax * d) > dmin:
+            lmax *= 2
+        l, t = 0, lmax // 2
+        while t >= 1:
+            if _prefix(keys, m, i, i + (l + t) * d) > dmin:
+                l += t
+            t //= 2
+        j = i + l * d
+        dnode = _prefix(keys, m, i, j)
+        s, t = 0, l
+        while True:
+            t = (t + 1) // 2
+            if _prefix(keys, m, i, i + (s + t) * d) > dnode:
+                s += t
+            if t <= 1:
+                break
+        other.append(j)
+        gamma.append(i + s * d + (-1 if d < 0 else 0))
+    return other, gamma
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_hierarchy_equals_karras_top_down(h, seed):
+    """The bottom-up build gives Karras' tree and numbering exactly, across many
+    256-leaf workgroups, with duplicate keys and with few distinct keys."""
+    rng = np.random.default_rng(100 + seed)
+    m = int(rng.integers(2, 6000)) if seed < 6 else (257 if seed == 6 else 4096)
+    bits = int(rng.integers(1, 48))
+    keys = np.sort(rng.integers(0, 2 ** bits, size=m, dtype=np.uint64))
+    gamma, other, _ = h.debug_lbvh(keys, mask=-1)
+    o_ref, g_ref = _karras_top_down(keys.tolist())
+    assert np.asarray(other).tolist() == o_ref
+    assert np.asarray(gamma).tolist() == g_ref
