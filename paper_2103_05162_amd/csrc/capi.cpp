@@ -832,7 +832,8 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
                    at<float4>(ws, plan.cell_lo), at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt),
                    at<float4>(ws, plan.prim_lo), at<float4>(ws, plan.prim_hi), at<uint64_t>(ws, plan.prim_key),
-                   at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s);
+                   at<int>(ws, plan.dense_list), lab, core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, 0,
+                   nullptr, nullptr, at<int>(ws, plan.ends), at<int>(ws, plan.minorig));
   }
   h->last_densebox = densebox;
   if (densebox) {
@@ -841,7 +842,7 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.ends),
                at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s,
-               at<float4>(ws, plan.cut), misc + kMiscCut);
+               at<float4>(ws, plan.cut), misc + kMiscCut, true);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = misc + kMiscNumPrims;
     ta.t.cut = at<float4>(ws, plan.cut);
@@ -863,12 +864,12 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     perm = vals[cur];
     st.mark("permute");
     launch_permute(points, n, dim, perm, xs, h->d_info, s);
-    launch_init_labels(lab, n, s);
+    launch_init_labels(lab, n, s, at<int>(ws, plan.ends), at<int>(ws, plan.minorig));
     st.mark("lbvh");
     build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.ends), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
-               nullptr, h->d_info, s, at<float4>(ws, plan.cut), misc + kMiscCut);
+               nullptr, h->d_info, s, at<float4>(ws, plan.cut), misc + kMiscCut, true);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = nullptr;
     ta.t.cut = at<float4>(ws, plan.cut);
@@ -912,7 +913,7 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
   st.mark("finalize");
   // with final core flags the pass also takes each cluster's smallest input index
   if (all_core) launch_finalize(lab, n, h->d_info, s);
-  else launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig));
+  else launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), false);
   if (all_core) launch_core_from_sets(lab, core, n, min_pts, s);
   st.mark("cluster_ids");
   canonical_ids(lab, core, perm, n, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), at<int>(ws, plan.rank),
@@ -1100,12 +1101,14 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
                    at<float4>(ws, plan.cell_hi), at<int>(ws, plan.pflag),
                    at<int>(ws, plan.prim_start), at<int>(ws, plan.prim_cnt), at<float4>(ws, plan.prim_lo),
                    at<float4>(ws, plan.prim_hi), at<uint64_t>(ws, plan.prim_key), at<int>(ws, plan.dense_list), lab,
-                   core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2);
+                   core, misc, at<int>(ws, plan.bsums), plan.scan_blocks, s, shift, cl_minpts, cl_eps2,
+                   at<int>(ws, plan.ends), at<int>(ws, plan.minorig));
     st.mark("lbvh");
     build_lbvh(at<void>(ws, plan.prim_key), true, static_cast<int>(n), dim, xs, n, at<float4>(ws, plan.prim_lo),
                at<float4>(ws, plan.prim_hi), at<float4>(ws, plan.node_a), at<float4>(ws, plan.node_b),
                at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope), at<int>(ws, plan.ends),
-               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s);
+               at<int>(ws, plan.other), at<int>(ws, plan.gamma), misc + kMiscNumPrims, h->d_info, s, nullptr,
+               nullptr, true);
     batch_roots(offsets, num_clouds, n, at<int>(ws, plan.cand), misc + kMiscNumPrims, at<int>(ws, plan.other),
                 cl_root, cl_end, h->d_info, s);
     ta.t.d_m = misc + kMiscNumPrims;
@@ -1116,12 +1119,12 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
     ta.dense_list = at<int>(ws, plan.dense_list);
     ta.d_ndense = misc + kMiscNumDense;
   } else {
-    launch_init_labels(lab, n, s);
+    launch_init_labels(lab, n, s, at<int>(ws, plan.ends), at<int>(ws, plan.minorig));
     st.mark("lbvh");
     build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.ends), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
-               nullptr, h->d_info, s);
+               nullptr, h->d_info, s, nullptr, nullptr, true);
     batch_roots(offsets, num_clouds, n, nullptr, nullptr, at<int>(ws, plan.other), cl_root, cl_end, h->d_info, s);
     ta.t.d_m = nullptr;
   }
@@ -1145,7 +1148,8 @@ fdb_status batched_launch(fdb_handle* h, const BatchArgs& args, const fdb_option
   }
   if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");
-  launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig));  // batches run the core pass
+  // batches run the core pass
+  launch_finalize(lab, n, h->d_info, s, core, perm, at<int>(ws, plan.minorig), at<uint32_t>(ws, plan.lflag), false);
   st.mark("cluster_ids");
   int* rank = at<int>(ws, plan.rank);
   uint32_t* lbits = at<uint32_t>(ws, plan.lflag);

@@ -180,18 +180,21 @@ int64_t planned_status_words(int64_t n);
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
                 const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
                 int* leaf_rope, int* ends, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s,
-                float4* cut = nullptr, int* cut_n = nullptr);
+                float4* cut = nullptr, int* cut_n = nullptr, bool ends_ready = false);
 
 // k_dense.hip
 // sorted_keys are 64-bit words when key64 (or, with d_key64 set, when *d_key64 on
 // the device says so), else 32-bit; prim_key receives each primitive's key as a
-// 64-bit word.
+// 64-bit word. ends / minorig (optional): set to -1 per primitive and to INT_MAX
+// per point, the starting values of build_lbvh's exchange words (pass
+// ends_ready) and of launch_finalize's minorig.
 void densebox_cells(const void* sorted_keys, bool key64, const int* d_key64, int64_t n, int dim, const float* xs,
                     float eps2, int min_pts, int* cell_id, int* cell_start, int* cand, uint8_t* cell_dense,
                     float4* cell_lo, float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
                     float4* prim_hi, uint64_t* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
                     int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift = 0,
-                    const int* cl_minpts = nullptr, const float* cl_eps2 = nullptr);
+                    const int* cl_minpts = nullptr, const float* cl_eps2 = nullptr, int* ends = nullptr,
+                    int* minorig = nullptr);
 
 // k_trav.hip
 struct TravArgs {
@@ -269,18 +272,21 @@ void launch_debug_walk(const TreeView& t, int m, int mask, int* out_leaves, int*
                        uint32_t* info, hipStream_t s);
 
 // k_label.hip
-void launch_init_labels(int* labels, int64_t n, hipStream_t s);
+// labels[i] = i; with ends / minorig, also those starting values (see densebox_cells).
+void launch_init_labels(int* labels, int64_t n, hipStream_t s, int* ends = nullptr, int* minorig = nullptr);
 // With minorig (core flags final): also the smallest input index (perm) of each
-// root's core points, in minorig[root] (filled here first).
+// root's core points, in minorig[root] (INT_MAX beforehand, unless minorig_init:
+// then filled here first), and the leader words `bits` (ceil(n/32)) cleared.
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s, const uint8_t* core = nullptr,
-                     const uint32_t* perm = nullptr, int* minorig = nullptr);
+                     const uint32_t* perm = nullptr, int* minorig = nullptr, uint32_t* bits = nullptr,
+                     bool minorig_init = true);
 void launch_core_from_sets(const int* labels, uint8_t* core, int64_t n, int min_pts, hipStream_t s);
 void launch_check_forest(const int* labels, const uint8_t* core, int64_t n, uint32_t* bad, uint32_t* info,
                          hipStream_t s);
 // Canonical cluster ids (ids 0..K-1 in increasing order of each cluster's
 // smallest core input index). bits: ceil(n/32) leader words followed by as many
 // ints of scratch (fits the n-int lflag array); wpre: ceil(n/32) ints.
-// minorig_ready: launch_finalize already filled minorig.
+// minorig_ready: launch_finalize already filled minorig and cleared the leader words.
 void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm, int64_t n, int* minorig,
                    uint32_t* bits, int* wpre, int* bsums, int64_t scan_blocks, int* cid, int* d_k, hipStream_t s,
                    bool ids = true, bool minorig_ready = false);
@@ -306,7 +312,10 @@ void launch_scatter(const int* labels, const uint8_t* core, const uint32_t* perm
 const uint32_t* handle_info(const fdb_handle* h);
 
 // Exclusive scan of blocks int32 counts in place (one workgroup); the total goes to *d_total.
-void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s);
+// With bsums2, a second array of as many counts is scanned by a second workgroup of
+// the same launch (its total to *d_total2).
+void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s, int* bsums2 = nullptr,
+                     int* d_total2 = nullptr);
 void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums, int64_t blocks, int* d_total,
                  hipStream_t s);
 

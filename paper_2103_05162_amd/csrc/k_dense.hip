@@ -283,7 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_prims_apply(KeyIn keys, const float*
                                                         float4* __restrict__ prim_lo, float4* __restrict__ prim_hi,
                                                         uint64_t* __restrict__ prim_key, int* __restrict__ dense_list,
                                                         int* __restrict__ labels, uint8_t* __restrict__ core,
-                                                        int* __restrict__ pidx) {
+                                                        int* __restrict__ pidx, int* __restrict__ ends,
+                                                        int* __restrict__ minorig) {
   __shared__ int s_v[kScanTile + kScanTile / 16];
   __shared__ int s_w[kBlock / 64];
   const bool wide = keys.wide();
@@ -321,6 +322,10 @@ __global__ __launch_bounds__(kBlock) void k_prims_apply(KeyIn keys, const float*
     const int ex = s_v[tile_lds(p)];
     const int pi = carry_p + (ex & 0xffff);
     if (pidx) pidx[i] = pi;  // primitives opened before point i (a batch finds its clouds' subtrees with it)
+    // starting values the hierarchy build and the finalisation expect, written here
+    // instead of in fills of their own
+    if (minorig) minorig[i] = 0x7fffffff;
+    if (ends && (fl[k] & 1)) ends[pi] = -1;
     const bool d = (dmask >> k) & 1u;
     if (d) {
       const int c = cl[k];
@@ -403,7 +408,7 @@ void cells_t(const KeyIn& keys, int64_t n, int dim, const float* xs, float eps2,
              int* cell_start, int* cand, uint8_t* dense, float4* cell_lo, float4* cell_hi, int* pflag,
              int* prim_start, int* prim_cnt, float4* prim_lo, float4* prim_hi, uint64_t* prim_key, int* dense_list,
              int* labels, uint8_t* core, int* misc, int* bsums, int64_t scan_blocks, const CloudParams& cp,
-             hipStream_t s) {
+             hipStream_t s, int* ends, int* minorig) {
   (void)scan_blocks;
   int* d_cells = misc + kMiscNumCells;
   int* d_big = misc + kMiscNumCand;  // candidate cells of more than kSmallCell points
@@ -434,16 +439,15 @@ void cells_t(const KeyIn& keys, int64_t n, int dim, const float* xs, float eps2,
   // large-cell list no longer needs by then)
   int* pidx = cp.minpts ? cand : nullptr;
   hipLaunchKernelGGL(k_prims_reduce, gt, dim3(kBlock), 0, s, cell_id, cell_start, dense, n, bsums, bsums_d);
-  scan_block_sums(bsums, tiles, d_prims, s);
-  scan_block_sums(bsums_d, tiles, d_dense, s);
+  scan_block_sums(bsums, tiles, d_prims, s, bsums_d, d_dense);
   if (dim == 3)
     hipLaunchKernelGGL(k_prims_apply<3>, gt, dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense, cell_lo,
                        cell_hi, bsums, bsums_d, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list, labels,
-                       core, pidx);
+                       core, pidx, ends, minorig);
   else
     hipLaunchKernelGGL(k_prims_apply<2>, gt, dim3(kBlock), 0, s, keys, xs, n, cell_id, cell_start, dense, cell_lo,
                        cell_hi, bsums, bsums_d, prim_start, prim_cnt, prim_lo, prim_hi, prim_key, dense_list, labels,
-                       core, pidx);
+                       core, pidx, ends, minorig);
 }
 
 }  // namespace
@@ -453,12 +457,13 @@ void densebox_cells(const void* sorted_keys, bool key64, const int* d_key64, int
                     float4* cell_lo, float4* cell_hi, int* pflag, int* prim_start, int* prim_cnt, float4* prim_lo,
                     float4* prim_hi, uint64_t* prim_key, int* dense_list, int* labels, uint8_t* core, int* misc,
                     int* bsums, int64_t scan_blocks, hipStream_t s, int key_shift, const int* cl_minpts,
-                    const float* cl_eps2) {
+                    const float* cl_eps2, int* ends, int* minorig) {
   // per-cloud parameters come with batches, whose keys are always 64-bit
   CloudParams cp{static_cast<const uint64_t*>(sorted_keys), key_shift, cl_minpts, cl_eps2};
   const KeyIn keys{sorted_keys, d_key64, key64 ? 1 : 0};
   cells_t(keys, n, dim, xs, eps2, min_pts, cell_id, cell_start, cand, cell_dense, cell_lo, cell_hi, pflag, prim_start,
-          prim_cnt, prim_lo, prim_hi, prim_key, dense_list, labels, core, misc, bsums, scan_blocks, cp, s);
+          prim_cnt, prim_lo, prim_hi, prim_key, dense_list, labels, core, misc, bsums, scan_blocks, cp, s, ends,
+          minorig);
 }
 
 }  // namespace fdb

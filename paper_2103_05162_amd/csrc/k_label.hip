@@ -19,9 +19,13 @@ inline int grid_for(int64_t n) {
   return static_cast<int>(g);
 }
 
-__global__ __launch_bounds__(kBlock) void k_iota(int* __restrict__ labels, int64_t n) {
-  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+__global__ __launch_bounds__(kBlock) void k_iota(int* __restrict__ labels, int64_t n, int* __restrict__ ends,
+                                                 int* __restrict__ minorig) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     labels[i] = static_cast<int>(i);
+    if (ends) ends[i] = -1;
+    if (minorig) minorig[i] = 0x7fffffff;
+  }
 }
 
 // No unions run now, so roots are fixed; a stale read is an ancestor and the
@@ -48,11 +52,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int* labels, int64_t n, uin
 // lanes all reach one root reduces first and issues a single atomic.
 __global__ __launch_bounds__(kBlock) void k_finalize_min(int* labels, const uint8_t* __restrict__ core,
                                                          const uint32_t* __restrict__ perm, int64_t n,
-                                                         int* __restrict__ minorig, uint32_t* __restrict__ info) {
+                                                         int* __restrict__ minorig, uint32_t* __restrict__ bits,
+                                                         uint32_t* __restrict__ info) {
   const int lane = threadIdx.x & 63;
   const int64_t stride = int64_t(gridDim.x) * kBlock;
   for (int64_t base = blockIdx.x * int64_t(kBlock) + (threadIdx.x & ~63); base < n; base += stride) {
     const int64_t i = base + lane;
+    if (bits && i < n && (i & 31) == 0) bits[i >> 5] = 0u;  // the leader words, set after this pass
     int r = -1;
     bool valid = false;
     int o = 0x7fffffff;
@@ -282,27 +288,37 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ 
   if (threadIdx.x == 0) bsums[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_bsums(int* __restrict__ bsums, int64_t blocks,
-                                                       int* __restrict__ d_total) {
-  __shared__ int s_w[kBlock / 64];
-  __shared__ int s_carry;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < blocks; base += kBlock) {
-    int64_t i = base + threadIdx.x;
-    int v = i < blocks ? bsums[i] : 0;
-    int inc = wave_inclusive(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 63) s_w[w] = inc;
-    __syncthreads();
-    int add = s_carry;
-    for (int j = 0; j < w; ++j) add += s_w[j];
-    if (i < blocks) bsums[i] = inc - v + add;
-    __syncthreads();
-    if (threadIdx.x == kBlock - 1) s_carry = add + inc;
-    __syncthreads();
+// Exclusive scan of the block sums in place, by one workgroup of kBsumsBlock
+// threads: thread t sums its own run of consecutive entries, the run totals are
+// scanned across the workgroup, and each thread rescans its run (a few entries
+// per thread for the sizes here, so the kernel is two short passes).
+constexpr int kBsumsBlock = 1024;
+
+__global__ __launch_bounds__(kBsumsBlock) void k_scan_bsums(int* __restrict__ bsums, int64_t blocks,
+                                                            int* __restrict__ d_total, int* __restrict__ bsums2,
+                                                            int* __restrict__ d_total2) {
+  __shared__ int s_w[kBsumsBlock / 64];
+  if (blockIdx.x == 1) {  // a second array, scanned by the second workgroup
+    bsums = bsums2;
+    d_total = d_total2;
   }
-  if (threadIdx.x == 0 && d_total) *d_total = s_carry;
+  const int64_t per = (blocks + kBsumsBlock - 1) / kBsumsBlock;
+  const int64_t b0 = threadIdx.x * per, b1 = b0 + per < blocks ? b0 + per : blocks;
+  int sum = 0;
+  for (int64_t i = b0; i < b1; ++i) sum += bsums[i];
+  const int inc = wave_inclusive(sum);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) s_w[w] = inc;
+  __syncthreads();
+  int add = 0;
+  for (int j = 0; j < w; ++j) add += s_w[j];
+  int run = inc - sum + add;  // exclusive prefix of this thread's run
+  for (int64_t i = b0; i < b1; ++i) {
+    const int v = bsums[i];
+    bsums[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == kBsumsBlock - 1 && d_total) *d_total = run;
 }
 
 // Tile position p lives at LDS word p + p/16: thread t's blocked items
@@ -363,23 +379,25 @@ void device_scan(const int* in, int* out, int64_t n, const int* d_n, int* bsums,
   const int64_t nb = ceil_div(n, kScanTile);
   (void)blocks;
   hipLaunchKernelGGL(k_scan_reduce, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, in, n, d_n, bsums);
-  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsums, nb, d_total);
+  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBsumsBlock), 0, s, bsums, nb, d_total, nullptr, nullptr);
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, in, out, n, d_n, bsums);
 }
 
-void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, s, bsums, blocks, d_total);
+void scan_block_sums(int* bsums, int64_t blocks, int* d_total, hipStream_t s, int* bsums2, int* d_total2) {
+  hipLaunchKernelGGL(k_scan_bsums, dim3(bsums2 ? 2 : 1), dim3(kBsumsBlock), 0, s, bsums, blocks, d_total, bsums2,
+                     d_total2);
 }
 
-void launch_init_labels(int* labels, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n);
+void launch_init_labels(int* labels, int64_t n, hipStream_t s, int* ends, int* minorig) {
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, ends, minorig);
 }
 
 void launch_finalize(int* labels, int64_t n, uint32_t* info, hipStream_t s, const uint8_t* core, const uint32_t* perm,
-                     int* minorig) {
+                     int* minorig, uint32_t* bits, bool minorig_init) {
   if (minorig) {
-    fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
-    hipLaunchKernelGGL(k_finalize_min, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, n, minorig, info);
+    if (minorig_init) fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
+    hipLaunchKernelGGL(k_finalize_min, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, core, perm, n, minorig, bits,
+                       info);
   } else {
     hipLaunchKernelGGL(k_finalize, dim3(grid_for(n)), dim3(kBlock), 0, s, labels, n, info);
   }
@@ -406,8 +424,8 @@ void canonical_ids(const int* labels, const uint8_t* core, const uint32_t* perm,
   const int g = grid_for(n);
   const int64_t words = ceil_div(n, 32);
   int* cnt = reinterpret_cast<int*>(bits + words);
-  fill_u32(bits, 0, words, s);
   if (!minorig_ready) {
+    fill_u32(bits, 0, words, s);
     fill_u32(reinterpret_cast<uint32_t*>(minorig), 0x7fffffffu, n, s);
     hipLaunchKernelGGL(k_minorig, dim3(g), dim3(kBlock), 0, s, labels, core, perm, n, minorig);
   }

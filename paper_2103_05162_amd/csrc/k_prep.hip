@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_gridkeys(const float* __restrict__ p
           static_cast<uint64_t*>(keys)[i] = code;
         else
           static_cast<uint32_t*>(keys)[i] = static_cast<uint32_t>(code);
-        vals[i] = static_cast<uint32_t>(i);
+        if (passes == 0) vals[i] = static_cast<uint32_t>(i);  // else the first sort pass makes them
       }
       hist_add(code, valid, passes, s_h);
     }

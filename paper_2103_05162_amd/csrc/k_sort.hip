@@ -131,12 +131,15 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   K key[kItems];
   uint32_t val[kItems];
   uint32_t rank[kItems];
+  // the planned sort's first pass starts from the identity permutation (the key
+  // kernel writes no values then)
+  const bool iota = plan && p == 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     int64_t pos = wbase + k * 64 + lane;
     bool valid = pos < n;
     key[k] = valid ? kin[pos] : K(0);
-    val[k] = valid ? vin[pos] : 0u;
+    val[k] = valid ? (iota ? static_cast<uint32_t>(pos) : vin[pos]) : 0u;
   }
   // Rank within the wavefront: positions run wave-major, then item, then lane,
   // so processing items in order keeps the sort stable.

@@ -1534,6 +1534,8 @@ __global__ void k_core_dbx(TravArgs a) {
 // the per-lane walks. Queries around a dense clump otherwise each walk most of
 // the clump's subtree one node per step.
 constexpr float kPointsPacketExt = 8.0f;
+constexpr int kPointsFewQueries = 32;   // at most this many queries ...
+constexpr float kPointsFewExt = 32.0f;  // ... form a packet up to this many eps wide
 
 template <int D, bool ALL_CORE, bool FIRST, bool B>
 __global__ void k_main_dbx_points(TravArgs a) {
@@ -1574,7 +1576,10 @@ __global__ void k_main_dbx_points(TravArgs a) {
     const bool other_cloud = B && mine && cloud_of(a, i) != cloud_of(a, i0);
     float ext = fmaxf(hi[0] - lo[0], hi[1] - lo[1]);
     if (D == 3) ext = fmaxf(ext, hi[2] - lo[2]);
-    if (!ballot(other_cloud) && ext * ext <= kPointsPacketExt * kPointsPacketExt * ps.eps2) {
+    // a few queries spread wider still walk as one packet: their per-lane walks
+    // would each cross the clumps in between on their own
+    const float ext_max = __popcll(mm) <= kPointsFewQueries ? kPointsFewExt : kPointsPacketExt;
+    if (!ballot(other_cloud) && ext * ext <= ext_max * ext_max * ps.eps2) {
       const float eps2 = ps.eps2;
       // Phase A: pairs of this wavefront's own queries (every core point primitive
       // in its range is a query), each joined from its lower primitive.

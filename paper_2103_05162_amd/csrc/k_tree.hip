@@ -306,11 +306,11 @@ __global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ 
 template <typename K>
 void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs, int64_t n_pts,
              const LeafSrc& ls, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends, int* other,
-             int* gamma, uint32_t* info, hipStream_t s, float4* cut, int* cut_n) {
+             int* gamma, uint32_t* info, hipStream_t s, float4* cut, int* cut_n, bool ends_ready) {
   if (m_cap <= 0) return;
   int g = static_cast<int>(ceil_div(m_cap, kBlock));
   if (m_cap >= 2) {
-    fill_u32(reinterpret_cast<uint32_t*>(ends), 0xffffffffu, m_cap, s);
+    if (!ends_ready) fill_u32(reinterpret_cast<uint32_t*>(ends), 0xffffffffu, m_cap, s);
     const bool buf = m_cap <= kRefitBufMaxNodes;
     const dim3 rg(static_cast<unsigned>(ceil_div(m_cap, kRefitBlock))), rb(kRefitBlock);
     if (dim == 3 && buf)
@@ -333,14 +333,15 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
 
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
                 const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends,
-                int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s, float4* cut, int* cut_n) {
+                int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s, float4* cut, int* cut_n,
+                bool ends_ready) {
   const LeafSrc ls{prim_lo, prim_hi};
   if (key64)
     build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
-            other, gamma, info, s, cut, cut_n);
+            other, gamma, info, s, cut, cut_n, ends_ready);
   else
     build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
-            other, gamma, info, s, cut, cut_n);
+            other, gamma, info, s, cut, cut_n, ends_ready);
 }
 
 }  // namespace fdb
