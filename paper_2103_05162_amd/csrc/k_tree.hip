@@ -289,12 +289,27 @@ __global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ 
       dl = len(i - 1);
     }
     // the new node's index: its own parent side decides it
-    const int p = i == 0 && j == m - 1 ? 0 : (dr > dl ? j : i);
+    const bool root = i == 0 && j == m - 1;
+    const int p = root ? 0 : (dr > dl ? j : i);
     const int o = p == i ? j : i;
-    if (BUF)
+    // a record another workgroup reads during this build (its parent's meeting is
+    // not in LDS) goes out with agent-scope stores; the others only need to be
+    // there for later kernels
+    bool shared = false;
+    if (!root) {
+      const bool l2 = dr > dl;
+      const int s2 = l2 ? j : i - 1;
+      shared = !(i >= L0 && j <= L1 &&
+                 (l2 ? s2 + 1 <= L1 && s_smin[s2 + 1 - (L0 - 1)] < dr : s2 >= L0 && s_pmin[s2 - 1 - (L0 - 1)] < dl));
+    }
+    if (!shared) {
+      node_a[kNodeStride * size_t(p)] = make_float4(box.lo[0], box.lo[1], box.lo[2], __int_as_float(o));
+      node_b[kNodeStride * size_t(p)] = make_float4(box.hi[0], box.hi[1], box.hi[2], __int_as_float(sp));
+    } else if (BUF) {
       store_node_buf(rb, p, box, o, sp);
-    else
+    } else {
       store_node(node_a, node_b, p, box, o, sp);
+    }
     other[p] = o;
     gamma[p] = sp;
   }
