@@ -209,123 +209,14 @@ __device__ __forceinline__ bool traverse_box(const TreeView& t, int m, const Sco
 // Wavefront-cooperative form of traverse_box: the wavefront expands up to 64
 // tree nodes per step (one per lane) from its own stack in LDS, newest first,
 // so a walk takes about as many steps as the tree is deep instead of one step
-// per node. It visits the same buckets and leaves as traverse_box (in another
-// order: callers only union, which does not depend on it). Children that do not
-// fit on the stack have their subtrees walked with traverse_box instead.
+// per node. Every bucket and leaf that one step reaches is handed out a
+// primitive per lane, visit_lanes(r) being called on the whole wavefront with
+// each lane's own primitive (-1 for none), so the visitor loads all of them at
+// once. It visits the same buckets and leaves as traverse_box (in another order:
+// callers only union, which does not depend on it). Children that do not fit on
+// the stack have their subtrees walked with traverse_box instead.
 constexpr int kWideStack = 512;  // entries per wavefront
 
-template <int D, typename F>
-__device__ __forceinline__ void traverse_box_wide(const TreeView& t, int m, const Scope& sc, const float* lo,
-                                                  const float* hi, int mask, int leaf_size, uint32_t* info,
-                                                  uint32_t* stack, F&& visit) {
-  if (m <= 0 || mask >= sc.end) return;
-  const int lane = lane_id();
-  int top = 0;
-  // a walk over the whole tree starts from the cut: its boxes are tested 64 at a
-  // time and the ones within reach pushed, instead of descending from the root
-  const int nc = t.cut && sc.start == 0 && sc.end == m - 1 ? *t.cut_n : 0;
-  if (nc > 0 && nc <= kCutMax) {
-    for (int b = 0; b < nc && top >= 0; b += 64 * kCutUnroll) {
-      float4 ca[kCutUnroll], cb[kCutUnroll];
-#pragma unroll
-      for (int u = 0; u < kCutUnroll; ++u) {  // the loads of kCutUnroll chunks in flight together
-        const int c = min(b + u * 64 + lane, nc - 1);
-        ca[u] = t.cut[2 * c];
-        cb[u] = t.cut[2 * c + 1];
-      }
-#pragma unroll
-      for (int u = 0; u < kCutUnroll; ++u) {
-        const bool hit = b + u * 64 + lane < nc && __float_as_int(cb[u].w) > mask &&
-                         boxbox_dist2<D>(lo, hi, ca[u].x, ca[u].y, ca[u].z, cb[u].x, cb[u].y, cb[u].z) <= sc.eps2;
-        const uint64_t hm = ballot(hit);
-        if (top < 0 || top + __popcll(hm) > kWideStack) {
-          top = -1;  // more than the stack holds: start from the root instead
-        } else {
-          if (hit) stack[top + __popcll(hm & lanemask_lt())] = __float_as_uint(ca[u].w);
-          top += __popcll(hm);
-        }
-      }
-    }
-  }
-  if (nc <= 0 || nc > kCutMax || top < 0) {
-    if (lane == 0) stack[0] = sc.start;
-    top = 1;
-  }
-  int64_t guard = 0;
-  const int64_t max_rounds = 2 * int64_t(m) + 2;
-  while (top > 0) {
-    if (++guard > max_rounds) {
-      atomicOr(info, kInternalBit);
-      return;
-    }
-    const int take = top < 64 ? top : 64;
-    top -= take;
-    const uint32_t node = lane < take ? stack[top + lane] : kEnd;
-    int bs = -1, be = -1;
-    uint32_t c0 = kEnd, c1 = kEnd;
-    if (node != kEnd) {
-      if (node & kLeaf) {
-        const int l = static_cast<int>(node & ~kLeaf);
-        if (l >= m) atomicOr(info, kInternalBit);
-        else if (l > mask) bs = be = l;
-      } else if (node >= static_cast<uint32_t>(m - 1)) {
-        atomicOr(info, kInternalBit);
-      } else {
-        const float4 na = t.node_a[kNodeStride * size_t(node)];
-        const float4 nb = t.node_b[kNodeStride * size_t(node)];
-        const int k = static_cast<int>(node);
-        const int o = __float_as_int(na.w), g = __float_as_int(nb.w);
-        const int first = o < k ? o : k, last = o > k ? o : k;
-        if (last > mask && boxbox_dist2<D>(lo, hi, na.x, na.y, na.z, nb.x, nb.y, nb.z) <= sc.eps2) {
-          if (first < 0 || last >= m || g < first || g >= last) {
-            atomicOr(info, kInternalBit);
-          } else if (last - first < leaf_size) {
-            bs = first <= mask ? mask + 1 : first;
-            be = last;
-          } else {
-            if (g > mask) c0 = first == g ? (kLeaf | static_cast<uint32_t>(g)) : static_cast<uint32_t>(g);
-            c1 = last == g + 1 ? (kLeaf | static_cast<uint32_t>(g + 1)) : static_cast<uint32_t>(g + 1);
-          }
-        }
-      }
-    }
-    for (uint64_t vm = ballot(bs >= 0); vm; vm &= vm - 1) {
-      const int L = __ffsll(static_cast<unsigned long long>(vm)) - 1;
-      if (visit(__shfl(bs, L), __shfl(be, L))) return;
-    }
-    const uint64_t m0 = ballot(c0 != kEnd), m1 = ballot(c1 != kEnd);
-    const int n0 = __popcll(m0), n1 = __popcll(m1);
-    if (top + n0 + n1 <= kWideStack) {
-      const uint64_t lt = lanemask_lt();
-      if (c0 != kEnd) stack[top + __popcll(m0 & lt)] = c0;
-      if (c1 != kEnd) stack[top + n0 + __popcll(m1 & lt)] = c1;
-      top += n0 + n1;
-    } else {
-      // stack full: walk each child's subtree on its own
-      for (uint64_t cm = m0 | m1; cm; cm &= cm - 1) {
-        const int L = __ffsll(static_cast<unsigned long long>(cm)) - 1;
-        for (int side = 0; side < 2; ++side) {
-          const uint32_t c = static_cast<uint32_t>(__shfl(static_cast<int>(side ? c1 : c0), L));
-          if (c == kEnd) continue;
-          int end;
-          if (c & kLeaf) {
-            end = static_cast<int>(c & ~kLeaf);
-          } else {
-            const int oc = __float_as_int(t.node_a[kNodeStride * size_t(c)].w);
-            end = oc > static_cast<int>(c) ? oc : static_cast<int>(c);
-          }
-          const Scope sub{c, end, sc.eps2, sc.min_pts};
-          if (traverse_box<D>(t, m, sub, lo, hi, mask, leaf_size, info, visit)) return;
-        }
-      }
-    }
-  }
-}
-
-// traverse_box_wide delivering primitives rather than ranges: every bucket and
-// leaf that one step of the walk reaches is handed out a primitive per lane,
-// visit_lanes(r) being called on the whole wavefront with each lane's own
-// primitive (-1 for none), so the visitor loads all of them at once.
 template <int D, typename F>
 __device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m, const Scope& sc, const float* lo,
                                                         const float* hi, int mask, int leaf_size, uint32_t* info,
@@ -803,45 +694,54 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   const int p1 = static_cast<int>(base) + 64 * Q - 1;
 
   uint32_t* stack = s_stack + (threadIdx.x >> 6) * kWideStack;
-  traverse_box_wide<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, stack, [&](int s0, int e0) {
-    const int cnt = e0 - s0 + 1;  // <= packet_leaf <= 64
+  // the buckets a step reaches are laid end to end over the lanes (one candidate
+  // per lane), so a step costs a round per 64 candidates, not one per bucket
+  traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, stack, [&](int jl) {
     float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     int cc = 0, cl = 0;
-    if (lane < cnt) {
-      const int j = s0 + lane;
-      cx = a.xs[j];
-      cy = a.xs[a.n + j];
-      cz = D == 3 ? a.xs[2 * a.n + j] : 0.0f;
-      cc = (ALL_CORE || a.core[j]) ? 1 : 0;
-      cl = ancestor_compress(labels, j);
+    if (jl >= 0) {
+      cx = a.xs[jl];
+      cy = a.xs[a.n + jl];
+      cz = D == 3 ? a.xs[2 * a.n + jl] : 0.0f;
+      cc = (ALL_CORE || a.core[jl]) ? 1 : 0;
+      cl = ancestor_compress(labels, jl);
     }
     // candidates that need a test, decided by each candidate's own lane: outside the
     // packet (its pairs are phase A's; j > i0 by the mask), core, and not already in
-    // the packet's set (r may grow during the bucket; a candidate skipped for the
+    // the packet's set (r may grow during the round; a candidate skipped for the
     // old r is in the new r's set too, sets only merge)
-    const bool need = lane < cnt && s0 + lane > p1 && cc && !(common && cl == r);
+    const bool need = jl > p1 && cc && !(common && cl == r);
+    if (!ballot(need)) return false;
+    if (common) {
+      // every lane tests its own candidate against the queries (register
+      // broadcasts, until every candidate has one within eps), and the lanes
+      // that reach one join the packet's set together rather than one by one
+      bool reach = false;
+#pragma unroll
+      for (int s = 0; s < Q; ++s)
+        for (uint64_t qm = mm[s]; qm && ballot(need && !reach); qm &= qm - 1) {
+          const int kl = __ffsll(static_cast<unsigned long long>(qm)) - 1;
+          reach |= need && dist2v<D>(cx, cy, cz, readlane_f(q[s].x, kl), readlane_f(q[s].y, kl),
+                                     readlane_f(q[s].z, kl)) <= eps2;
+        }
+      if (ballot(reach)) {
+        if (reach && !known_same_set(labels, jl, r)) uf_union(labels, r, jl, a.info);
+        int nr = 0;
+        if (lane == fl) nr = uf_find(labels, r, a.info);
+        r = __shfl(nr, fl);
+      }
+      return false;
+    }
     for (uint64_t km = ballot(need); km; km &= km - 1) {
       const int k = __ffsll(static_cast<unsigned long long>(km)) - 1;
-      const int j = s0 + k;
+      const int j = __builtin_amdgcn_readlane(jl, k);
       const int lj = __builtin_amdgcn_readlane(cl, k);
       const float px = readlane_f(cx, k), py = readlane_f(cy, k), pz = readlane_f(cz, k);
-      if (common) {
-        bool h = false;
 #pragma unroll
-        for (int s = 0; s < Q; ++s) h |= mine[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2;
-        const uint64_t hit = ballot(h);
-        if (!hit) continue;
-        const int leader = __ffsll(static_cast<unsigned long long>(hit)) - 1;
-        int nr = r;
-        if (lane == leader && !known_same_set(labels, j, r)) nr = uf_union(labels, r, j, a.info);
-        r = __shfl(nr, leader);
-      } else {
-#pragma unroll
-        for (int s = 0; s < Q; ++s)
-          if (mine[s] && lj != root[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2 &&
-              !known_same_set(labels, j, root[s]))
-            root[s] = uf_union(labels, root[s], j, a.info);
-      }
+      for (int s = 0; s < Q; ++s)
+        if (mine[s] && lj != root[s] && dist2v<D>(px, py, pz, q[s].x, q[s].y, q[s].z) <= eps2 &&
+            !known_same_set(labels, j, root[s]))
+          root[s] = uf_union(labels, root[s], j, a.info);
     }
     return false;
   });
