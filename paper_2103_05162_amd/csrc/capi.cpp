@@ -51,7 +51,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.vals0 = take(N * 4);
   p.vals1 = take(N * 4);
   p.hist = take(8 * 256 * 4);
-  p.digoff = take(8 * 256 * 4);
+  p.digoff = take((8 * 256 + 8) * 4);  // digit offsets of 8 passes, then a "digit constant" flag per pass
   p.tilectr = take(64);
   p.status = take(static_cast<size_t>(p.sort_tiles) * 256 * 8);
   p.xs = take(static_cast<size_t>(dim) * N * 4);

@@ -157,7 +157,9 @@ void launch_permute(const float* pts, int64_t n, int dim, const uint32_t* perm, 
 
 // k_sort.hip: LSD radix sort of (key, index) pairs over the low `bits` bits.
 // hist_ready: hist already holds the digit counts of every pass (from the key
-// kernel). Returns which of the two buffers holds the result (0 or 1).
+// kernel). digoff: 8 * 256 + 8 words (digit offsets, and per pass a flag set when
+// every key has the same digit, whose pass then copies instead of sorting).
+// Returns which of the two buffers holds the result (0 or 1).
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
                uint32_t* hist, bool hist_ready, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
                uint32_t* info, hipStream_t s);

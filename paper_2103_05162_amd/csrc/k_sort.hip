@@ -52,13 +52,21 @@ __global__ __launch_bounds__(kBlock) void k_hist(const K* __restrict__ keys, int
   hist_flush(s_h, passes, hist);
 }
 
-// Exclusive scan of each pass's 256 digit counts -> global digit offsets.
+// Exclusive scan of each pass's 256 digit counts -> global digit offsets, and in
+// digoff[8 * 256 + p] a flag (1) for a pass whose digit is the same for every key.
 __global__ __launch_bounds__(kRadix) void k_digit_offsets(const uint32_t* __restrict__ hist,
                                                           uint32_t* __restrict__ digoff) {
   __shared__ uint32_t s[kRadix];
+  __shared__ uint32_t s_one;
   const int p = blockIdx.x, d = threadIdx.x;
   s[d] = hist[p * kRadix + d];
+  if (d == 0) s_one = 0;
   __syncthreads();
+  uint32_t tot = 0;
+  for (int k = 0; k < kRadix; ++k) tot += s[k];  // every thread, from LDS
+  if (tot > 0 && s[d] == tot) s_one = 1;
+  __syncthreads();
+  if (d == 0) digoff[8 * kRadix + p] = s_one;
   for (int off = 1; off < kRadix; off <<= 1) {
     uint32_t v = d >= off ? s[d - off] : 0;
     __syncthreads();
@@ -66,6 +74,26 @@ __global__ __launch_bounds__(kRadix) void k_digit_offsets(const uint32_t* __rest
     __syncthreads();
   }
   digoff[p * kRadix + d] = s[d] - hist[p * kRadix + d];
+}
+
+// Pass plan of a host-sequenced sort (one thread): constant-digit passes are
+// skipped two at a time, so the number of passes run keeps its parity; each pass
+// run gets the buffer it reads. digoff[8 * 256 + p] becomes bit 1 = skip, bit 0 =
+// source buffer.
+__global__ void k_pass_plan(uint32_t* __restrict__ digoff, int passes) {
+  uint32_t* f = digoff + 8 * kRadix;
+  bool skip[8];
+  for (int p = 0; p < 8; ++p) skip[p] = false;
+  for (int p = 0; p + 1 < passes; ++p)
+    if (f[p] && f[p + 1]) {
+      skip[p] = skip[p + 1] = true;
+      ++p;
+    }
+  int cur = 0;
+  for (int p = 0; p < passes; ++p) {
+    f[p] = (skip[p] ? 2u : 0u) | static_cast<uint32_t>(cur);
+    if (!skip[p]) cur ^= 1;
+  }
 }
 
 // Block-wide exclusive scan of one value per thread (kBlock threads).
@@ -100,12 +128,20 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   if (plan) {
     if (plan->key64 != (sizeof(K) == 8 ? 1 : 0) || p >= plan->passes) return;  // the whole grid leaves
     from = (plan->start ^ p) & 1;
+  } else {
+    // the pass plan of k_pass_plan: a pass whose digit is the same for every key
+    // is the identity permutation and is skipped (in pairs, so the result still
+    // ends in the buffer the host expects)
+    const uint32_t* pp = digoff_all + 8 * kRadix;
+    if (pp[p] & 2u) return;
+    from = static_cast<int>(pp[p] & 1u);
   }
   const K* __restrict__ kin = from ? k1 : k0;
   K* __restrict__ kout = from ? k0 : k1;
   const uint32_t* __restrict__ vin = from ? v1 : v0;
   uint32_t* __restrict__ vout = from ? v0 : v1;
   const int shift = 8 * p;
+
   const uint32_t epoch = static_cast<uint32_t>(p + 1);
   const uint32_t* __restrict__ digoff = digoff_all + p * kRadix;
   uint32_t* __restrict__ tilectr = tilectr_all + p;
@@ -249,6 +285,7 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
     hipLaunchKernelGGL(k_hist<K>, dim3(hg), dim3(kBlock), 0, s, keys0, n, passes, hist);
   }
   hipLaunchKernelGGL(k_digit_offsets, dim3(passes), dim3(kRadix), 0, s, hist, digoff);
+  hipLaunchKernelGGL(k_pass_plan, dim3(1), dim3(1), 0, s, digoff, passes);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(k_onesweep<K>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1, vals0,
