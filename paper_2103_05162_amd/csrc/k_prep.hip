@@ -419,7 +419,7 @@ void launch_morton(const float* pts, int64_t n, int dim, const uint32_t* bounds,
                    int sort_bits, uint32_t* hist, hipStream_t s) {
   const int passes = (sort_bits + 7) / 8;
   fill_u32(hist, 0, passes * 256, s);
-  int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
+  int g = grid_for(n, kBlock * 16, 1024);  // a workgroup histogram per 4096+ keys, flushes kept few
   if (dim == 3)
     hipLaunchKernelGGL(k_morton<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, keys, vals, passes, hist);
   else
@@ -438,7 +438,9 @@ void launch_gridkeys(const float* pts, int64_t n, int dim, const uint32_t* bound
                      void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, uint32_t* hist, hipStream_t s,
                      bool hist_clear) {
   if (hist_clear) fill_u32(hist, 0, 8 * 256, s);
-  int g = grid_for(n, kBlock * 16, 2048);  // a workgroup histogram per 4096+ keys
+  // A workgroup histogram per 4096+ keys, at most 1024 of them: each flushes up to 2048 bins into the
+  // one global histogram, and fewer flushes contend less at L2 than more workgroups gain.
+  int g = grid_for(n, kBlock * 16, 1024);
   if (dim == 3)
     hipLaunchKernelGGL(k_gridkeys<3>, dim3(g), dim3(kBlock), 0, s, pts, n, bounds, plan, keys0, keys1, vals0, vals1,
                        hist);
