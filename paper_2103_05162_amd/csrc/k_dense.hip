@@ -333,11 +333,12 @@ __global__ __launch_bounds__(kBlock) void k_prims_apply(KeyIn keys, const float*
       labels[i] = st;
       core[i] = 1;
       if (fl[k] >> 16) {  // the cell's first point opens its primitive
-        const float4 lo = cell_lo[c];
+        const float4 lo = cell_lo[c], hi = cell_hi[c];
+        const int np = cell_start[c + 1] - st;
         prim_start[pi] = st;
-        prim_cnt[pi] = -(cell_start[c + 1] - st);
+        prim_cnt[pi] = -np;
         prim_lo[pi] = make_float4(lo.x, lo.y, lo.z, __int_as_float(-2 - st));
-        prim_hi[pi] = cell_hi[c];
+        prim_hi[pi] = make_float4(hi.x, hi.y, hi.z, __int_as_float(np));  // w: the cell's point count
         prim_key[pi] = key_at(keys, wide, i);
         dense_list[carry_d + (ex >> 16)] = pi;
       }

@@ -811,6 +811,19 @@ __device__ __forceinline__ bool cell_box_near(const TravArgs& a, int r, float4 l
   return box_dist2<D>(q.x, q.y, q.z, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= eps2;
 }
 
+// Is every point of the dense cell with tight box [lo, hi] within eps of q, as the
+// point-by-point test would decide? Per axis the corner farther from q (by the
+// rounded difference) bounds every point's rounded difference, since rounded
+// subtraction, squaring and addition are monotone; so the test at that corner,
+// made with the same operations in the same order, holds for all of them.
+template <int D>
+__device__ __forceinline__ bool cell_within(float4 lo, float4 hi, const Query& q, float eps2) {
+  const float cx = fabsf(lo.x - q.x) > fabsf(hi.x - q.x) ? lo.x : hi.x;
+  const float cy = fabsf(lo.y - q.y) > fabsf(hi.y - q.y) ? lo.y : hi.y;
+  const float cz = fabsf(lo.z - q.z) > fabsf(hi.z - q.z) ? lo.z : hi.z;
+  return dist2v<D>(cx, cy, cz, q.x, q.y, q.z) <= eps2;
+}
+
 // The query of point primitive p (its record), or an idle lane's (mine false).
 __device__ __forceinline__ void own_record(const TravArgs& a, int p, int m, bool& mine, int& i, Query& q) {
   const float4 lr = p >= 0 && p < m ? a.prim_lo[p] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
@@ -1402,8 +1415,16 @@ __global__ void k_core_dbx(TravArgs a) {
               ++cnt[t];
               if (s != i[t]) rec_add(rec[t], s);
             }
-          } else if (cell_box_near<D>(a, r, lr, q[t], sc[t].eps2)) {
-            pend[t] = r;
+          } else {
+            const float4 hr = a.prim_hi[r];
+            if (box_dist2<D>(q[t].x, q[t].y, q[t].z, lr.x, lr.y, lr.z, hr.x, hr.y, hr.z) <= sc[t].eps2) {
+              if (cell_within<D>(lr, hr, q[t], sc[t].eps2)) {  // counted whole, no scan
+                cnt[t] += __float_as_int(hr.w);
+                rec_add(rec[t], s);  // s == cell_ref(first point)
+              } else {
+                pend[t] = r;
+              }
+            }
           }
         }
       }
@@ -1560,7 +1581,22 @@ __global__ void k_main_dbx_points(TravArgs a) {
                           box_dist2<D>(q.x, q.y, q.z, px, py, pz, ux, uy, uz) <= eps2 &&
                           (common || !known_same_set(labels, j, root));
           if (common && ballot(nb) && known_same_set(labels, j, r)) continue;
-          for (uint64_t lm = ballot(nb); lm; lm &= lm - 1) {
+          // a query whose eps-ball holds the whole cell reaches it without a scan
+          const bool full = nb && cell_within<D>(make_float4(px, py, pz, 0.0f), make_float4(ux, uy, uz, 0.0f), q, eps2);
+          if (common) {
+            const uint64_t fm = ballot(full);
+            if (fm) {
+              const int L = __ffsll(static_cast<unsigned long long>(fm)) - 1;
+              int nr = 0;
+              if (lane == L) nr = uf_union(labels, r, j, a.info);
+              r = __shfl(nr, L);
+              root = r;
+              continue;  // the whole packet is in one set with the cell now
+            }
+          } else if (full) {
+            root = uf_union(labels, root, j, a.info);
+          }
+          for (uint64_t lm = ballot(nb && !full); lm; lm &= lm - 1) {
             const int L = __ffsll(static_cast<unsigned long long>(lm)) - 1;
             const bool reach = cell_reaches_point<D>(a.xs, a.n, j, -a.prim_cnt[rk], readlane_f(q.x, L),
                                                      readlane_f(q.y, L), readlane_f(q.z, L), eps2);
