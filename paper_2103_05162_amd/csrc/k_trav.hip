@@ -871,6 +871,8 @@ __device__ __forceinline__ bool cells_touch(const float* __restrict__ xs, int64_
       act = box_dist2<D>(ax, ay, az, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z) <= eps2;
     }
     if (!ballot(act)) continue;
+    // an A point whose eps-ball holds B's whole tight box pairs with every B point
+    if (ballot(act && cell_within<D>(blo, bhi, Query{ax, ay, az}, eps2))) return true;
     float lo[3] = {act ? ax : INFINITY, act ? ay : INFINITY, act ? az : INFINITY};
     float hi[3] = {act ? ax : -INFINITY, act ? ay : -INFINITY, act ? az : -INFINITY};
 #pragma unroll
