@@ -14,7 +14,7 @@ namespace fdb {
 // 6144-key tiles per CU in LDS; 32-bit keys do best at 5120). The workspace
 // sizes the look-back status for the smaller tile.
 template <typename K>
-constexpr int sort_items() { return sizeof(K) == 8 ? 24 : 20; }
+constexpr int sort_items() { return sizeof(K) == 8 ? 24 : 22; }
 constexpr int kSortTileMin = 256 * 20;  // smallest keys-per-workgroup tile
 constexpr int kScanItems = 16;                 // items per thread in the device scan
 constexpr int kScanTile = 256 * kScanItems;

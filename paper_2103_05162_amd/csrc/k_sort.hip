@@ -3,14 +3,18 @@
 // the keys sorted with equal keys left in index order, which a stable LSD sort
 // started from the identity permutation gives.
 //
-// Design (single-pass per digit, after Merrill & Adinets' "onesweep"): one
-// kernel builds the histograms of every pass at once; then each pass is a
-// single kernel in which a workgroup ranks a tile (5120 32-bit or 6144 64-bit
-// keys) with wavefront ballots, learns its global offsets by a decoupled
-// look-back over earlier tiles (four status words per round trip), and
-// scatters through LDS so that writes are contiguous per digit.
-// Tiles are numbered in the order workgroups start (an atomic ticket), so a
-// tile only waits on tiles already running.
+// Design (after Merrill & Adinets' "onesweep"): one kernel builds the histograms
+// of every pass at once; then in each pass a workgroup ranks a tile (5632 32-bit
+// or 6144 64-bit keys) with wavefront ballots and scatters it through LDS, so that
+// writes are contiguous per digit. A tile learns its global offsets in one of two
+// ways. Look-back: a decoupled look-back over earlier tiles (four status words per
+// round trip), tiles numbered in the order workgroups start (an atomic ticket), so
+// a tile only waits on tiles already running. Reduce-then-scan (the 32-bit passes
+// of the sort planned on the device): a count kernel stores every tile's digit
+// counts and a scan turns them into offsets before the pass, which then waits on
+// nothing. With ~770 tiles in flight at once on 256 CUs, the look-back's walks over
+// earlier tiles' uncached status words cost more than the count kernel's extra
+// read of the keys (per-tile clocks: ~10 of a tile's ~24 us went to the look-back).
 #include "fdb_device.hpp"
 #include "fdb_internal.hpp"
 
@@ -113,29 +117,113 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return x - v + add;
 }
 
-// Pass p reads buffer `from` and writes the other. With a plan (a DenseBox grid
-// sized on the device), the pass runs only if the plan's key width is K's and p
-// is below its pass count, and `from` follows the plan's start buffer; without
-// one, the host's pass sequence starts in buffer 0.
+// Does pass p run, and which buffer does it read (`from`; it writes the other)?
+// With a plan (a DenseBox grid sized on the device), the pass runs only if the
+// plan's key width is K's and p is below its pass count, and `from` follows the
+// plan's start buffer. Without one, the pass plan of k_pass_plan decides: a pass
+// whose digit is the same for every key is the identity permutation and is
+// skipped (in pairs, so the result still ends in the buffer the host expects).
 template <typename K>
+__device__ __forceinline__ bool pass_source(int p, const GridPlan* plan, const uint32_t* digoff_all, int& from) {
+  if (plan) {
+    if (plan->key64 != (sizeof(K) == 8 ? 1 : 0) || p >= plan->passes) return false;
+    from = (plan->start ^ p) & 1;
+    return true;
+  }
+  const uint32_t f = digoff_all[8 * kRadix + p];
+  if (f & 2u) return false;
+  from = static_cast<int>(f & 1u);
+  return true;
+}
+
+// Reduce step of a pass without look-back: every digit's count in every tile,
+// digit-major (counts[d * tiles + tile]) for the scan. Tiles are the pass's.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_tile_counts(const K* __restrict__ k0, const K* __restrict__ k1,
+                                                        int64_t n, int p, const GridPlan* __restrict__ plan,
+                                                        const uint32_t* __restrict__ digoff_all,
+                                                        uint32_t* __restrict__ counts, int64_t tiles) {
+  int from = 0;
+  if (!pass_source<K>(p, plan, digoff_all, from)) return;  // the whole grid leaves
+  const K* __restrict__ kin = from ? k1 : k0;
+  constexpr int kItems = sort_items<K>();
+  constexpr int kTile = 256 * kItems;
+  __shared__ uint32_t s_h[kRadix];
+  const int tid = threadIdx.x, lane = tid & 63;
+  s_h[tid] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kTile;
+  const int shift = 8 * p;
+  K key[kItems];
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t pos = base + k * kBlock + tid;
+    key[k] = pos < n ? kin[pos] : K(0);
+  }
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const bool valid = base + k * kBlock + tid < n;
+    const uint32_t d = digit_of(key[k], shift);
+    const uint64_t m = match_digit(d, valid);
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    if (valid && lane == leader) atomicAdd(s_h + d, static_cast<uint32_t>(__popcll(m)));  // one per distinct digit
+  }
+  __syncthreads();
+  counts[int64_t(tid) * tiles + blockIdx.x] = s_h[tid];
+}
+
+// Scan step: for digit d (workgroup d), the digit's global offset plus the
+// running sum of its counts in earlier tiles, in place: where each tile's keys of
+// digit d start in the output.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_tile_scan(uint32_t* __restrict__ counts, int64_t tiles, int p,
+                                                      const GridPlan* __restrict__ plan,
+                                                      const uint32_t* __restrict__ digoff_all) {
+  int from = 0;
+  if (!pass_source<K>(p, plan, digoff_all, from)) return;
+  constexpr int kPer = 8;
+  __shared__ uint32_t s_wsum[kWaves];
+  __shared__ uint32_t s_tot;
+  const int d = blockIdx.x, tid = threadIdx.x;
+  uint32_t* __restrict__ c = counts + int64_t(d) * tiles;
+  uint32_t run = digoff_all[p * kRadix + d];
+  for (int64_t c0 = 0; c0 < tiles; c0 += kBlock * kPer) {
+    uint32_t v[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t i = c0 + int64_t(tid) * kPer + k;
+      v[k] = i < tiles ? c[i] : 0u;
+      sum += v[k];
+    }
+    const uint32_t ex = block_exclusive_scan(sum, s_wsum);
+    if (tid == kBlock - 1) s_tot = ex + sum;
+    uint32_t r = run + ex;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t i = c0 + int64_t(tid) * kPer + k;
+      if (i < tiles) c[i] = r;
+      r += v[k];
+    }
+    __syncthreads();
+    run += s_tot;
+    __syncthreads();
+  }
+}
+
+// One pass: reads buffer `from` (pass_source) and writes the other. OFFS: the
+// tile is the workgroup's index and its offsets come from k_tile_scan (offs);
+// otherwise from the look-back.
+template <typename K, bool OFFS>
 __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __restrict__ k1,
                                                      uint32_t* __restrict__ v0, uint32_t* __restrict__ v1, int64_t n,
                                                      int p, const GridPlan* __restrict__ plan,
                                                      const uint32_t* __restrict__ digoff_all,
                                                      uint32_t* __restrict__ tilectr_all, uint64_t* __restrict__ status,
+                                                     const uint32_t* __restrict__ offs, int64_t otiles,
                                                      uint32_t* __restrict__ info) {
-  int from = p & 1;
-  if (plan) {
-    if (plan->key64 != (sizeof(K) == 8 ? 1 : 0) || p >= plan->passes) return;  // the whole grid leaves
-    from = (plan->start ^ p) & 1;
-  } else {
-    // the pass plan of k_pass_plan: a pass whose digit is the same for every key
-    // is the identity permutation and is skipped (in pairs, so the result still
-    // ends in the buffer the host expects)
-    const uint32_t* pp = digoff_all + 8 * kRadix;
-    if (pp[p] & 2u) return;
-    from = static_cast<int>(pp[p] & 1u);
-  }
+  int from = 0;
+  if (!pass_source<K>(p, plan, digoff_all, from)) return;  // the whole grid leaves
   const K* __restrict__ kin = from ? k1 : k0;
   K* __restrict__ kout = from ? k0 : k1;
   const uint32_t* __restrict__ vin = from ? v1 : v0;
@@ -158,10 +246,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   __shared__ uint32_t s_vals[kTile];
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  if (tid == 0) s_tile = atomicAdd(tilectr, 1u);
+  if (!OFFS && tid == 0) s_tile = atomicAdd(tilectr, 1u);
   for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t tile = s_tile;
+  const int64_t tile = OFFS ? int64_t(blockIdx.x) : int64_t(s_tile);
   const int64_t wbase = tile * kTile + int64_t(w) * kWaveTile;
 
   K key[kItems];
@@ -195,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   }
   __syncthreads();
 
-  // Thread d: prefix over wavefronts, tile total, then the look-back.
+  // Thread d: prefix over wavefronts and tile total of digit d.
   const uint32_t d = tid;
   uint32_t total = 0;
 #pragma unroll
@@ -204,42 +292,47 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
     s_wcnt[j][d] = total;
     total += c;
   }
-  uint64_t* st = status + tile * kRadix + d;
-  uint32_t excl = 0;
-  if (tile == 0) {
-    st_agent64(st, pack_status(epoch, kFlagIncl, total));
+  // Thread d: its tile's global start for digit d.
+  if constexpr (OFFS) {
+    s_gbase[d] = offs[int64_t(d) * otiles + tile];
   } else {
-    st_agent64(st, pack_status(epoch, kFlagAgg, total));
-    int spins = 0;
-    for (int64_t j = tile - 1; j >= 0;) {
-      // four predecessors per round trip
-      uint64_t v[4];
+    uint64_t* st = status + tile * kRadix + d;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      st_agent64(st, pack_status(epoch, kFlagIncl, total));
+    } else {
+      st_agent64(st, pack_status(epoch, kFlagAgg, total));
+      int spins = 0;
+      for (int64_t j = tile - 1; j >= 0;) {
+        // four predecessors per round trip
+        uint64_t v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = j - u >= 0 ? ld_agent64(status + (j - u) * kRadix + d) : 0;
-      bool done = false, wait = false;
+        for (int u = 0; u < 4; ++u) v[u] = j - u >= 0 ? ld_agent64(status + (j - u) * kRadix + d) : 0;
+        bool done = false, wait = false;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (done || wait || j < 0) continue;
-        if (static_cast<uint32_t>(v[u] >> 34) != epoch) {
-          wait = true;
-          continue;
+        for (int u = 0; u < 4; ++u) {
+          if (done || wait || j < 0) continue;
+          if (static_cast<uint32_t>(v[u] >> 34) != epoch) {
+            wait = true;
+            continue;
+          }
+          excl += static_cast<uint32_t>(v[u]);
+          if (((v[u] >> 32) & 3u) == kFlagIncl) done = true;
+          else --j;
         }
-        excl += static_cast<uint32_t>(v[u]);
-        if (((v[u] >> 32) & 3u) == kFlagIncl) done = true;
-        else --j;
-      }
-      if (done) break;
-      if (wait) {
-        if (++spins > (1 << 24)) {
-          atomicOr(info, kInternalBit);
-          break;
+        if (done) break;
+        if (wait) {
+          if (++spins > (1 << 24)) {
+            atomicOr(info, kInternalBit);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_s_sleep(1);
       }
+      st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
     }
-    st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
+    s_gbase[d] = digoff[d] + excl;
   }
-  s_gbase[d] = digoff[d] + excl;
   uint32_t ds = block_exclusive_scan(total, s_wsum);
   s_dstart[d] = ds;
   __syncthreads();
@@ -288,8 +381,9 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
   hipLaunchKernelGGL(k_pass_plan, dim3(1), dim3(1), 0, s, digoff, passes);
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(k_onesweep<K>, dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1, vals0,
-                       vals1, n, p, static_cast<const GridPlan*>(nullptr), digoff, tilectr, status, info);
+    hipLaunchKernelGGL((k_onesweep<K, false>), dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1,
+                       vals0, vals1, n, p, static_cast<const GridPlan*>(nullptr), digoff, tilectr, status,
+                       static_cast<const uint32_t*>(nullptr), int64_t(0), info);
     cur ^= 1;
   }
   return cur;
@@ -297,7 +391,9 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
 
 }  // namespace
 
-int64_t planned_status_words(int64_t n) { return ceil_div(n, 256 * sort_items<uint32_t>()) * kRadix * 2; }
+// Look-back words of the planned sort's 64-bit passes (the 32-bit passes keep
+// their tile counts in the same buffer; a call runs one width only).
+int64_t planned_status_words(int64_t n) { return ceil_div(n, 256 * sort_items<uint64_t>()) * kRadix * 2; }
 
 void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, const GridPlan* plan,
                         const uint32_t* hist, uint32_t* digoff, uint32_t* tilectr, uint64_t* status,
@@ -310,14 +406,22 @@ void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* val
     fill_u32(reinterpret_cast<uint32_t*>(status), 0, planned_status_words(n), s);
   }
   hipLaunchKernelGGL(k_digit_offsets, dim3(8), dim3(kRadix), 0, s, hist, digoff);
-  for (int p = 0; p < 4; ++p)  // 32-bit keys: at most 4 passes
-    hipLaunchKernelGGL(k_onesweep<uint32_t>, dim3(static_cast<unsigned>(tiles32)), dim3(kBlock), 0, s,
-                       static_cast<uint32_t*>(keys0), static_cast<uint32_t*>(keys1), vals0, vals1, n, p, plan, digoff,
-                       tilectr, status, info);
+  // 32-bit keys (at most 4 passes): reduce, scan, then the pass, the tile counts
+  // in the look-back buffer (tiles32 * 256 words of its tiles32 * 512)
+  uint32_t* counts = reinterpret_cast<uint32_t*>(status);
+  uint32_t* k32[2] = {static_cast<uint32_t*>(keys0), static_cast<uint32_t*>(keys1)};
+  for (int p = 0; p < 4; ++p) {
+    hipLaunchKernelGGL(k_tile_counts<uint32_t>, dim3(static_cast<unsigned>(tiles32)), dim3(kBlock), 0, s, k32[0],
+                       k32[1], n, p, plan, digoff, counts, tiles32);
+    hipLaunchKernelGGL(k_tile_scan<uint32_t>, dim3(kRadix), dim3(kBlock), 0, s, counts, tiles32, p, plan, digoff);
+    hipLaunchKernelGGL((k_onesweep<uint32_t, true>), dim3(static_cast<unsigned>(tiles32)), dim3(kBlock), 0, s, k32[0],
+                       k32[1], vals0, vals1, n, p, plan, digoff, tilectr, status,
+                       static_cast<const uint32_t*>(counts), tiles32, info);
+  }
   for (int p = 0; p < 8; ++p)  // 64-bit keys
-    hipLaunchKernelGGL(k_onesweep<uint64_t>, dim3(static_cast<unsigned>(tiles64)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(static_cast<unsigned>(tiles64)), dim3(kBlock), 0, s,
                        static_cast<uint64_t*>(keys0), static_cast<uint64_t*>(keys1), vals0, vals1, n, p, plan,
-                       digoff, tilectr, status, info);
+                       digoff, tilectr, status, static_cast<const uint32_t*>(nullptr), int64_t(0), info);
 }
 
 int radix_sort(void* keys0, void* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n, bool key64, int bits,
