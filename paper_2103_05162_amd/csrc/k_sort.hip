@@ -152,7 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const K* __restrict__ k0
   const int tid = threadIdx.x, lane = tid & 63;
   s_h[tid] = 0;
   __syncthreads();
-  const int64_t base = int64_t(blockIdx.x) * kTile;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);  // the pass's mapping: it re-reads these keys from L2
+  const int64_t base = int64_t(tile) * kTile;
   const int shift = 8 * p;
   K key[kItems];
 #pragma unroll
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const K* __restrict__ k0
     if (valid && lane == leader) atomicAdd(s_h + d, static_cast<uint32_t>(__popcll(m)));  // one per distinct digit
   }
   __syncthreads();
-  counts[int64_t(tid) * tiles + blockIdx.x] = s_h[tid];
+  counts[int64_t(tid) * tiles + tile] = s_h[tid];
 }
 
 // Scan step: for digit d (workgroup d), the digit's global offset plus the
@@ -212,8 +213,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(uint32_t* __restrict__ cou
 }
 
 // One pass: reads buffer `from` (pass_source) and writes the other. OFFS: the
-// tile is the workgroup's index and its offsets come from k_tile_scan (offs);
-// otherwise from the look-back.
+// tile follows from the workgroup's index and its offsets come from k_tile_scan
+// (offs); otherwise from the look-back.
 template <typename K, bool OFFS>
 __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __restrict__ k1,
                                                      uint32_t* __restrict__ v0, uint32_t* __restrict__ v1, int64_t n,
@@ -249,7 +250,10 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   if (!OFFS && tid == 0) s_tile = atomicAdd(tilectr, 1u);
   for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t tile = OFFS ? int64_t(blockIdx.x) : int64_t(s_tile);
+  // OFFS: tiles laid contiguously per XCD (as in k_tile_counts), so the partial
+  // output lines where one tile's run of a digit meets the next tile's are
+  // completed in one L2 instead of being written to memory from two
+  const int64_t tile = OFFS ? int64_t(xcd_block(blockIdx.x, gridDim.x)) : int64_t(s_tile);
   const int64_t wbase = tile * kTile + int64_t(w) * kWaveTile;
 
   K key[kItems];
@@ -379,6 +383,9 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
   }
   hipLaunchKernelGGL(k_digit_offsets, dim3(passes), dim3(kRadix), 0, s, hist, digoff);
   hipLaunchKernelGGL(k_pass_plan, dim3(1), dim3(1), 0, s, digoff, passes);
+  // (look-back passes: for 64-bit keys, a count kernel's second read of the keys
+  // and its extra launches cost more than the look-back; measured on the Morton
+  // and batch sorts)
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL((k_onesweep<K, false>), dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1,
