@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const K* __restrict__ k0
   constexpr int kItems = sort_items<K>();
   constexpr int kTile = 256 * kItems;
   __shared__ uint32_t s_h[kRadix];
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   s_h[tid] = 0;
   __syncthreads();
   const int tile = xcd_block(blockIdx.x, gridDim.x);  // the pass's mapping: it re-reads these keys from L2
@@ -161,14 +161,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_counts(const K* __restrict__ k0
     const int64_t pos = base + k * kBlock + tid;
     key[k] = pos < n ? kin[pos] : K(0);
   }
+  // counts only (no ranks): one LDS atomic per wavefront when its lanes share the
+  // digit, else one per lane; the ranking pass's eight-ballot digit match made
+  // this kernel VALU-bound (24 us a pass on 8M keys)
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    const bool valid = base + k * kBlock + tid < n;
-    const uint32_t d = digit_of(key[k], shift);
-    const uint64_t m = match_digit(d, valid);
-    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    if (valid && lane == leader) atomicAdd(s_h + d, static_cast<uint32_t>(__popcll(m)));  // one per distinct digit
-  }
+  for (int k = 0; k < kItems; ++k) hist_add(static_cast<K>(key[k] >> shift), base + k * kBlock + tid < n, 1, s_h);
   __syncthreads();
   counts[int64_t(tid) * tiles + tile] = s_h[tid];
 }
