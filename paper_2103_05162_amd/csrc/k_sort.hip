@@ -244,123 +244,141 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(K* __restrict__ k0, K* __re
   __shared__ uint32_t s_vals[kTile];
 
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  if (!OFFS && tid == 0) s_tile = atomicAdd(tilectr, 1u);
-  for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
-  __syncthreads();
-  // OFFS: tiles laid contiguously per XCD (as in k_tile_counts), so the partial
-  // output lines where one tile's run of a digit meets the next tile's are
-  // completed in one L2 instead of being written to memory from two
-  const int64_t tile = OFFS ? int64_t(xcd_block(blockIdx.x, gridDim.x)) : int64_t(s_tile);
-  const int64_t wbase = tile * kTile + int64_t(w) * kWaveTile;
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  // Look-back: a workgroup takes tiles by ticket until none is left, so the grid
+  // is what is resident at once rather than a workgroup per tile. OFFS: one tile
+  // per workgroup.
+  for (;;) {
+    if (!OFFS && tid == 0) s_tile = atomicAdd(tilectr, 1u);
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    // OFFS: tiles laid contiguously per XCD (as in k_tile_counts), so the partial
+    // output lines where one tile's run of a digit meets the next tile's are
+    // completed in one L2 instead of being written to memory from two
+    const int64_t tile = OFFS ? int64_t(xcd_block(blockIdx.x, gridDim.x)) : int64_t(s_tile);
+    if (tile >= ntiles) break;  // uniform: s_tile is shared
+    const int64_t wbase = tile * kTile + int64_t(w) * kWaveTile;
 
-  K key[kItems];
-  uint32_t val[kItems];
-  uint32_t rank[kItems];
-  // the planned sort's first pass starts from the identity permutation (the key
-  // kernel writes no values then)
-  const bool iota = plan && p == 0;
+    K key[kItems];
+    uint32_t val[kItems];
+    uint32_t rank[kItems];
+    // the planned sort's first pass starts from the identity permutation (the key
+    // kernel writes no values then)
+    const bool iota = plan && p == 0;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    int64_t pos = wbase + k * 64 + lane;
-    bool valid = pos < n;
-    key[k] = valid ? kin[pos] : K(0);
-    val[k] = valid ? (iota ? static_cast<uint32_t>(pos) : vin[pos]) : 0u;
-  }
-  // Rank within the wavefront: positions run wave-major, then item, then lane,
-  // so processing items in order keeps the sort stable.
-#pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    bool valid = wbase + k * 64 + lane < n;
-    uint32_t d = digit_of(key[k], shift);
-    uint64_t m = match_digit(d, valid);
-    int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
-    uint32_t before = 0;
-    if (valid && lane == leader) {  // leaders of distinct digits touch distinct words
-      before = s_wcnt[w][d];
-      s_wcnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
+    for (int k = 0; k < kItems; ++k) {
+      int64_t pos = wbase + k * 64 + lane;
+      bool valid = pos < n;
+      key[k] = valid ? kin[pos] : K(0);
+      val[k] = valid ? (iota ? static_cast<uint32_t>(pos) : vin[pos]) : 0u;
     }
-    before = __shfl(before, leader < 0 ? 0 : leader);
-    rank[k] = before + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
-  }
-  __syncthreads();
-
-  // Thread d: prefix over wavefronts and tile total of digit d.
-  const uint32_t d = tid;
-  uint32_t total = 0;
+    // Rank within the wavefront: positions run wave-major, then item, then lane,
+    // so processing items in order keeps the sort stable.
 #pragma unroll
-  for (int j = 0; j < kWaves; ++j) {
-    uint32_t c = s_wcnt[j][d];
-    s_wcnt[j][d] = total;
-    total += c;
-  }
-  // Thread d: its tile's global start for digit d.
-  if constexpr (OFFS) {
-    s_gbase[d] = offs[int64_t(d) * otiles + tile];
-  } else {
-    uint64_t* st = status + tile * kRadix + d;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      st_agent64(st, pack_status(epoch, kFlagIncl, total));
-    } else {
-      st_agent64(st, pack_status(epoch, kFlagAgg, total));
-      int spins = 0;
-      for (int64_t j = tile - 1; j >= 0;) {
-        // four predecessors per round trip
-        uint64_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = j - u >= 0 ? ld_agent64(status + (j - u) * kRadix + d) : 0;
-        bool done = false, wait = false;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (done || wait || j < 0) continue;
-          if (static_cast<uint32_t>(v[u] >> 34) != epoch) {
-            wait = true;
-            continue;
-          }
-          excl += static_cast<uint32_t>(v[u]);
-          if (((v[u] >> 32) & 3u) == kFlagIncl) done = true;
-          else --j;
-        }
-        if (done) break;
-        if (wait) {
-          if (++spins > (1 << 24)) {
-            atomicOr(info, kInternalBit);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+    for (int k = 0; k < kItems; ++k) {
+      bool valid = wbase + k * 64 + lane < n;
+      uint32_t d = digit_of(key[k], shift);
+      uint64_t m = match_digit(d, valid);
+      int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+      uint32_t before = 0;
+      if (valid && lane == leader) {  // leaders of distinct digits touch distinct words
+        before = s_wcnt[w][d];
+        s_wcnt[w][d] = before + static_cast<uint32_t>(__popcll(m));
       }
-      st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
+      before = __shfl(before, leader < 0 ? 0 : leader);
+      rank[k] = before + static_cast<uint32_t>(__popcll(m & lanemask_lt()));
     }
-    s_gbase[d] = digoff[d] + excl;
-  }
-  uint32_t ds = block_exclusive_scan(total, s_wsum);
-  s_dstart[d] = ds;
-  __syncthreads();
+    __syncthreads();
 
-  // Local scatter into LDS in sorted order.
+    // Thread d: prefix over wavefronts and tile total of digit d.
+    const uint32_t d = tid;
+    uint32_t total = 0;
 #pragma unroll
-  for (int k = 0; k < kItems; ++k) {
-    if (wbase + k * 64 + lane < n) {
-      uint32_t dk = digit_of(key[k], shift);
-      uint32_t pos = s_dstart[dk] + s_wcnt[w][dk] + rank[k];
-      s_keys[pos] = key[k];
-      s_vals[pos] = val[k];
+    for (int j = 0; j < kWaves; ++j) {
+      uint32_t c = s_wcnt[j][d];
+      s_wcnt[j][d] = total;
+      total += c;
     }
-  }
-  __syncthreads();
-  const int64_t tile_n = n - tile * kTile < kTile ? n - tile * kTile : kTile;
-  for (int i = tid; i < tile_n; i += kBlock) {
-    K kk = s_keys[i];
-    uint32_t dk = digit_of(kk, shift);
-    uint32_t dest = s_gbase[dk] + (i - s_dstart[dk]);
-    if (dest >= n) {  // only after a failed look-back
-      atomicOr(info, kInternalBit);
-      continue;
+    // Thread d: its tile's global start for digit d.
+    if constexpr (OFFS) {
+      s_gbase[d] = offs[int64_t(d) * otiles + tile];
+    } else {
+      uint64_t* st = status + tile * kRadix + d;
+      uint32_t excl = 0;
+      if (tile == 0) {
+        st_agent64(st, pack_status(epoch, kFlagIncl, total));
+      } else {
+        st_agent64(st, pack_status(epoch, kFlagAgg, total));
+        int spins = 0;
+        for (int64_t j = tile - 1; j >= 0;) {
+          // four predecessors per round trip
+          uint64_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = j - u >= 0 ? ld_agent64(status + (j - u) * kRadix + d) : 0;
+          bool done = false, wait = false;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (done || wait || j < 0) continue;
+            if (static_cast<uint32_t>(v[u] >> 34) != epoch) {
+              wait = true;
+              continue;
+            }
+            excl += static_cast<uint32_t>(v[u]);
+            if (((v[u] >> 32) & 3u) == kFlagIncl) done = true;
+            else --j;
+          }
+          if (done) break;
+          if (wait) {
+            if (++spins > (1 << 24)) {
+              atomicOr(info, kInternalBit);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        st_agent64(st, pack_status(epoch, kFlagIncl, excl + total));
+      }
+      s_gbase[d] = digoff[d] + excl;
     }
-    kout[dest] = kk;
-    vout[dest] = s_vals[i];
+    uint32_t ds = block_exclusive_scan(total, s_wsum);
+    s_dstart[d] = ds;
+    __syncthreads();
+
+    // Local scatter into LDS in sorted order.
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (wbase + k * 64 + lane < n) {
+        uint32_t dk = digit_of(key[k], shift);
+        uint32_t pos = s_dstart[dk] + s_wcnt[w][dk] + rank[k];
+        s_keys[pos] = key[k];
+        s_vals[pos] = val[k];
+      }
+    }
+    __syncthreads();
+    const int64_t tile_n = n - tile * kTile < kTile ? n - tile * kTile : kTile;
+    for (int i = tid; i < tile_n; i += kBlock) {
+      K kk = s_keys[i];
+      uint32_t dk = digit_of(kk, shift);
+      uint32_t dest = s_gbase[dk] + (i - s_dstart[dk]);
+      if (dest >= n) {  // only after a failed look-back
+        atomicOr(info, kInternalBit);
+        continue;
+      }
+      kout[dest] = kk;
+      vout[dest] = s_vals[i];
+    }
+    if (OFFS) break;
+    __syncthreads();  // the next tile reuses the LDS
   }
+}
+
+// Workgroups of a look-back pass: at most what is resident at once on 256 CUs
+// (two 64-bit or three 32-bit tiles per CU, bound by registers); they loop over
+// the tiles.
+template <typename K>
+unsigned lookback_grid(int64_t tiles) {
+  const int64_t cap = (sizeof(K) == 8 ? 2 : 3) * 256;
+  return static_cast<unsigned>(tiles < cap ? tiles : cap);
 }
 
 template <typename K>
@@ -385,7 +403,7 @@ int radix_sort_t(K* keys0, K* keys1, uint32_t* vals0, uint32_t* vals1, int64_t n
   // and batch sorts)
   int cur = 0;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_onesweep<K, false>), dim3(static_cast<unsigned>(tiles)), dim3(kBlock), 0, s, keys0, keys1,
+    hipLaunchKernelGGL((k_onesweep<K, false>), dim3(lookback_grid<K>(tiles)), dim3(kBlock), 0, s, keys0, keys1,
                        vals0, vals1, n, p, static_cast<const GridPlan*>(nullptr), digoff, tilectr, status,
                        static_cast<const uint32_t*>(nullptr), int64_t(0), info);
     cur ^= 1;
@@ -423,7 +441,7 @@ void radix_sort_planned(void* keys0, void* keys1, uint32_t* vals0, uint32_t* val
                        static_cast<const uint32_t*>(counts), tiles32, info);
   }
   for (int p = 0; p < 8; ++p)  // 64-bit keys
-    hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(static_cast<unsigned>(tiles64)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_onesweep<uint64_t, false>), dim3(lookback_grid<uint64_t>(tiles64)), dim3(kBlock), 0, s,
                        static_cast<uint64_t*>(keys0), static_cast<uint64_t*>(keys1), vals0, vals1, n, p, plan,
                        digoff, tilectr, status, static_cast<const uint32_t*>(nullptr), int64_t(0), info);
 }
