@@ -130,8 +130,10 @@ def test_leaf_and_block_sizes_do_not_change_labels(dev, leaf, block):
 # ---- edge cases ----------------------------------------------------------------------
 
 @pytest.mark.parametrize("algo", ALGOS)
-@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 4095, 4096, 4097, 8193])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 4095, 4096, 4097, 5631, 5632, 5633, 6143, 6144, 6145, 8193,
+                               11265, 12289])
 def test_ragged_sizes(dev, algo, n):
+    # sort tiles: 5632 32-bit keys (grid keys), 6144 64-bit keys (Morton codes)
     pts = _mixture(100 + n, n, 3, 3, 0.02)
     for mp in (1, 2, 4):
         assert_exact(dev, pts, 0.05, mp, algo)
