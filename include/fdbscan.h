@@ -178,7 +178,7 @@ fdb_status fdb_dbscan(fdb_handle* h, const float* points, int64_t n, int32_t dim
  *     on the handle's device (no hipMalloc, no hipFree, no allocating library
  *     call; the handle was set up by fdb_create). An input whose
  *     fdb_workspace_bytes exceeds it returns FDB_ERR_SCRATCH before any launch
- *     (64 MiB holds about 299k 3D points for DenseBox, 544k for FDbscan);
+ *     (64 MiB holds about 298k 3D points for DenseBox, 543k for FDbscan);
  *   - opt->flags must not hold FDB_FLAG_GRAPH (recording a graph allocates):
  *     FDB_ERR_INVALID;
  *   - stage timing (fdb_set_timing) is not recorded.

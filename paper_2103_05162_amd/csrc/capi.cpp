@@ -60,7 +60,7 @@ Plan make_plan(int64_t n, int dim, int algo, int num_clouds) {
   p.rope = take(N * 4);
   p.leaf_rope = take(N * 4);
   p.ends = take(N * 4);
-  p.cut = take(static_cast<size_t>(kCutMax) * 32);
+  p.cut = take(static_cast<size_t>(kCutMax) * 36);  // kCutMax box pairs, then a summary word each
   p.other = take(N * 4);
   p.gamma = take(N * 4);
   p.labels = take(N * 4);
@@ -869,7 +869,7 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     build_lbvh(keys[cur], true, static_cast<int>(n), dim, xs, n, nullptr, nullptr, at<float4>(ws, plan.node_a),
                at<float4>(ws, plan.node_b), at<int>(ws, plan.rope), at<int>(ws, plan.leaf_rope),
                at<int>(ws, plan.ends), at<int>(ws, plan.other), at<int>(ws, plan.gamma),
-               nullptr, h->d_info, s, at<float4>(ws, plan.cut), misc + kMiscCut, true);
+               nullptr, h->d_info, s, at<float4>(ws, plan.cut), misc + kMiscCut, true, kCutDivFine);
     ta.t.m_cap = static_cast<int>(n);
     ta.t.d_m = nullptr;
     ta.t.cut = at<float4>(ws, plan.cut);
@@ -907,7 +907,19 @@ fdb_status dbscan_launch(fdb_handle* h, const SingleArgs& args, const fdb_option
     launch_main(ta, dim, true, all_core, first_border && !all_core, 2, s);
   } else {
     st.mark("main");
-    launch_main(ta, dim, false, all_core, first_border && !all_core, 0, s);
+    if (all_core || !first_border) {
+      // the packet main phase: core pairs of curve neighbours first, then per cut
+      // subtree the set its core points are in, so packets pass over subtrees
+      // already in their own set
+      int* csum = reinterpret_cast<int*>(at<float4>(ws, plan.cut) + 2 * kCutMax);
+      launch_fdb_local(ta, dim, all_core, s);
+      launch_cut_summary(ta, all_core, csum, s);
+      ta.t.cut_sum = csum;
+      launch_main(ta, dim, false, all_core, false, 0, s);
+    } else {
+      launch_main(ta, dim, false, all_core, first_border && !all_core, 0, s);
+    }
+    ta.t.cut_sum = nullptr;
   }
   if (o.flags & FDB_FLAG_VALIDATE) launch_check_forest(lab, all_core ? nullptr : core, n, h->d_info + 1, h->d_info, s);
   st.mark("finalize");

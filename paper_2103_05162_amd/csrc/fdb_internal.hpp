@@ -109,13 +109,19 @@ struct TreeView {
   // instead of descending from the root. Null, or a count above kCutMax: no cut.
   const float4* cut = nullptr;
   const int* cut_n = nullptr;
+  // Optional, per cut subtree (FDbscan's main phase): the root that every core point
+  // under it had when the summary was taken, kCutNoCore when it holds none, or
+  // kCutMixed. A subtree already in a packet's set adds no union and is not walked.
+  const int* cut_sum = nullptr;
 };
 
-constexpr int kCutMax = 4096;
-constexpr int kCutDiv = 256;   // the cut holds about kCutDiv to 2 kCutDiv subtrees
-constexpr int kCutUnroll = 4;         // cut entries a lane loads at once
-__host__ __device__ inline int cut_span(int m) {
-  return (m + kCutDiv - 1) / kCutDiv > 64 ? (m + kCutDiv - 1) / kCutDiv : 64;
+constexpr int kCutMax = 8192;
+constexpr int kCutDiv = 256;      // the cut holds about kCutDiv to 2 kCutDiv subtrees
+constexpr int kCutDivFine = 4096;  // FDbscan: subtrees of ~m/4096 primitives, smaller than a clump
+constexpr int kCutUnroll = 4;     // cut entries a lane loads at once
+constexpr int kCutMixed = -1, kCutNoCore = -2;
+__host__ __device__ inline int cut_span(int m, int div = kCutDiv) {
+  return (m + div - 1) / div > 64 ? (m + div - 1) / div : 64;
 }
 
 // ---- launch helpers (stream-ordered, asynchronous) --------------------------
@@ -182,7 +188,7 @@ int64_t planned_status_words(int64_t n);
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts,
                 const float4* prim_lo, const float4* prim_hi, float4* node_a, float4* node_b, int* rope,
                 int* leaf_rope, int* ends, int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s,
-                float4* cut = nullptr, int* cut_n = nullptr, bool ends_ready = false);
+                float4* cut = nullptr, int* cut_n = nullptr, bool ends_ready = false, int cut_div = kCutDiv);
 
 // k_dense.hip
 // sorted_keys are 64-bit words when key64 (or, with d_key64 set, when *d_key64 on
@@ -258,6 +264,11 @@ struct TravArgs {
   int block;
 };
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s);
+// FDbscan, one cloud, before the packet main phase: core pairs among curve
+// neighbours joined early, then a summary per cut subtree (kCutMax words at sum;
+// a.t.cut must be set) for a.t.cut_sum.
+void launch_fdb_local(const TravArgs& a, int dim, bool all_core, hipStream_t s);
+void launch_cut_summary(const TravArgs& a, bool all_core, int* sum, hipStream_t s);
 // Isolated points before the DenseBox core pass (one cloud, 32-bit grid keys): an
 // occupancy map of the grid cells (words: plan->lone_words 64-bit words, one per
 // brick of 64 cells, written only for occupied bricks; table: one bit per brick,

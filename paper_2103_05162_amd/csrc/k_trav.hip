@@ -214,13 +214,16 @@ __device__ __forceinline__ bool traverse_box(const TreeView& t, int m, const Sco
 // each lane's own primitive (-1 for none), so the visitor loads all of them at
 // once. It visits the same buckets and leaves as traverse_box (in another order:
 // callers only union, which does not depend on it). Children that do not fit on
-// the stack have their subtrees walked with traverse_box instead.
+// the stack have their subtrees walked with traverse_box instead. SKIP: cut
+// subtrees that t.cut_sum marks as holding no core point, or as already in the
+// set of root skip_root (labels skip_labels), are not walked.
 constexpr int kWideStack = 512;  // entries per wavefront
 
-template <int D, typename F>
+template <int D, bool SKIP = false, typename F>
 __device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m, const Scope& sc, const float* lo,
                                                         const float* hi, int mask, int leaf_size, uint32_t* info,
-                                                        uint32_t* stack, F&& visit_lanes) {
+                                                        uint32_t* stack, F&& visit_lanes,
+                                                        const int* skip_labels = nullptr, int skip_root = -1) {
   if (m <= 0 || mask >= sc.end) return;
   const int lane = lane_id();
   // a range [s, e] of one lane (wave-uniform arguments), 64 primitives per call
@@ -236,16 +239,23 @@ __device__ __forceinline__ void traverse_box_wide_lanes(const TreeView& t, int m
   if (nc > 0 && nc <= kCutMax) {
     for (int b = 0; b < nc && top >= 0; b += 64 * kCutUnroll) {
       float4 ca[kCutUnroll], cb[kCutUnroll];
+      int cs[kCutUnroll];
 #pragma unroll
       for (int u = 0; u < kCutUnroll; ++u) {  // the loads of kCutUnroll chunks in flight together
         const int c = min(b + u * 64 + lane, nc - 1);
         ca[u] = t.cut[2 * c];
         cb[u] = t.cut[2 * c + 1];
+        cs[u] = SKIP && t.cut_sum ? t.cut_sum[c] : kCutMixed;
       }
 #pragma unroll
       for (int u = 0; u < kCutUnroll; ++u) {
-        const bool hit = b + u * 64 + lane < nc && __float_as_int(cb[u].w) > mask &&
-                         boxbox_dist2<D>(lo, hi, ca[u].x, ca[u].y, ca[u].z, cb[u].x, cb[u].y, cb[u].z) <= sc.eps2;
+        bool hit = b + u * 64 + lane < nc && __float_as_int(cb[u].w) > mask &&
+                   boxbox_dist2<D>(lo, hi, ca[u].x, ca[u].y, ca[u].z, cb[u].x, cb[u].y, cb[u].z) <= sc.eps2;
+        // a subtree without core points, or one whose core points were all in the
+        // walker's set (skip_root) when summarised, adds no union: sets only merge
+        if (SKIP && hit && cs[u] != kCutMixed)
+          hit = !(cs[u] == kCutNoCore ||
+                  (skip_root >= 0 && (cs[u] == skip_root || skip_labels[cs[u]] == skip_root)));
         const uint64_t hm = ballot(hit);
         if (top < 0 || top + __popcll(hm) > kWideStack) {
           top = -1;  // more than the stack holds: start from the root instead
@@ -584,6 +594,81 @@ __global__ void k_main_fdb_first(TravArgs a) {
   });
 }
 
+// Before FDbscan's packet main phase: each core point joins the core points among
+// the next kLocalWindow along the curve that are within eps (pairs of the main
+// phase, taken early: in a dense clump consecutive points are close, so a clump
+// ends up in one or a few sets), so that the cut summaries below find whole
+// subtrees already in one set.
+constexpr int kLocalWindow = 8;
+
+template <int D, bool ALL_CORE>
+__global__ __launch_bounds__(256) void k_fdb_local(TravArgs a) {
+  const int64_t i64 = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i64 >= a.n) return;
+  const int i = static_cast<int>(i64);
+  if (!(ALL_CORE || a.core[i])) return;
+  const Query q = load_point<D>(a.xs, a.n, i);
+  int root = i;
+  for (int u = 1; u <= kLocalWindow; ++u) {
+    const int j = i + u;
+    if (j >= a.n) break;
+    if (!(ALL_CORE || a.core[j]) || !near<D>(a.xs, a.n, j, q, a.eps2)) continue;
+    if (!known_same_set(a.labels, j, root)) root = uf_union(a.labels, root, j, a.info);
+  }
+}
+
+// Summary of cut subtree c (a workgroup each): the root of every core point under
+// it (kCutNoCore: none; kCutMixed: more than one, or a chain too long to follow).
+template <bool ALL_CORE>
+__global__ __launch_bounds__(256) void k_cut_summary(TreeView t, int m, const int* __restrict__ labels,
+                                                     const uint8_t* __restrict__ core, int* __restrict__ sum) {
+  __shared__ int s_lo[4], s_hi[4];
+  const int nc = *t.cut_n;
+  const int c = blockIdx.x;
+  if (nc > kCutMax || c >= nc) return;  // whole workgroup
+  const float4 ca = t.cut[2 * c], cb = t.cut[2 * c + 1];
+  const uint32_t ref = __float_as_uint(ca.w);
+  const int last = __float_as_int(cb.w);
+  int first = last;
+  if (!(ref & kLeaf) && ref < static_cast<uint32_t>(m - 1)) {
+    const int k = static_cast<int>(ref);
+    const int o = __float_as_int(t.node_a[kNodeStride * size_t(k)].w);
+    first = o < k ? o : k;
+  }
+  int lo = 0x7fffffff, hi = -1;  // smallest and largest root among the core points
+  if (first < 0 || last >= m || first > last) lo = -3;  // not a range: never skipped
+  for (int i = first + static_cast<int>(threadIdx.x); lo != -3 && i <= last; i += 256) {
+    if (!(ALL_CORE || core[i])) continue;
+    int x = i, p = labels[x];
+    for (int h = 0; p != x && h < 64; ++h) {
+      x = p;
+      p = labels[x];
+    }
+    if (p != x) {
+      lo = -3;  // mixed
+      break;
+    }
+    lo = x < lo ? x : lo;
+    hi = x > hi ? x : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off));
+    hi = max(hi, __shfl_xor(hi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[threadIdx.x >> 6] = lo;
+    s_hi[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = min(lo, s_lo[w]);
+      hi = max(hi, s_hi[w]);
+    }
+    sum[c] = lo == -3 ? kCutMixed : (hi < 0 ? kCutNoCore : (lo == hi ? lo : kCutMixed));
+  }
+}
+
 // Canonical (and minPts <= 2) main phase, Q queries per lane: a wavefront owns
 // 64*Q consecutive queries. When they lie in a small box (and, in a batch, in
 // one cloud) they walk as one packet: the lanes load a bucket of candidates
@@ -646,6 +731,38 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   }
   const bool packet = !ballot(other_cloud) && ext * ext <= a.packet_ext_eps2 * ps.eps2;
 
+  if (!packet && a.t.cut_sum && !B) {
+    // spread out, with cut summaries: each query walks as a packet of one (the
+    // lane-wide walk, passing over cut subtrees already in its set). Per-lane
+    // rope walks of a wavefront of such queries at a clump's edge took 13-15 ms,
+    // each lane visiting the clump's candidates one by one.
+    uint32_t* qstack = s_stack + (threadIdx.x >> 6) * kWideStack;
+#pragma unroll
+    for (int s = 0; s < Q; ++s)
+      for (uint64_t qm = mm[s]; qm; qm &= qm - 1) {
+        const int kl = __ffsll(static_cast<unsigned long long>(qm)) - 1;
+        const int i = __builtin_amdgcn_readlane(idx[s], kl);
+        const float qx = readlane_f(q[s].x, kl), qy = readlane_f(q[s].y, kl), qz = readlane_f(q[s].z, kl);
+        const float qb[3] = {qx, qy, qz};
+        const Scope sc = scope_of<B>(a, m, i);
+        int r = 0;
+        if (lane == 0) r = uf_find(labels, i, a.info);
+        r = __shfl(r, 0);
+        traverse_box_wide_lanes<D, true>(a.t, m, sc, qb, qb, i, a.packet_leaf, a.info, qstack, [&](int jl) {
+          bool hit = false;
+          if (jl > i && (ALL_CORE || a.core[jl]))
+            hit = dist2v<D>(a.xs[jl], a.xs[a.n + jl], D == 3 ? a.xs[2 * a.n + jl] : 0.0f, qx, qy, qz) <= sc.eps2;
+          if (ballot(hit)) {
+            if (hit && !known_same_set(labels, jl, r)) uf_union(labels, r, jl, a.info);
+            int nr = 0;
+            if (lane == 0) nr = uf_find(labels, r, a.info);
+            r = __shfl(nr, 0);
+          }
+          return false;
+        }, labels, r);
+      }
+    return;
+  }
   if (!packet) {  // spread out: every query walks on its own
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
@@ -696,7 +813,7 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   uint32_t* stack = s_stack + (threadIdx.x >> 6) * kWideStack;
   // the buckets a step reaches are laid end to end over the lanes (one candidate
   // per lane), so a step costs a round per 64 candidates, not one per bucket
-  traverse_box_wide_lanes<D>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, stack, [&](int jl) {
+  traverse_box_wide_lanes<D, true>(a.t, m, ps, lo, hi, i0, a.packet_leaf, a.info, stack, [&](int jl) {
     float cx = 0.0f, cy = 0.0f, cz = 0.0f;
     int cc = 0, cl = 0;
     if (jl >= 0) {
@@ -744,7 +861,7 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
           root[s] = uf_union(labels, root[s], j, a.info);
     }
     return false;
-  });
+  }, labels, common ? r : -1);
 }
 
 // Border pass from the core pass's neighbour records (no walk): the smallest
@@ -1999,6 +2116,25 @@ void launch_lone_filter(const TravArgs& a, int dim, const uint64_t* prim_key, co
   if (a.n <= 0) return;
   if (dim == 3) lone_t<3>(a, prim_key, plan, table, words, bounds, list, list_n, s);
   else lone_t<2>(a, prim_key, plan, table, words, bounds, list, list_n, s);
+}
+
+void launch_fdb_local(const TravArgs& a, int dim, bool all_core, hipStream_t s) {
+  if (a.n <= 1) return;
+  const dim3 g(static_cast<unsigned>(ceil_div(a.n, 256))), b(256);
+  if (dim == 3) {
+    if (all_core) hipLaunchKernelGGL((k_fdb_local<3, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fdb_local<3, false>), g, b, 0, s, a);
+  } else {
+    if (all_core) hipLaunchKernelGGL((k_fdb_local<2, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fdb_local<2, false>), g, b, 0, s, a);
+  }
+}
+
+void launch_cut_summary(const TravArgs& a, bool all_core, int* sum, hipStream_t s) {
+  if (a.n <= 1 || !a.t.cut || !a.t.cut_n) return;
+  const int m = static_cast<int>(a.n);
+  if (all_core) hipLaunchKernelGGL(k_cut_summary<true>, dim3(kCutMax), dim3(256), 0, s, a.t, m, a.labels, a.core, sum);
+  else hipLaunchKernelGGL(k_cut_summary<false>, dim3(kCutMax), dim3(256), 0, s, a.t, m, a.labels, a.core, sum);
 }
 
 void launch_core(const TravArgs& a, int dim, bool densebox, hipStream_t s) {

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ 
                                                      int64_t n, LeafSrc ls, int* __restrict__ other,
                                                      int* __restrict__ gamma, int* __restrict__ ends, float4* node_a,
                                                      float4* node_b, uint32_t* __restrict__ info,
-                                                     float4* __restrict__ cut, int* __restrict__ cut_n) {
+                                                     float4* __restrict__ cut, int* __restrict__ cut_n, int cut_div) {
   constexpr int E = kRefitBlock + 1;  // edges L0-1 .. L0+255
   __shared__ int s_far[kRefitBlock];
   __shared__ float s_side[2][6][kRefitBlock];  // [child side][lo.xyz, hi.xyz][split - L0]
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ 
     if (cut) {
       // a child of at most span primitives under a larger parent is a cut node
       const int a0 = left ? i : far, a1 = sp, b0 = sp + 1, b1 = left ? far : j;
-      const int span = cut_span(m);
+      const int span = cut_span(m, cut_div);
       if (b1 - a0 + 1 > span) {
         if (a1 - a0 + 1 <= span)
           cut_add(cut, cut_n, a0 == a1 ? (kLeaf | static_cast<uint32_t>(a1)) : static_cast<uint32_t>(a1), a1,
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kRefitBlock) void k_build_up(const K* __restrict__ 
 template <typename K>
 void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs, int64_t n_pts,
              const LeafSrc& ls, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends, int* other,
-             int* gamma, uint32_t* info, hipStream_t s, float4* cut, int* cut_n, bool ends_ready) {
+             int* gamma, uint32_t* info, hipStream_t s, float4* cut, int* cut_n, bool ends_ready, int cut_div) {
   if (m_cap <= 0) return;
   int g = static_cast<int>(ceil_div(m_cap, kBlock));
   if (m_cap >= 2) {
@@ -330,16 +330,16 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
     const dim3 rg(static_cast<unsigned>(ceil_div(m_cap, kRefitBlock))), rb(kRefitBlock);
     if (dim == 3 && buf)
       hipLaunchKernelGGL((k_build_up<K, 3, true>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
-                         node_a, node_b, info, cut, cut_n);
+                         node_a, node_b, info, cut, cut_n, cut_div);
     else if (dim == 3)
       hipLaunchKernelGGL((k_build_up<K, 3, false>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
-                         node_a, node_b, info, cut, cut_n);
+                         node_a, node_b, info, cut, cut_n, cut_div);
     else if (buf)
       hipLaunchKernelGGL((k_build_up<K, 2, true>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
-                         node_a, node_b, info, cut, cut_n);
+                         node_a, node_b, info, cut, cut_n, cut_div);
     else
       hipLaunchKernelGGL((k_build_up<K, 2, false>), rg, rb, 0, s, keys, m_cap, d_m, xs, n_pts, ls, other, gamma, ends,
-                         node_a, node_b, info, cut, cut_n);
+                         node_a, node_b, info, cut, cut_n, cut_div);
   }
   hipLaunchKernelGGL(k_ropes, dim3(g), dim3(kBlock), 0, s, other, m_cap, d_m, rope, leaf_rope);
 }
@@ -349,14 +349,14 @@ void build_t(const K* keys, int m_cap, const int* d_m, int dim, const float* xs,
 void build_lbvh(const void* keys, bool key64, int m, int dim, const float* xs, int64_t n_pts, const float4* prim_lo,
                 const float4* prim_hi, float4* node_a, float4* node_b, int* rope, int* leaf_rope, int* ends,
                 int* other, int* gamma, const int* d_m, uint32_t* info, hipStream_t s, float4* cut, int* cut_n,
-                bool ends_ready) {
+                bool ends_ready, int cut_div) {
   const LeafSrc ls{prim_lo, prim_hi};
   if (key64)
     build_t(static_cast<const uint64_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
-            other, gamma, info, s, cut, cut_n, ends_ready);
+            other, gamma, info, s, cut, cut_n, ends_ready, cut_div);
   else
     build_t(static_cast<const uint32_t*>(keys), m, d_m, dim, xs, n_pts, ls, node_a, node_b, rope, leaf_rope, ends,
-            other, gamma, info, s, cut, cut_n, ends_ready);
+            other, gamma, info, s, cut, cut_n, ends_ready, cut_div);
 }
 
 }  // namespace fdb
