@@ -731,11 +731,14 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   }
   const bool packet = !ballot(other_cloud) && ext * ext <= a.packet_ext_eps2 * ps.eps2;
 
-  if (!packet && a.t.cut_sum && !B) {
-    // spread out, with cut summaries: each query walks as a packet of one (the
+  if (!ALL_CORE && !packet && a.t.cut_sum && !B) {
+    // spread out, with cut summaries and minPts > 2 (so every query is a core
+    // point, in a dense neighbourhood): each query walks as a packet of one (the
     // lane-wide walk, passing over cut subtrees already in its set). Per-lane
     // rope walks of a wavefront of such queries at a clump's edge took 13-15 ms,
-    // each lane visiting the clump's candidates one by one.
+    // each lane visiting the clump's candidates one by one. With minPts <= 2
+    // every point is a query and sparse ones walk cheaply on their own lanes
+    // (a 2M-point friends-of-friends set: 5.0 ms that way, 11.1 ms as packets of one).
     uint32_t* qstack = s_stack + (threadIdx.x >> 6) * kWideStack;
 #pragma unroll
     for (int s = 0; s < Q; ++s)
