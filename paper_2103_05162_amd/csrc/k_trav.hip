@@ -1523,10 +1523,11 @@ __global__ void k_core_dbx(TravArgs a) {
 #pragma unroll
     for (int t = 0; t < kCoreQ; ++t) any |= active[t];
     if (!ballot(any)) break;
-    int pend[kCoreQ];
+    int pend[kCoreQ], pcnt[kCoreQ];  // a dense cell to scan: its first point and its size
 #pragma unroll
     for (int t = 0; t < kCoreQ; ++t) {
       pend[t] = -1;
+      pcnt[t] = 0;
       if (active[t]) {
         const int r = walk_step<D, false>(w[t], a.t, m, q[t], sc[t].eps2, 0, a.info);
         if (r >= 0) {
@@ -1543,8 +1544,9 @@ __global__ void k_core_dbx(TravArgs a) {
               if (cell_within<D>(lr, hr, q[t], sc[t].eps2)) {  // counted whole, no scan
                 cnt[t] += __float_as_int(hr.w);
                 rec_add(rec[t], s);  // s == cell_ref(first point)
-              } else {
-                pend[t] = r;
+              } else {  // both from the records already loaded: the scan starts with the points
+                pend[t] = ref_point(s);
+                pcnt[t] = __float_as_int(hr.w);
               }
             }
           }
@@ -1555,10 +1557,9 @@ __global__ void k_core_dbx(TravArgs a) {
     for (int t = 0; t < kCoreQ; ++t) {
       for (uint64_t pm = ballot(pend[t] >= 0); pm; pm &= pm - 1) {
         const int L = __ffsll(static_cast<unsigned long long>(pm)) - 1;
-        const int r = __shfl(pend[t], L);
+        const int s = __shfl(pend[t], L);
         const int want = __shfl(sc[t].min_pts - cnt[t], L);
-        const int s = a.prim_start[r];
-        const int found = cell_count_near<D>(a.xs, a.n, s, -a.prim_cnt[r], __shfl(q[t].x, L), __shfl(q[t].y, L),
+        const int found = cell_count_near<D>(a.xs, a.n, s, __shfl(pcnt[t], L), __shfl(q[t].x, L), __shfl(q[t].y, L),
                                              __shfl(q[t].z, L), readlane_f(sc[t].eps2, L), want);
         if (lane == L && found > 0) {
           cnt[t] += found;
@@ -1699,6 +1700,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
           }
           // a dense cell: one of its points within eps of a query suffices
           const float ux = readlane_f(hr.x, k), uy = readlane_f(hr.y, k), uz = readlane_f(hr.z, k);
+          const int nk = __builtin_amdgcn_readlane(__float_as_int(hr.w), k);  // the cell's size
           const bool nb = mine && rk > p && (common || ak != root) &&
                           box_dist2<D>(q.x, q.y, q.z, px, py, pz, ux, uy, uz) <= eps2 &&
                           (common || !known_same_set(labels, j, root));
@@ -1720,7 +1722,7 @@ __global__ void k_main_dbx_points(TravArgs a) {
           }
           for (uint64_t lm = ballot(nb && !full); lm; lm &= lm - 1) {
             const int L = __ffsll(static_cast<unsigned long long>(lm)) - 1;
-            const bool reach = cell_reaches_point<D>(a.xs, a.n, j, -a.prim_cnt[rk], readlane_f(q.x, L),
+            const bool reach = cell_reaches_point<D>(a.xs, a.n, j, nk, readlane_f(q.x, L),
                                                      readlane_f(q.y, L), readlane_f(q.z, L), eps2);
             if (common) {
               if (!reach) continue;
