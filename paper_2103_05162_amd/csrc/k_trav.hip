@@ -785,9 +785,25 @@ __global__ __launch_bounds__(256) void k_main_fdb_q(TravArgs a) {
   }
   const float eps2 = ps.eps2;
 
-  // Phase A: pairs inside the packet.
+  // Phase A: pairs inside the packet. Skipped when every query is already in one
+  // set (the curve-neighbour unions usually see to that): its pairs would then
+  // only join a set to itself.
+  bool split = false;
 #pragma unroll
-  for (int ks = 0; ks < Q; ++ks) {
+  for (int s = 0; s < Q; ++s)
+    if (mine[s]) root[s] = uf_find(labels, root[s], a.info);
+  {
+    int r0 = 0;
+#pragma unroll
+    for (int s = 0; s < Q; ++s)
+      if (s == first_slot) r0 = root[s];
+    r0 = __shfl(r0, fl);
+#pragma unroll
+    for (int s = 0; s < Q; ++s) split |= mine[s] && root[s] != r0;
+  }
+  const bool phase_a = ballot(split) != 0;
+#pragma unroll
+  for (int ks = 0; ks < Q && phase_a; ++ks) {
     for (int kl = 0; kl < 64; ++kl) {
       if (!((mm[ks] >> kl) & 1)) continue;
       const int jk = static_cast<int>(base) + ks * 64 + kl;
